@@ -1,0 +1,28 @@
+"""FP64 CPU oracle for QTT contraction, orthogonalisation, rounding and inner products.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check of the package
+entry file and the CPU-baseline leg of the benchmark may import this package.
+The product path (the HIP library and its Python binding) never calls it and
+shares no code with it.
+
+Everything here is plain NumPy in float64 with LAPACK QR/SVD through
+numpy.linalg, written from the paper's definitions:
+
+  * contraction: Sec. 3.1, eqs. quant_sum and einsum -- local core
+    contractions with the bond indices flattened as xi = (mu, nu), mu major;
+  * exact addition: Sec. 3.1, the block-diagonal core structure;
+  * orthogonalisation: the QR-based normalisation step of Sec. 3.2 (and the
+    canonical form of Sec. 1), swept left to right;
+  * rounding: a left-to-right QR sweep followed by a right-to-left truncated
+    SVD sweep -- the TT-rounding algorithm of Oseledets (2011), which the
+    paper cites for tensor trains; the paper's "decomposition(max_rank,
+    cutoff)" options are read as a relative Frobenius tolerance and a rank cap;
+  * inner product: the <C|C>-type contractions of Sec. 3.3.
+
+Pins (tests/test_oracle_*.py) tie each function to something other than
+itself: dense reconstruction + numpy.einsum on tiny grids, the closed forms of
+Sec. 4 (exp rank 1, cos/sin rank 2, degree-p polynomial rank p+1, the shift
+matrices of Sec. 4.2), Laplacian eigenvectors, and invariants.
+"""
+from .tt import *  # noqa: F401,F403
+from .tt import __all__  # noqa: F401

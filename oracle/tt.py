@@ -1,0 +1,482 @@
+"""FP64 oracle implementation (test infrastructure only; see package docstring).
+
+Core layouts: MPS core [r_l, d, r_r], MPO core [r_l, d_out, d_in, r_r], all
+float64 row-major.  Core 0 holds the most significant digit (Sec. 2, eq.
+quantization).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "contract",
+    "tt_add",
+    "tt_scale",
+    "orthogonalize",
+    "round_tt",
+    "RoundInfo",
+    "truncation_rank",
+    "inner",
+    "norm",
+    "rel_error",
+    "diff_norm",
+    "to_dense",
+    "mpo_to_dense",
+    "ranks_of",
+    "bond_singular_values",
+    "shift_mpo_paper",
+    "dense_shift",
+    "dense_laplacian",
+    "interleaved_index",
+    "env_left",
+    "env_right",
+    "inner_grad",
+    "contract_grad",
+    "loss_axb",
+    "grad_axb",
+    "grad_axb_sandwich",
+]
+
+
+# --------------------------------------------------------------------------
+# exact operations (Sec. 3.1)
+# --------------------------------------------------------------------------
+def contract(spec: str, A: Sequence[np.ndarray], B: Sequence[np.ndarray]):
+    """Core-by-core Einstein summation (eq. einsum).
+
+    'i,i->i':  C_k[(mu,nu), i, (mu',nu')] = A_k[mu,i,mu'] B_k[nu,i,nu']
+    'ij,j->i': C_k[(mu,nu), i, (mu',nu')] = sum_j A_k[mu,i,j,mu'] B_k[nu,j,nu']
+    The flattened bond is xi = mu * r_B + nu (mu major), as in the flatten
+    xi_q = overline{mu_q nu_q} of the paper.
+    """
+    if len(A) != len(B):
+        raise ValueError("core count mismatch")
+    out = []
+    for a, b in zip(A, B):
+        if spec == "i,i->i":
+            c = np.einsum("aib,cid->acibd", a, b)
+            ra, d, rb = a.shape
+            rc, _, rd = b.shape
+            out.append(c.reshape(ra * rc, d, rb * rd))
+        elif spec == "ij,j->i":
+            c = np.einsum("aijb,cjd->acibd", a, b)
+            ra, di, dj, rb = a.shape
+            rc, _, rd = b.shape
+            out.append(c.reshape(ra * rc, di, rb * rd))
+        else:
+            raise ValueError(f"unsupported spec {spec!r}")
+    return out
+
+
+def tt_add(X, Y, alpha: float = 1.0, beta: float = 1.0):
+    """alpha X + beta Y as an exact TT with block cores (Sec. 3.1, addition).
+
+    First core [X_1 Y_1] (row), middle cores diag(X_k, Y_k), last core
+    [X_n; Y_n] (column); the scalars are folded into the first core.
+    """
+    n = len(X)
+    if n != len(Y):
+        raise ValueError("core count mismatch")
+    if n == 1:
+        return [alpha * X[0] + beta * Y[0]]
+    out = []
+    for k in range(n):
+        x, y = X[k], Y[k]
+        rx0, d, rx1 = x.shape
+        ry0, _, ry1 = y.shape
+        if k == 0:
+            c = np.concatenate([alpha * x, beta * y], axis=2)
+        elif k == n - 1:
+            c = np.concatenate([x, y], axis=0)
+        else:
+            c = np.zeros((rx0 + ry0, d, rx1 + ry1))
+            c[:rx0, :, :rx1] = x
+            c[rx0:, :, rx1:] = y
+        out.append(c)
+    return out
+
+
+def tt_scale(X, s: float):
+    out = [c.copy() for c in X]
+    out[0] = out[0] * s
+    return out
+
+
+def ranks_of(X) -> List[int]:
+    return [X[0].shape[0]] + [c.shape[-1] for c in X]
+
+
+# --------------------------------------------------------------------------
+# orthogonalisation (QR sweep) -- normalisation step of Sec. 3.2
+# --------------------------------------------------------------------------
+def orthogonalize(X):
+    """Left-to-right QR sweep.  Returns (cores, norm).
+
+    For k = 1..n-1: the (r_{k-1} d) x r_k unfolding of core k is factored
+    Q R (reduced QR, signs fixed so that diag(R) >= 0); Q becomes core k and R
+    is multiplied into core k+1.  A wide unfolding gives the new rank
+    r_{k-1} d.  The norm of the tensor is the Frobenius norm of the last core.
+    """
+    cores = [np.array(c, dtype=np.float64, copy=True) for c in X]
+    n = len(cores)
+    for k in range(n - 1):
+        c = cores[k]
+        r0 = c.shape[0]
+        mid = c.shape[1:-1]
+        r1 = c.shape[-1]
+        M = c.reshape(-1, r1)
+        Q, R = np.linalg.qr(M, mode="reduced")
+        s = np.sign(np.diag(R))
+        s[s == 0] = 1.0
+        Q = Q * s[None, :]
+        R = R * s[:, None]
+        q = Q.shape[1]
+        cores[k] = Q.reshape((r0,) + mid + (q,))
+        nxt = cores[k + 1]
+        cores[k + 1] = np.tensordot(R, nxt, axes=([1], [0]))
+    nrm = float(np.linalg.norm(cores[-1].ravel()))
+    return cores, nrm
+
+
+# --------------------------------------------------------------------------
+# rounding (QR sweep + truncated SVD sweep)
+# --------------------------------------------------------------------------
+@dataclass
+class RoundInfo:
+    norm: float = 0.0
+    delta: float = 0.0
+    err_bound: float = 0.0
+    ranks: List[int] = field(default_factory=list)
+    tails: List[float] = field(default_factory=list)       # per bond 1..n-1
+    margin_lo: List[float] = field(default_factory=list)   # tail(r-1)/delta
+    margin_hi: List[float] = field(default_factory=list)   # tail(r)/delta
+    maxrank_hit: List[bool] = field(default_factory=list)
+    sigmas: List[np.ndarray] = field(default_factory=list)  # per bond 1..n-1
+
+
+def truncation_rank(sig: np.ndarray, delta: float, max_rank: int):
+    """Smallest r >= 1 with sqrt(sum_{i>r} sigma_i^2) <= delta, capped at max_rank.
+
+    Returns (r, tail(r), tail(r-1), capped).  The tail sums are accumulated
+    from the smallest singular value upwards.
+    """
+    s = np.asarray(sig, dtype=np.float64)
+    m = s.size
+    tail2 = np.zeros(m + 1)  # tail2[r] = sum_{i >= r} s_i^2 (0-based i)
+    acc = 0.0
+    for i in range(m - 1, -1, -1):
+        acc += s[i] * s[i]
+        tail2[i] = acc
+    r = m
+    for cand in range(1, m + 1):
+        if math.sqrt(tail2[cand]) <= delta:
+            r = cand
+            break
+    capped = False
+    if max_rank and max_rank > 0 and r > max_rank:
+        r = max_rank
+        capped = True
+    r = max(1, min(r, max(m, 1)))
+    t_r = math.sqrt(tail2[r]) if r <= m else 0.0
+    t_rm1 = math.sqrt(tail2[r - 1]) if r - 1 <= m else 0.0
+    return r, t_r, t_rm1, capped
+
+
+def round_tt(X, rel_tol: float, max_rank: int = 0, return_info: bool = False):
+    """TT rounding: QR sweep left to right, truncated SVD sweep right to left.
+
+    delta = rel_tol * ||X|| / sqrt(n-1).  At bond k the kept rank is the
+    smallest r >= 1 whose discarded singular values have 2-norm <= delta,
+    capped at max_rank (max_rank <= 0: no cap).  A zero tensor rounds to
+    rank 1.
+    """
+    n = len(X)
+    cores, nrm = orthogonalize(X)
+    info = RoundInfo(norm=nrm)
+    if n == 1:
+        info.ranks = ranks_of(cores)
+        return (cores, info) if return_info else cores
+    delta = rel_tol * nrm / math.sqrt(n - 1)
+    info.delta = delta
+    tails = [0.0] * (n - 1)
+    mlo = [0.0] * (n - 1)
+    mhi = [0.0] * (n - 1)
+    hit = [False] * (n - 1)
+    sigs = [None] * (n - 1)
+    for k in range(n - 1, 0, -1):
+        c = cores[k]
+        r0 = c.shape[0]
+        mid = c.shape[1:-1]
+        r1 = c.shape[-1]
+        B = c.reshape(r0, -1)
+        U, S, Vt = np.linalg.svd(B, full_matrices=False)
+        r, t_r, t_rm1, capped = truncation_rank(S, delta, max_rank)
+        if nrm == 0.0:
+            r, t_r, t_rm1 = 1, 0.0, 0.0
+        sigs[k - 1] = S.copy()
+        tails[k - 1] = t_r
+        hit[k - 1] = capped
+        mlo[k - 1] = (t_rm1 / delta) if delta > 0 else math.inf
+        mhi[k - 1] = (t_r / delta) if delta > 0 else 0.0
+        cores[k] = Vt[:r].reshape((r,) + mid + (r1,))
+        US = U[:, :r] * S[None, :r]
+        prev = cores[k - 1]
+        cores[k - 1] = np.tensordot(prev, US, axes=([prev.ndim - 1], [0]))
+    info.ranks = ranks_of(cores)
+    info.tails = tails
+    info.margin_lo = mlo
+    info.margin_hi = mhi
+    info.maxrank_hit = hit
+    info.sigmas = sigs
+    info.err_bound = math.sqrt(sum(t * t for t in tails))
+    return (cores, info) if return_info else cores
+
+
+def bond_singular_values(X):
+    """Singular values of every bond unfolding (QR sweep, then untruncated SVD sweep)."""
+    _, info = round_tt(X, 0.0, 0, return_info=True)
+    return info.sigmas
+
+
+# --------------------------------------------------------------------------
+# inner products and norms (Sec. 3.3, <C|C>-type contractions)
+# --------------------------------------------------------------------------
+def _mat(core):
+    """[r_l, phys..., r_r] -> (r_l, P, r_r) with the physical legs flattened."""
+    return core.reshape(core.shape[0], -1, core.shape[-1])
+
+
+def inner(A, B) -> float:
+    """<A, B> = E_n with E_0 = [[1]], E_k = sum_i A_k(i)^T E_{k-1} B_k(i)."""
+    E = np.ones((1, 1))
+    for a, b in zip(A, B):
+        a3, b3 = _mat(a), _mat(b)
+        E = np.einsum("ab,aic,bid->cd", E, a3, b3)
+    return float(E[0, 0])
+
+
+def norm(X) -> float:
+    return orthogonalize(X)[1]
+
+
+def diff_norm(X, Y) -> float:
+    """||X - Y||_F via the exact difference TT and a QR sweep (no cancellation)."""
+    D = tt_add(X, Y, 1.0, -1.0)
+    return orthogonalize(D)[1]
+
+
+def rel_error(X, Y) -> float:
+    """||X - Y|| / ||Y|| (Frobenius), computed without Gram cancellation."""
+    ny = norm(Y)
+    dn = diff_norm(X, Y)
+    return dn / ny if ny > 0 else dn
+
+
+# --------------------------------------------------------------------------
+# dense helpers (tiny grids only)
+# --------------------------------------------------------------------------
+def to_dense(X) -> np.ndarray:
+    """Full tensor as a flat vector, core 0 = most significant digit."""
+    T = np.ones((1, 1))
+    for c in X:
+        c3 = _mat(c)
+        T = np.einsum("pa,aib->pib", T, c3).reshape(-1, c3.shape[-1])
+    return T[:, 0]
+
+
+def mpo_to_dense(W) -> np.ndarray:
+    """Dense matrix A(i, j) of an MPO with cores [r, d_out, d_in, r']."""
+    T = np.ones((1, 1, 1))
+    for c in W:
+        T = np.einsum("pqa,aijb->piqjb", T, c)
+        s = T.shape
+        T = T.reshape(s[0] * s[1], s[2] * s[3], s[4])
+    return T[:, :, 0]
+
+
+def interleaved_index(m: int, D: int) -> np.ndarray:
+    """Map flat TT index (interleaved digits) -> row-major grid index (x_0, .., x_{D-1}).
+
+    Core k = q*D + a holds bit q (MSB first) of axis a.
+    """
+    n = m * D
+    flat = np.arange(2 ** n)
+    coords = np.zeros((D, flat.size), dtype=np.int64)
+    for k in range(n):
+        bit = (flat >> (n - 1 - k)) & 1
+        q, a = divmod(k, D)
+        coords[a] |= bit << (m - 1 - q)
+    grid = np.zeros(flat.size, dtype=np.int64)
+    for a in range(D):
+        grid = grid * (2 ** m) + coords[a]
+    return grid
+
+
+def dense_shift(N: int, d: int) -> np.ndarray:
+    """Q^N_d(i, j) = 1 iff i - j = d (Sec. 4.2); zero if d > N."""
+    Q = np.zeros((N, N))
+    for j in range(N):
+        i = j + d
+        if 0 <= i < N:
+            Q[i, j] = 1.0
+    return Q
+
+
+def dense_laplacian(m: int, D: int) -> np.ndarray:
+    """Kronecker sum of the 1D Dirichlet stencil 2I - S - S^T on (2^m)^D points."""
+    N = 2 ** m
+    S = dense_shift(N, 1)
+    L1 = 2.0 * np.eye(N) - S - S.T
+    out = np.zeros((N ** D, N ** D))
+    for a in range(D):
+        term = np.ones((1, 1))
+        for b in range(D):
+            term = np.kron(term, L1 if b == a else np.eye(N))
+        out += term
+    return out
+
+
+def shift_mpo_paper(n: int, dshift: int):
+    """TT of (Q^N_d; R^N_d) by the paper's recursion (eq. shif_dec), N = 2^n.
+
+    Each core is the 2x2 block [[Q^2_{d_q}, Q^2_{d_q+1}], [R^2_{d_q},
+    R^2_{d_q+1}]] of 2x2 shift matrices, the last core the column (Q^2_{d_n};
+    R^2_{d_n}); the digits d_q of d are taken MSB first.  Q is selected by the
+    row vector (1, 0) from the left.  Uses R^N_d = (Q^N_{N-d})^T and Q^N_d = 0
+    for d >= N.  Returns MPO cores for Q^N_d.
+    """
+    def Q2(dd):
+        return dense_shift(2, dd) if dd < 2 else np.zeros((2, 2))
+
+    def R2(dd):
+        return Q2(2 - dd).T if 0 <= 2 - dd else np.zeros((2, 2))
+
+    digits = [(dshift >> (n - 1 - q)) & 1 for q in range(n)]
+    cores = []
+    for q in range(n):
+        dq = digits[q]
+        if q < n - 1:
+            c = np.zeros((2, 2, 2, 2))
+            c[0, :, :, 0] = Q2(dq)
+            c[0, :, :, 1] = Q2(dq + 1)
+            c[1, :, :, 0] = R2(dq)
+            c[1, :, :, 1] = R2(dq + 1)
+        else:
+            c = np.zeros((2, 2, 2, 1))
+            c[0, :, :, 0] = Q2(dq)
+            c[1, :, :, 0] = R2(dq)
+        cores.append(c)
+    sel = np.array([1.0, 0.0])
+    cores[0] = np.einsum("a,aijb->ijb", sel, cores[0])[None]
+    return cores
+
+
+# --------------------------------------------------------------------------
+# gradients (variational derivative, Sec. 3.3)
+# --------------------------------------------------------------------------
+def env_left(A, B) -> List[np.ndarray]:
+    """E[k] = left environment before core k of <A,B>; E[0] = [[1]]."""
+    E = [np.ones((1, 1))]
+    for a, b in zip(A, B):
+        E.append(np.einsum("ab,aic,bid->cd", E[-1], _mat(a), _mat(b)))
+    return E
+
+
+def env_right(A, B) -> List[np.ndarray]:
+    """F[k] = right environment after core k-1 of <A,B>; F[n] = [[1]]."""
+    n = len(A)
+    F = [None] * (n + 1)
+    F[n] = np.ones((1, 1))
+    for k in range(n - 1, -1, -1):
+        F[k] = np.einsum("aic,bid,cd->ab", _mat(A[k]), _mat(B[k]), F[k + 1])
+    return F
+
+
+def inner_grad(A, B) -> List[np.ndarray]:
+    """d<A,B>/dA_k = E_{k-1} B_k(i) F_{k+1}^T for every core k."""
+    E, F = env_left(A, B), env_right(A, B)
+    out = []
+    for k in range(len(A)):
+        g = np.einsum("ab,bid,cd->aic", E[k], _mat(B[k]), F[k + 1])
+        out.append(g.reshape(A[k].shape))
+    return out
+
+
+def contract_grad(spec: str, W, X, dC):
+    """Local backward of contract(): (dW, dX) from dC, core by core."""
+    dW, dX = [], []
+    for w, x, dc in zip(W, X, dC):
+        if spec == "ij,j->i":
+            ra, di, dj, rb = w.shape
+            rc, _, rd = x.shape
+            g = dc.reshape(ra, rc, di, rb, rd)
+            dX.append(np.einsum("aijb,acibd->cjd", w, g))
+            dW.append(np.einsum("cjd,acibd->aijb", x, g))
+        elif spec == "i,i->i":
+            ra, d, rb = w.shape
+            rc, _, rd = x.shape
+            g = dc.reshape(ra, rc, d, rb, rd)
+            dX.append(np.einsum("aib,acibd->cid", w, g))
+            dW.append(np.einsum("cid,acibd->aib", x, g))
+        else:
+            raise ValueError(spec)
+    return dW, dX
+
+
+def loss_axb(W, x, b) -> float:
+    """L = ||W x - b||^2 via the exact difference TT (no cancellation)."""
+    y = contract("ij,j->i", W, x)
+    return diff_norm(y, b) ** 2
+
+
+def grad_axb(W, x, b) -> List[np.ndarray]:
+    """dL/dx_k for L = ||W x - b||^2 (route 1: through y = W x).
+
+    L = <y,y> - 2<y,b> + <b,b>, so dL/dy_k = 2 E^{yy} y_k F^{yy} -
+    2 E^{yb} b_k F^{yb} (environments of the two inner products); the local
+    contraction backward then maps dL/dy_k to dL/dx_k.
+    """
+    y = contract("ij,j->i", W, x)
+    gyy = inner_grad(y, y)      # one slot of <y,y>; both slots give 2 * gyy
+    gyb = inner_grad(y, b)
+    dy = [2.0 * g1 - 2.0 * g2 for g1, g2 in zip(gyy, gyb)]
+    _, dx = contract_grad("ij,j->i", W, x, dy)
+    return dx
+
+
+def grad_axb_sandwich(W, x, b) -> List[np.ndarray]:
+    """dL/dx_k (route 2): three-layer environments of <x|W^T W|x> and <b|W|x>.
+
+    L = <x, W^T W x> - 2 <b, W x> + <b, b>; no contracted TT is formed.
+    """
+    n = len(x)
+    # left environments of x^T W^T W x : tensors [r_x, r_w, r_w, r_x]
+    EL = [np.ones((1, 1, 1, 1))]
+    for k in range(n - 1):
+        EL.append(np.einsum("pabq,pjx,aijc,bikd,qky->xcdy",
+                            EL[-1], x[k], W[k], W[k], x[k]))
+    ER = [None] * (n + 1)
+    ER[n] = np.ones((1, 1, 1, 1))
+    for k in range(n - 1, 0, -1):
+        ER[k] = np.einsum("pjx,aijc,bikd,qky,xcdy->pabq",
+                          x[k], W[k], W[k], x[k], ER[k + 1])
+    # left/right environments of <b, W x>: [r_b, r_w, r_x]
+    GL = [np.ones((1, 1, 1))]
+    for k in range(n - 1):
+        GL.append(np.einsum("pab,piq,aijc,bjd->qcd", GL[-1], b[k], W[k], x[k]))
+    GR = [None] * (n + 1)
+    GR[n] = np.ones((1, 1, 1))
+    for k in range(n - 1, 0, -1):
+        GR[k] = np.einsum("piq,aijc,bjd,qcd->pab", b[k], W[k], x[k], GR[k + 1])
+    out = []
+    for k in range(n):
+        # <Wx, Wx> with x_k removed from one slot; both slots give 2 * g1
+        g1 = np.einsum("pabq,aijc,bikd,qky,xcdy->pjx",
+                       EL[k], W[k], W[k], x[k], ER[k + 1])
+        g2 = np.einsum("pab,piq,aijc,qcd->bjd", GL[k], b[k], W[k], GR[k + 1])
+        out.append(2.0 * g1 - 2.0 * g2)
+    return out
