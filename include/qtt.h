@@ -1,0 +1,169 @@
+/*
+ * qtt.h -- C ABI of libqtt: quantics-tensor-train contraction and rounding
+ * on an AMD Instinct MI355X (gfx950).
+ *
+ * A tensor train (TT) with n cores represents A(i_1..i_n) = C_1(i_1) ... C_n(i_n)
+ * (paper Sec. 2, eqs. vector_dec / tensor_dec); core 1 holds the most
+ * significant digit (eq. quantization).  Cores cross this boundary as device
+ * pointers in row-major layout:
+ *     MPS core k: [r_{k-1}, d_k, r_k]           (legs == 1)
+ *     MPO core k: [r_{k-1}, d_out, d_in, r_k]   (legs == 2),  y(i) = sum_j A(i,j) x(j)
+ * with ranks[0] == ranks[n] == 1.
+ *
+ * Ownership: the caller owns every device buffer (cores, workspace); the
+ * library allocates no device memory after qtt_create.  Host arrays (phys,
+ * ranks, info arrays) are caller-owned too.  All work is ordered on the
+ * caller's stream.  Calls that return host values (qtt_inner, qtt_round,
+ * qtt_orthogonalize, qtt_contract_round) synchronise that stream before
+ * returning; qtt_contract and the backward calls do not.
+ *
+ * Errors: every call returns a qtt_status; QTT_OK == 0, errors are negative.
+ * On error the outputs are unspecified and host rank arrays are unchanged.
+ * qtt_status_string() names a status.  No C++ exception crosses the ABI.
+ */
+#ifndef QTT_H_
+#define QTT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QTT_OK = 0,
+  QTT_ERR_ARG = -1,         /* null pointer, n < 1, tol < 0, bad enum */
+  QTT_ERR_SPEC = -2,        /* unsupported einsum string */
+  QTT_ERR_SHAPE = -3,       /* core count / physical size / boundary rank mismatch */
+  QTT_ERR_DTYPE = -4,       /* storage type not supported by this call */
+  QTT_ERR_WORKSPACE = -5,   /* workspace missing or smaller than required */
+  QTT_ERR_NODEVICE = -6,    /* no HIP device, or not a gfx950 device */
+  QTT_ERR_HIP = -7,         /* a HIP runtime call failed */
+  QTT_ERR_NONFINITE = -8,   /* NaN/Inf met in the data (norm not finite) */
+  QTT_ERR_NOCONV = -9,      /* Jacobi sweep cap reached */
+  QTT_ERR_UNSUPPORTED = -10 /* size outside the implemented range */
+} qtt_status;
+
+/* Storage type of the cores. */
+typedef enum { QTT_F64 = 0, QTT_F32 = 1 } qtt_dtype;
+
+/* Arithmetic of the GEMM steps of a rounding sweep (the bond products).  The
+ * Householder QR, the Jacobi SVD, norms and the rank decisions are always FP64. */
+typedef enum {
+  QTT_GEMM_FP64 = 0,   /* FP64 MFMA */
+  QTT_GEMM_FP32 = 1,   /* operands rounded to FP32, FP32 MFMA accumulation */
+  QTT_GEMM_BF16X3 = 2, /* three-piece bf16 split, 3 cross products, FP32 MFMA accumulation */
+  QTT_GEMM_BF16X6 = 3  /* three-piece bf16 split, 6 cross products, FP32 MFMA accumulation */
+} qtt_prec;
+
+typedef struct {
+  int32_t n;             /* number of cores, >= 1 */
+  int32_t legs;          /* 1 = MPS (vector), 2 = MPO (matrix) */
+  const int32_t *phys;   /* host, n*legs physical sizes (MPO: d_out, d_in per core) */
+  int64_t *ranks;        /* host, n+1 bond ranks; rewritten by rounding calls */
+  void *const *cores;    /* host array of n device pointers */
+  qtt_dtype dtype;
+} qtt_tt;
+
+/* Diagnostics of a rounding sweep.  Arrays are caller-owned host buffers of
+ * n-1 entries (bond k between cores k and k+1) and may be NULL. */
+typedef struct {
+  double norm;            /* ||A||_F after the QR sweep */
+  double delta;           /* rel_tol * ||A|| / sqrt(n-1) */
+  double err_bound;       /* sqrt(sum_k tail_k^2) >= ||A - round(A)||_F */
+  double *tail;           /* discarded singular-value 2-norm per bond */
+  double *margin_lo;      /* tail(r-1)/delta: > 1 means rank r-1 was not admissible */
+  double *margin_hi;      /* tail(r)/delta:  <= 1 unless the max rank capped */
+  uint8_t *maxrank_hit;   /* 1 where max_rank capped the bond */
+  double *sigma;          /* optional: singular values, bond k at sigma + k*sigma_ld */
+  int64_t sigma_ld;       /* row stride of sigma (>= largest pre-truncation rank) */
+  int32_t jacobi_sweeps_max;
+} qtt_round_info;
+
+typedef struct qtt_context *qtt_handle;
+
+/* Bind a handle to HIP device `device` (must be gfx950). */
+int qtt_create(qtt_handle *h, int device);
+int qtt_destroy(qtt_handle h);
+const char *qtt_status_string(int status);
+
+/* Operation codes for qtt_workspace_size. */
+typedef enum {
+  QTT_OP_CONTRACT = 0,
+  QTT_OP_ORTHOGONALIZE = 1,
+  QTT_OP_ROUND = 2,
+  QTT_OP_CONTRACT_ROUND = 3,
+  QTT_OP_INNER = 4,
+  QTT_OP_INNER_BACKWARD = 5,
+  QTT_OP_CONTRACT_BACKWARD = 6
+} qtt_op;
+
+/* Device workspace (bytes) needed by `op` on operands a (and b for the binary
+ * ops; NULL otherwise).  Pure shape arithmetic: h may be NULL and the core
+ * pointers are not dereferenced.  For QTT_OP_CONTRACT_ROUND, spec selects the product
+ * and max_rank bounds the result; prec selects the GEMM arithmetic. */
+int qtt_workspace_size(qtt_handle h, int op, const char *spec, const qtt_tt *a, const qtt_tt *b,
+                       int64_t max_rank, int prec, size_t *bytes);
+
+/* Exact core-by-core Einstein summation (paper Sec. 3.1, eqs. quant_sum and
+ * einsum): "i,i->i" (Hadamard, a and b MPS) or "ij,j->i" (a an MPO applied to
+ * the MPS b).  C_k[(mu,nu), i, (mu',nu')] with the flattened bond
+ * xi = mu * r_B + nu.  c must be an MPS whose host ranks equal
+ * ranks_a * ranks_b and whose cores are caller-allocated; c's dtype must
+ * match a's and b's (FP64 or FP32).  Asynchronous. */
+int qtt_contract(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qtt_tt *c,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* Left-to-right QR sweep (the QR normalisation of Sec. 3.2; canonical form
+ * of Sec. 1): cores 1..n-1 become left-orthonormal, the norm moves to core n.
+ * In place (FP64 MPS); ranks may shrink to min(d r'_{k-1}, r_k) and are
+ * rewritten in t->ranks.  *norm_host receives ||A||_F.  Synchronous. */
+int qtt_orthogonalize(qtt_handle h, qtt_tt *t, double *norm_host, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* TT rounding: QR sweep left to right, then truncated SVD sweep right to left
+ * (Householder QR and one-sided Jacobi SVD, FP64).  At each bond the kept
+ * rank is the smallest r >= 1 whose discarded singular values have 2-norm
+ * <= delta = rel_tol * ||A|| / sqrt(n-1), capped at max_rank (<= 0: no cap);
+ * this is the truncation of Sec. 3.2's decomposition(max_rank, cutoff)
+ * options read as a relative Frobenius tolerance.  In place on an FP64 MPS;
+ * the result is right-orthonormal in cores 2..n.  Synchronous. */
+int qtt_round(qtt_handle h, qtt_tt *t, double rel_tol, int64_t max_rank, int prec,
+              qtt_round_info *info, void *ws, size_t ws_bytes, void *stream);
+
+/* Contraction followed by rounding without materialising the contracted
+ * cores: the QR sweep works on the bond products R_{k-1} C_k formed from the
+ * operand cores directly (for "ij,j->i": (R X_k) then the MPO core).  out
+ * is an FP64 MPS with caller-allocated cores large enough for the rounded
+ * ranks (min(r_a r_b, max_rank, profile) per bond is always sufficient);
+ * its ranks are written on return.  Synchronous. */
+int qtt_contract_round(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qtt_tt *out,
+                       double rel_tol, int64_t max_rank, int prec, qtt_round_info *info,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* <a, b> = E_n, E_0 = [[1]], E_k = sum_i a_k(i)^T E_{k-1} b_k(i) (the <C|C>
+ * contractions of Sec. 3.3).  MPS operands of equal length and physical
+ * sizes, FP64 or FP32 (accumulated in the storage type).  Synchronous. */
+int qtt_inner(qtt_handle h, const qtt_tt *a, const qtt_tt *b, double *out_host, void *ws,
+              size_t ws_bytes, void *stream);
+
+/* Gradient of g * <a, b> with respect to the cores of a (and of b when db is
+ * not NULL): da_k = g * E_{k-1} b_k(i) F_{k+1}^T from left/right environment
+ * sweeps (the core derivative of Sec. 3.3, eq. variational).  da/db are
+ * caller-allocated MPS with the shapes of a/b.  Asynchronous. */
+int qtt_inner_backward(qtt_handle h, const qtt_tt *a, const qtt_tt *b, double g, qtt_tt *da,
+                       qtt_tt *db, void *ws, size_t ws_bytes, void *stream);
+
+/* Local backward of qtt_contract: given dC (shaped like c), writes
+ * dB_k[nu,j,nu'] = sum_{mu,i,mu'} A_k[mu,i,j,mu'] dC_k[(mu,nu),i,(mu',nu')]
+ * (and dA when da is not NULL).  Asynchronous. */
+int qtt_contract_backward(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b,
+                          const qtt_tt *dc, qtt_tt *da, qtt_tt *db, void *ws, size_t ws_bytes,
+                          void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTT_H_ */

@@ -1,0 +1,891 @@
+// libqtt host side: argument validation, workspace planning and sequencing of
+// the contraction / QR sweep / SVD sweep / environment sweeps on the caller's
+// stream.  See include/qtt.h for the contract of every entry point.
+#include "../../include/qtt.h"
+#include "qtt_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace qtt;
+
+struct qtt_context {
+  int device;
+  TruncOut* pin_trunc;  // pinned host readback
+  int* pin_int;
+  double* pin_dbl;
+};
+
+namespace {
+
+constexpr int kMaxSweeps = 40;
+constexpr int kMaxRows = 4096;
+
+#define QTT_HIP(call)                          \
+  do {                                         \
+    hipError_t e_ = (call);                    \
+    if (e_ != hipSuccess) return QTT_ERR_HIP;  \
+  } while (0)
+
+struct Scoped {
+  int prev = -1;
+  explicit Scoped(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~Scoped() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int check_tt(const qtt_tt* t, int legs_expected) {
+  if (!t || !t->phys || !t->ranks || !t->cores) return QTT_ERR_ARG;
+  if (t->n < 1) return QTT_ERR_ARG;
+  if (t->legs != 1 && t->legs != 2) return QTT_ERR_ARG;
+  if (legs_expected && t->legs != legs_expected) return QTT_ERR_SHAPE;
+  if (t->dtype != QTT_F64 && t->dtype != QTT_F32) return QTT_ERR_DTYPE;
+  if (t->ranks[0] != 1 || t->ranks[t->n] != 1) return QTT_ERR_SHAPE;
+  for (int k = 0; k <= t->n; ++k)
+    if (t->ranks[k] < 1 || t->ranks[k] > (1 << 24)) return QTT_ERR_SHAPE;
+  for (int k = 0; k < t->n * t->legs; ++k)
+    if (t->phys[k] < 1) return QTT_ERR_SHAPE;
+  for (int k = 0; k < t->n; ++k)
+    if (!t->cores[k]) return QTT_ERR_ARG;
+  return QTT_OK;
+}
+
+inline int dphys(const qtt_tt* t, int k) { return t->phys[k * t->legs]; }          // output leg
+inline int dphys_in(const qtt_tt* t, int k) { return t->phys[k * t->legs + t->legs - 1]; }  // input leg
+
+enum Kind { K_TT = 0, K_HAD = 1, K_MPO = 2 };
+
+// Shapes of the operand(s) of a rounding sweep.
+struct Shape {
+  Kind kind;
+  int n;
+  std::vector<int> d;        // output physical size per core
+  std::vector<long> rc;      // contracted bond ranks r_C (n+1)
+  std::vector<long> ra, rb;  // operand ranks (factored kinds)
+  std::vector<int> dj;       // MPO input leg
+};
+
+// Workspace plan (offsets in doubles) shared by size queries and execution.
+struct Plan {
+  std::vector<long> m;     // rows of M_k (k < n-1): rho_{k-1} d_k
+  std::vector<long> rho;   // rank after QR, rho[-1] = 1 stored at index 0 => rho[k+1]
+  std::vector<long> offM, offT;
+  long offCenter = 0, offR = 0, offY = 0, offZ = 0, offX = 0, offXc = 0, offYn = 0, offTB = 0;
+  long offSig = 0, offPerm = 0, offTrunc = 0, offCtr = 0, offNorm = 0, offSweeps = 0, offOne = 0;
+  long total = 0;
+  long maxr_bound = 0;
+};
+
+long round_up(long x, long a) { return (x + a - 1) / a * a; }
+
+int make_plan(const Shape& s, long max_rank, Plan& P) {
+  const int n = s.n;
+  P.m.assign(n, 0);
+  P.rho.assign(n + 1, 1);
+  P.offM.assign(n, 0);
+  P.offT.assign(n, 0);
+  long off = 0;
+  auto take = [&](long cnt) {
+    long o = off;
+    off += round_up(std::max(cnt, 1L), 32);
+    return o;
+  };
+  long maxR = 1, maxY = 1, maxQ = 1;
+  for (int k = 0; k + 1 < n; ++k) {
+    const long m = P.rho[k] * s.d[k];
+    const long cols = s.rc[k + 1];
+    if (m > kMaxRows) return QTT_ERR_UNSUPPORTED;
+    P.m[k] = m;
+    P.rho[k + 1] = std::min(m, cols);
+    P.offM[k] = take(m * cols);
+    P.offT[k] = take((long)qr_num_panels((int)m, (int)cols) * 256);
+    maxR = std::max(maxR, P.rho[k + 1] * cols);
+    maxQ = std::max(maxQ, m * P.rho[k + 1]);  // explicit Q_k for qtt_orthogonalize
+    if (s.kind != K_TT) {
+      // Y = R X_k (rows rho_{k-1} * r_a, cols dj * r_b')
+      const long dj = (s.kind == K_MPO) ? s.dj[k] : s.d[k];
+      maxY = std::max(maxY, P.rho[k] * s.ra[k] * dj * s.rb[k + 1]);
+    }
+  }
+  {
+    const int k = n - 1;
+    const long dj = (s.kind == K_MPO) ? s.dj[k] : s.d[k];
+    if (s.kind != K_TT) maxY = std::max(maxY, P.rho[k] * s.ra[k] * dj * s.rb[k + 1]);
+  }
+  P.offCenter = take(P.rho[n - 1] * s.d[n - 1]);
+  P.offR = take(maxR);
+  P.offY = take(maxY);
+  // SVD sweep bounds: r''_k <= min(rho_k, max_rank, d^(n-k) products)
+  std::vector<long> rr(n + 1, 1);
+  {
+    long right = 1;
+    for (int k = n - 1; k >= 1; --k) {
+      right = std::min<long>(right * s.d[k], 1L << 40);
+      long b = std::min(P.rho[k], right);
+      if (max_rank > 0) b = std::min(b, max_rank);
+      rr[k] = std::max(b, 1L);
+    }
+  }
+  long maxZ = 1, maxX = 1, maxYn = 1, maxTB = 1, maxP = 1;
+  for (int k = n - 1; k >= 1; --k) {
+    const long D = s.d[k] * rr[k + 1];
+    const long rows = P.rho[k];  // rho_{k-1} in 1-based terms = rows of B
+    // Q_k [Y; 0] lives in Z: m_k x r''_{k+1}  (for k = n-1 the centre is used)
+    if (k < n - 1) maxZ = std::max(maxZ, P.m[k] * rr[k + 1]);
+    maxZ = std::max(maxZ, rows * D);
+    if (rows >= D) {
+      maxX = std::max(maxX, D * D);
+      maxTB = std::max(maxTB, (long)qr_num_panels((int)rows, (int)D) * 256);
+      maxP = std::max(maxP, D);
+    } else {
+      maxX = std::max(maxX, rows * D);
+      maxP = std::max(maxP, rows);
+    }
+    if (16 * D > 20000) return QTT_ERR_UNSUPPORTED;  // Jacobi stages 16 rows of length D in LDS
+    maxYn = std::max(maxYn, rows * rr[k]);
+  }
+  if (n >= 2) maxZ = std::max(maxZ, P.m[0] * rr[1]);
+  maxZ = std::max(maxZ, maxQ);
+  P.offZ = take(maxZ);
+  P.offX = take(maxX);
+  P.offXc = take(maxX);
+  P.offYn = take(maxYn);
+  P.offTB = take(maxTB);
+  P.offSig = take(maxP);
+  P.offPerm = take(maxP / 2 + 1);
+  P.offTrunc = take(8);
+  P.offCtr = take(8);
+  P.offNorm = take(1);
+  P.offSweeps = take(1);
+  P.offOne = take(1);
+  P.total = off;
+  P.maxr_bound = 0;
+  for (int k = 0; k <= n; ++k) P.maxr_bound = std::max(P.maxr_bound, rr[k]);
+  return QTT_OK;
+}
+
+int shape_from_tt(const qtt_tt* t, Shape& s) {
+  s.kind = K_TT;
+  s.n = t->n;
+  s.d.resize(t->n);
+  s.rc.resize(t->n + 1);
+  for (int k = 0; k < t->n; ++k) s.d[k] = dphys(t, k);
+  for (int k = 0; k <= t->n; ++k) s.rc[k] = t->ranks[k];
+  return QTT_OK;
+}
+
+int parse_spec(const char* spec, Kind& kind) {
+  if (!spec) return QTT_ERR_ARG;
+  std::string sp(spec);
+  std::string t;
+  for (char c : sp)
+    if (c != ' ') t += c;
+  if (t == "i,i->i") {
+    kind = K_HAD;
+    return QTT_OK;
+  }
+  if (t == "ij,j->i") {
+    kind = K_MPO;
+    return QTT_OK;
+  }
+  return QTT_ERR_SPEC;
+}
+
+int shape_from_pair(const char* spec, const qtt_tt* a, const qtt_tt* b, Shape& s) {
+  Kind kind;
+  int st = parse_spec(spec, kind);
+  if (st) return st;
+  if ((st = check_tt(a, kind == K_MPO ? 2 : 1))) return st;
+  if ((st = check_tt(b, 1))) return st;
+  if (a->n != b->n) return QTT_ERR_SHAPE;
+  const int n = a->n;
+  s.kind = kind;
+  s.n = n;
+  s.d.resize(n);
+  s.dj.resize(n);
+  s.rc.resize(n + 1);
+  s.ra.resize(n + 1);
+  s.rb.resize(n + 1);
+  for (int k = 0; k < n; ++k) {
+    if (kind == K_HAD) {
+      if (dphys(a, k) != dphys(b, k)) return QTT_ERR_SHAPE;
+      s.d[k] = dphys(a, k);
+      s.dj[k] = s.d[k];
+    } else {
+      if (dphys_in(a, k) != dphys(b, k)) return QTT_ERR_SHAPE;
+      s.d[k] = dphys(a, k);
+      s.dj[k] = dphys_in(a, k);
+    }
+  }
+  for (int k = 0; k <= n; ++k) {
+    s.ra[k] = a->ranks[k];
+    s.rb[k] = b->ranks[k];
+    s.rc[k] = a->ranks[k] * b->ranks[k];
+  }
+  return QTT_OK;
+}
+
+// Y = R * X (rows, K) x (K, cols) in the requested GEMM arithmetic.
+hipError_t bond_gemm(hipStream_t st, int prec, int rows, int cols, int K, const double* R, long ldr,
+                     const double* X, long ldx, double* Y, long ldy) {
+  switch (prec) {
+    case QTT_GEMM_FP32:
+      return gemm_f64_via_f32(st, false, false, rows, cols, K, R, ldr, X, ldx, Y, ldy);
+    case QTT_GEMM_BF16X3:
+      return gemm_bf16split(st, false, false, rows, cols, K, R, ldr, X, ldx, Y, ldy, 3);
+    case QTT_GEMM_BF16X6:
+      return gemm_bf16split(st, false, false, rows, cols, K, R, ldr, X, ldx, Y, ldy, 6);
+    default:
+      return gemm_f64(st, false, false, rows, cols, K, 1.0, R, ldr, 0, X, ldx, 0, 0.0, Y, ldy, 0, 1);
+  }
+}
+
+struct Sweep {
+  qtt_context* h;
+  hipStream_t st;
+  double* ws;
+  const Shape* s;
+  const Plan* P;
+  int prec;
+};
+
+// QR sweep: M_k = R_{k-1} C_k factored in place; fills the centre core.
+int qr_sweep(Sweep& w, const qtt_tt* t, const qtt_tt* a, const qtt_tt* b) {
+  const Shape& s = *w.s;
+  const Plan& P = *w.P;
+  const int n = s.n;
+  double* ws = w.ws;
+  double* R = ws + P.offR;
+  double* Yb = ws + P.offY;
+  for (int k = 0; k < n; ++k) {
+    const long rho0 = P.rho[k];
+    const long cols = s.rc[k + 1];
+    const bool last = (k == n - 1);
+    double* M = last ? ws + P.offCenter : ws + P.offM[k];
+    const long ldm = cols;
+    if (s.kind == K_TT) {
+      const double* Ck = (const double*)t->cores[k];
+      if (k == 0) {
+        QTT_HIP(copy_pad_rows(w.st, Ck, (int)(s.d[k]), (int)cols, cols, M, (int)(s.d[k]), ldm));
+      } else {
+        QTT_HIP(bond_gemm(w.st, w.prec, (int)rho0, (int)(s.d[k] * cols), (int)s.rc[k], R, s.rc[k], Ck,
+                          s.d[k] * cols, M, s.d[k] * cols));
+      }
+    } else {
+      // factored: Y[(a,mu),(j,nu')] = sum_nu R[(a,mu),nu] B[nu,(j,nu')]
+      const double* Ak = (const double*)a->cores[k];
+      const double* Bk = (const double*)b->cores[k];
+      const long ra0 = s.ra[k], ra1 = s.ra[k + 1], rb0 = s.rb[k], rb1 = s.rb[k + 1];
+      const long dj = s.dj[k];
+      const double* Rk = R;
+      if (k == 0) {
+        // R_{-1} = [[1]]: Y = B_0 repeated over mu (ra0 == 1)
+        QTT_HIP(fill_f64(w.st, ws + P.offOne, 1.0, 1));
+        Rk = ws + P.offOne;
+      }
+      QTT_HIP(bond_gemm(w.st, w.prec, (int)(rho0 * ra0), (int)(dj * rb1), (int)rb0, Rk, rb0, Bk, dj * rb1, Yb,
+                        dj * rb1));
+      if (s.kind == K_MPO) {
+        QTT_HIP(bond_mpo_apply(w.st, Yb, (int)rho0, (int)ra0, (int)dj, (int)rb1, Ak, s.d[k], (int)ra1, M));
+      } else {
+        QTT_HIP(bond_hadamard_apply(w.st, Yb, (int)rho0, (int)ra0, s.d[k], (int)rb1, Ak, (int)ra1, M));
+      }
+    }
+    if (!last) {
+      const long m = P.m[k];
+      QTT_HIP(householder_qr(w.st, M, (int)m, (int)cols, ldm, ws + P.offT[k]));
+      QTT_HIP(extract_r(w.st, M, (int)P.rho[k + 1], (int)cols, ldm, R));
+    }
+  }
+  QTT_HIP(frob_norm(w.st, ws + P.offCenter, P.rho[n - 1] * s.d[n - 1], ws + P.offNorm));
+  return QTT_OK;
+}
+
+int readback(qtt_context* h, hipStream_t st, const void* dev, size_t bytes, void* pinned) {
+  QTT_HIP(hipMemcpyAsync(pinned, dev, bytes, hipMemcpyDeviceToHost, st));
+  QTT_HIP(hipStreamSynchronize(st));
+  return QTT_OK;
+}
+
+// SVD sweep from the right; writes the rounded cores into out.
+int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_info* info, std::vector<long>& newr) {
+  const Shape& s = *w.s;
+  const Plan& P = *w.P;
+  const int n = s.n;
+  double* ws = w.ws;
+  double* Z = ws + P.offZ;
+  double* X = ws + P.offX;
+  double* Xc = ws + P.offXc;
+  double* Yn = ws + P.offYn;
+  double* TB = ws + P.offTB;
+  double* sig = ws + P.offSig;
+  int* perm = (int*)(ws + P.offPerm);
+  TruncOut* tr = (TruncOut*)(ws + P.offTrunc);
+  unsigned* ctr = (unsigned*)(ws + P.offCtr);
+  int* sweeps = (int*)(ws + P.offSweeps);
+  newr.assign(n + 1, 1);
+  double norm = 0.0;
+  {
+    int e = readback(w.h, w.st, ws + P.offNorm, sizeof(double), w.h->pin_dbl);
+    if (e) return e;
+    norm = w.h->pin_dbl[0];
+  }
+  if (!std::isfinite(norm)) return QTT_ERR_NONFINITE;
+  double err2 = 0.0;
+  int maxsw = 0;
+  long rnext = 1;  // r''_{k+1}
+  for (int k = n - 1; k >= 1; --k) {
+    const long rows = P.rho[k];
+    const long D = s.d[k] * rnext;
+    const double* B;
+    if (k == n - 1) {
+      B = ws + P.offCenter;
+    } else {
+      // Z = Q_k [Y_{k+1}; 0]  (m_k x r''_{k+1}) = B_k as rows x D
+      QTT_HIP(copy_pad_rows(w.st, Yn, (int)P.rho[k + 1], (int)rnext, rnext, Z, (int)P.m[k], rnext));
+      QTT_HIP(apply_q(w.st, ws + P.offM[k], (int)P.m[k], (int)P.rho[k + 1], s.rc[k + 1], ws + P.offT[k], Z,
+                      (int)rnext, rnext, false));
+      B = Z;
+    }
+    // Jacobi acts on the rows of F: F = R (D x D) from a QR of B when B is
+    // tall, F = B itself otherwise.  Xc keeps F for U Sigma = F V.
+    const bool tall = rows >= D;
+    int p;
+    const int L = (int)D;
+    if (tall) {
+      if (B != Z) QTT_HIP(copy_pad_rows(w.st, B, (int)rows, (int)D, D, Z, (int)rows, D));
+      QTT_HIP(householder_qr(w.st, Z, (int)rows, (int)D, D, TB));
+      QTT_HIP(extract_r(w.st, Z, (int)D, (int)D, D, X));
+      p = (int)D;
+    } else {
+      QTT_HIP(copy_pad_rows(w.st, B, (int)rows, (int)D, D, X, (int)rows, D));
+      p = (int)rows;
+    }
+    QTT_HIP(copy_pad_rows(w.st, X, p, L, L, Xc, p, L));
+    QTT_HIP(jacobi_rows(w.st, X, p, L, ctr, kMaxSweeps, sweeps));
+    QTT_HIP(row_norms_sorted(w.st, X, p, L, sig, perm));
+    QTT_HIP(truncate_decide(w.st, sig, p, ws + P.offNorm, rel_tol, n - 1, max_rank, tr));
+    QTT_HIP(hipMemcpyAsync(w.h->pin_int, sweeps, sizeof(int), hipMemcpyDeviceToHost, w.st));
+    int e = readback(w.h, w.st, tr, sizeof(TruncOut), w.h->pin_trunc);
+    if (e) return e;
+    const TruncOut t = *w.h->pin_trunc;
+    const int swp = *w.h->pin_int;
+    if (swp >= kMaxSweeps) return QTT_ERR_NOCONV;
+    maxsw = std::max(maxsw, swp);
+    const int r = t.rank;
+    if (info) {
+      if (info->tail) info->tail[k - 1] = t.tail_r;
+      if (info->margin_lo) info->margin_lo[k - 1] = t.delta > 0 ? t.tail_rm1 / t.delta : INFINITY;
+      if (info->margin_hi) info->margin_hi[k - 1] = t.delta > 0 ? t.tail_r / t.delta : 0.0;
+      if (info->maxrank_hit) info->maxrank_hit[k - 1] = (uint8_t)t.capped;
+      if (info->sigma && info->sigma_ld > 0) {
+        const long cnt = std::min<long>(p, info->sigma_ld);
+        QTT_HIP(hipMemcpyAsync(info->sigma + (long)(k - 1) * info->sigma_ld, sig, cnt * sizeof(double),
+                               hipMemcpyDeviceToHost, w.st));
+        QTT_HIP(hipStreamSynchronize(w.st));
+        for (long i = cnt; i < info->sigma_ld; ++i) info->sigma[(long)(k - 1) * info->sigma_ld + i] = 0.0;
+      }
+    }
+    err2 += t.tail_r * t.tail_r;
+    // core k <- V_r^T: rows perm[:r] of X, normalised  ([r, d_k, r''_{k+1}])
+    double* core = (double*)out->cores[k];
+    QTT_HIP(gather_rows_normalized(w.st, X, L, perm, sig, tr, core, L, r));
+    // Y_k = U Sigma = B V_r  (rows x r): tall B = Q_B R  =>  Q_B [R V_r; 0]
+    if (tall) {
+      QTT_HIP(gemm_f64(w.st, false, true, p, r, L, 1.0, Xc, L, 0, core, L, 0, 0.0, Yn, r, 0, 1));
+      if (rows > p) QTT_HIP(fill_f64(w.st, Yn + (long)p * r, 0.0, (rows - p) * r));
+      QTT_HIP(apply_q(w.st, Z, (int)rows, p, D, TB, Yn, r, r, false));
+    } else {
+      QTT_HIP(gemm_f64(w.st, false, true, p, r, L, 1.0, Xc, L, 0, core, L, 0, 0.0, Yn, r, 0, 1));
+    }
+    newr[k] = r;
+    rnext = r;
+  }
+  // core 0 = Q_0 [Y_1; 0]
+  if (n == 1) {
+    QTT_HIP(copy_pad_rows(w.st, ws + P.offCenter, 1, s.d[0], s.d[0], (double*)out->cores[0], 1, s.d[0]));
+  } else {
+    QTT_HIP(copy_pad_rows(w.st, Yn, (int)P.rho[1], (int)rnext, rnext, Z, (int)P.m[0], rnext));
+    QTT_HIP(apply_q(w.st, ws + P.offM[0], (int)P.m[0], (int)P.rho[1], s.rc[1], ws + P.offT[0], Z, (int)rnext,
+                    rnext, false));
+    QTT_HIP(copy_pad_rows(w.st, Z, (int)P.m[0], (int)rnext, rnext, (double*)out->cores[0], (int)P.m[0], rnext));
+  }
+  QTT_HIP(hipStreamSynchronize(w.st));
+  if (info) {
+    info->norm = norm;
+    info->delta = (n > 1) ? rel_tol * norm / std::sqrt((double)(n - 1)) : 0.0;
+    info->err_bound = std::sqrt(err2);
+    info->jacobi_sweeps_max = maxsw;
+  }
+  return QTT_OK;
+}
+
+size_t ws_bytes_of(const Plan& P) { return (size_t)P.total * sizeof(double) + 256; }
+
+double* align_ws(void* ws) {
+  uintptr_t p = (uintptr_t)ws;
+  p = (p + 255) & ~(uintptr_t)255;
+  return (double*)p;
+}
+
+// ---------------------------------------------------------------- inner products
+struct InnerPlan {
+  long offE0, offE1, offT, total;
+};
+InnerPlan inner_plan(const qtt_tt* a, const qtt_tt* b) {
+  long maxE = 1, maxT = 1;
+  for (int k = 0; k < a->n; ++k) {
+    maxE = std::max(maxE, a->ranks[k + 1] * b->ranks[k + 1]);
+    maxE = std::max(maxE, a->ranks[k] * b->ranks[k]);
+    maxT = std::max(maxT, a->ranks[k] * (long)dphys(a, k) * b->ranks[k + 1]);
+  }
+  InnerPlan p;
+  p.offE0 = 0;
+  p.offE1 = round_up(maxE, 32);
+  p.offT = p.offE1 + round_up(maxE, 32);
+  p.total = p.offT + round_up(maxT, 32);
+  return p;
+}
+
+struct EnvPlan {
+  std::vector<long> offE, offF;
+  long offT, offT2, total;
+};
+EnvPlan env_plan(const qtt_tt* a, const qtt_tt* b) {
+  EnvPlan p;
+  const int n = a->n;
+  p.offE.resize(n + 1);
+  p.offF.resize(n + 1);
+  long off = 0, maxT = 1;
+  for (int k = 0; k <= n; ++k) {
+    p.offE[k] = off;
+    off += round_up(a->ranks[k] * b->ranks[k], 32);
+    p.offF[k] = off;
+    off += round_up(a->ranks[k] * b->ranks[k], 32);
+  }
+  for (int k = 0; k < n; ++k) {
+    const long d = dphys(a, k);
+    maxT = std::max(maxT, a->ranks[k] * d * b->ranks[k + 1]);
+    maxT = std::max(maxT, b->ranks[k] * d * a->ranks[k + 1]);
+  }
+  p.offT = off;
+  off += round_up(maxT, 32);
+  p.offT2 = off;
+  off += round_up(maxT, 32);
+  p.total = off;
+  return p;
+}
+
+template <typename T>
+hipError_t gemmT(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const T* A, long lda,
+                 const T* B, long ldb, double beta, T* C, long ldc);
+template <>
+hipError_t gemmT<double>(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+                         long lda, const double* B, long ldb, double beta, double* C, long ldc) {
+  return gemm_f64(s, ta, tb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+}
+template <>
+hipError_t gemmT<float>(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const float* A,
+                        long lda, const float* B, long ldb, double beta, float* C, long ldc) {
+  return gemm_f32(s, ta, tb, M, N, K, (float)alpha, A, lda, 0, B, ldb, 0, (float)beta, C, ldc, 0, 1);
+}
+
+template <typename T>
+hipError_t fill_T(hipStream_t s, T* p, double v, long n);
+template <>
+hipError_t fill_T<double>(hipStream_t s, double* p, double v, long n) {
+  return fill_f64(s, p, v, n);
+}
+template <>
+hipError_t fill_T<float>(hipStream_t s, float* p, double v, long n) {
+  return fill_f32(s, p, (float)v, n);
+}
+
+// E_{k+1} = sum_i a_k(i)^T E_k b_k(i)
+template <typename T>
+hipError_t env_step_left(hipStream_t st, const T* E, const T* ak, const T* bk, long ra0, long ra1, long rb0, long rb1,
+                         long d, T* Tt, T* Enext) {
+  hipError_t e = gemmT<T>(st, false, false, (int)ra0, (int)(d * rb1), (int)rb0, 1.0, E, rb0, bk, d * rb1, 0.0, Tt,
+                          d * rb1);
+  if (e != hipSuccess) return e;
+  return gemmT<T>(st, true, false, (int)ra1, (int)rb1, (int)(ra0 * d), 1.0, ak, ra1, Tt, rb1, 0.0, Enext, rb1);
+}
+// F_k = sum_i a_k(i) F_{k+1} b_k(i)^T
+template <typename T>
+hipError_t env_step_right(hipStream_t st, const T* F, const T* ak, const T* bk, long ra0, long ra1, long rb0,
+                          long rb1, long d, T* Tt, T* Fprev) {
+  hipError_t e = gemmT<T>(st, false, false, (int)(ra0 * d), (int)rb1, (int)ra1, 1.0, ak, ra1, F, rb1, 0.0, Tt, rb1);
+  if (e != hipSuccess) return e;
+  return gemmT<T>(st, false, true, (int)ra0, (int)rb0, (int)(d * rb1), 1.0, Tt, d * rb1, bk, d * rb1, 0.0, Fprev,
+                  rb0);
+}
+
+template <typename T>
+int inner_impl(qtt_context* h, const qtt_tt* a, const qtt_tt* b, double* out, void* ws_raw, hipStream_t st) {
+  InnerPlan p = inner_plan(a, b);
+  T* ws = (T*)align_ws(ws_raw);
+  T* E = ws + p.offE0;
+  T* E2 = ws + p.offE1;
+  T* Tt = ws + p.offT;
+  QTT_HIP(fill_T<T>(st, E, 1.0, 1));
+  for (int k = 0; k < a->n; ++k) {
+    QTT_HIP(env_step_left<T>(st, E, (const T*)a->cores[k], (const T*)b->cores[k], a->ranks[k], a->ranks[k + 1],
+                             b->ranks[k], b->ranks[k + 1], dphys(a, k), Tt, E2));
+    std::swap(E, E2);
+  }
+  T hv;
+  QTT_HIP(hipMemcpyAsync(&hv, E, sizeof(T), hipMemcpyDeviceToHost, st));
+  QTT_HIP(hipStreamSynchronize(st));
+  *out = (double)hv;
+  return QTT_OK;
+}
+
+template <typename T>
+int inner_backward_impl(const qtt_tt* a, const qtt_tt* b, double g, qtt_tt* da, qtt_tt* db, void* ws_raw,
+                        hipStream_t st) {
+  EnvPlan p = env_plan(a, b);
+  T* ws = (T*)align_ws(ws_raw);
+  const int n = a->n;
+  QTT_HIP(fill_T<T>(st, ws + p.offE[0], 1.0, 1));
+  QTT_HIP(fill_T<T>(st, ws + p.offF[n], 1.0, 1));
+  for (int k = 0; k < n; ++k)
+    QTT_HIP(env_step_left<T>(st, ws + p.offE[k], (const T*)a->cores[k], (const T*)b->cores[k], a->ranks[k],
+                             a->ranks[k + 1], b->ranks[k], b->ranks[k + 1], dphys(a, k), ws + p.offT,
+                             ws + p.offE[k + 1]));
+  for (int k = n - 1; k >= 0; --k)
+    QTT_HIP(env_step_right<T>(st, ws + p.offF[k + 1], (const T*)a->cores[k], (const T*)b->cores[k], a->ranks[k],
+                              a->ranks[k + 1], b->ranks[k], b->ranks[k + 1], dphys(a, k), ws + p.offT,
+                              ws + p.offF[k]));
+  for (int k = 0; k < n; ++k) {
+    const long ra0 = a->ranks[k], ra1 = a->ranks[k + 1], rb0 = b->ranks[k], rb1 = b->ranks[k + 1], d = dphys(a, k);
+    if (da) {
+      // T = E_k b_k  (ra0 x d rb1);  da = g T F_{k+1}^T  ((ra0 d) x ra1)
+      QTT_HIP(gemmT<T>(st, false, false, (int)ra0, (int)(d * rb1), (int)rb0, 1.0, ws + p.offE[k], rb0,
+                       (const T*)b->cores[k], d * rb1, 0.0, ws + p.offT, d * rb1));
+      QTT_HIP(gemmT<T>(st, false, true, (int)(ra0 * d), (int)ra1, (int)rb1, g, ws + p.offT, rb1, ws + p.offF[k + 1],
+                       rb1, 0.0, (T*)da->cores[k], ra1));
+    }
+    if (db) {
+      // T = E_k^T a_k  (rb0 x d ra1);  db = g T F_{k+1}  ((rb0 d) x rb1)
+      QTT_HIP(gemmT<T>(st, true, false, (int)rb0, (int)(d * ra1), (int)ra0, 1.0, ws + p.offE[k], rb0,
+                       (const T*)a->cores[k], d * ra1, 0.0, ws + p.offT, d * ra1));
+      QTT_HIP(gemmT<T>(st, false, false, (int)(rb0 * d), (int)rb1, (int)ra1, g, ws + p.offT, ra1, ws + p.offF[k + 1],
+                       rb1, 0.0, (T*)db->cores[k], rb1));
+    }
+  }
+  return QTT_OK;
+}
+
+int same_layout(const qtt_tt* a, const qtt_tt* b) {
+  if (a->n != b->n || a->dtype != b->dtype) return QTT_ERR_SHAPE;
+  for (int k = 0; k < a->n; ++k)
+    if (dphys(a, k) != dphys(b, k)) return QTT_ERR_SHAPE;
+  return QTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qtt_status_string(int status) {
+  switch (status) {
+    case QTT_OK: return "ok";
+    case QTT_ERR_ARG: return "invalid argument";
+    case QTT_ERR_SPEC: return "unsupported einsum specification";
+    case QTT_ERR_SHAPE: return "shape mismatch";
+    case QTT_ERR_DTYPE: return "unsupported dtype";
+    case QTT_ERR_WORKSPACE: return "workspace too small";
+    case QTT_ERR_NODEVICE: return "no gfx950 HIP device";
+    case QTT_ERR_HIP: return "HIP runtime error";
+    case QTT_ERR_NONFINITE: return "non-finite value";
+    case QTT_ERR_NOCONV: return "Jacobi SVD did not converge";
+    case QTT_ERR_UNSUPPORTED: return "size outside the implemented range";
+    default: return "unknown status";
+  }
+}
+
+int qtt_create(qtt_handle* h, int device) {
+  if (!h) return QTT_ERR_ARG;
+  *h = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return QTT_ERR_NODEVICE;
+  if (device < 0 || device >= count) return QTT_ERR_NODEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return QTT_ERR_NODEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return QTT_ERR_NODEVICE;
+  Scoped sc(device);
+  qtt_context* c = new (std::nothrow) qtt_context();
+  if (!c) return QTT_ERR_ARG;
+  c->device = device;
+  if (hipHostMalloc((void**)&c->pin_trunc, sizeof(TruncOut), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->pin_int, 64, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->pin_dbl, 64, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return QTT_ERR_HIP;
+  }
+  *h = c;
+  return QTT_OK;
+}
+
+int qtt_destroy(qtt_handle h) {
+  if (!h) return QTT_ERR_ARG;
+  (void)hipHostFree(h->pin_trunc);
+  (void)hipHostFree(h->pin_int);
+  (void)hipHostFree(h->pin_dbl);
+  delete h;
+  return QTT_OK;
+}
+
+int qtt_workspace_size(qtt_handle h, int op, const char* spec, const qtt_tt* a, const qtt_tt* b, int64_t max_rank,
+                       int prec, size_t* bytes) {
+  (void)h;  // pure shape arithmetic: a NULL handle is accepted
+  if (!bytes) return QTT_ERR_ARG;
+  *bytes = 0;
+  int st;
+  switch (op) {
+    case QTT_OP_CONTRACT:
+    case QTT_OP_CONTRACT_BACKWARD:
+      *bytes = 0;
+      return QTT_OK;
+    case QTT_OP_ORTHOGONALIZE:
+    case QTT_OP_ROUND: {
+      if ((st = check_tt(a, 1))) return st;
+      Shape s;
+      shape_from_tt(a, s);
+      Plan P;
+      if ((st = make_plan(s, op == QTT_OP_ROUND ? max_rank : 0, P))) return st;
+      *bytes = ws_bytes_of(P);
+      return QTT_OK;
+    }
+    case QTT_OP_CONTRACT_ROUND: {
+      Shape s;
+      if ((st = shape_from_pair(spec, a, b, s))) return st;
+      Plan P;
+      if ((st = make_plan(s, max_rank, P))) return st;
+      *bytes = ws_bytes_of(P);
+      return QTT_OK;
+    }
+    case QTT_OP_INNER: {
+      if ((st = check_tt(a, 1)) || (st = check_tt(b, 1))) return st;
+      *bytes = (size_t)inner_plan(a, b).total * 8 + 256;
+      return QTT_OK;
+    }
+    case QTT_OP_INNER_BACKWARD: {
+      if ((st = check_tt(a, 1)) || (st = check_tt(b, 1))) return st;
+      *bytes = (size_t)env_plan(a, b).total * 8 + 256;
+      return QTT_OK;
+    }
+    default:
+      return QTT_ERR_ARG;
+  }
+  (void)prec;
+}
+
+int qtt_contract(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* c, void* ws,
+                 size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (!h) return QTT_ERR_ARG;
+  Shape s;
+  int st = shape_from_pair(spec, a, b, s);
+  if (st) return st;
+  if ((st = check_tt(c, 1))) return st;
+  if (c->n != a->n || a->dtype != b->dtype || c->dtype != a->dtype) return QTT_ERR_SHAPE;
+  for (int k = 0; k <= a->n; ++k)
+    if (c->ranks[k] != a->ranks[k] * b->ranks[k]) return QTT_ERR_SHAPE;
+  for (int k = 0; k < a->n; ++k)
+    if (dphys(c, k) != s.d[k]) return QTT_ERR_SHAPE;
+  Scoped sc(h->device);
+  hipStream_t strm = (hipStream_t)stream;
+  for (int k = 0; k < a->n; ++k) {
+    const int ra0 = (int)a->ranks[k], ra1 = (int)a->ranks[k + 1], rb0 = (int)b->ranks[k], rb1 = (int)b->ranks[k + 1];
+    hipError_t e;
+    if (s.kind == K_HAD) {
+      if (a->dtype == QTT_F64)
+        e = contract_hadamard<double>(strm, (const double*)a->cores[k], ra0, s.d[k], ra1, (const double*)b->cores[k],
+                                      rb0, rb1, (double*)c->cores[k]);
+      else
+        e = contract_hadamard<float>(strm, (const float*)a->cores[k], ra0, s.d[k], ra1, (const float*)b->cores[k],
+                                     rb0, rb1, (float*)c->cores[k]);
+    } else {
+      if (a->dtype == QTT_F64)
+        e = contract_mpo<double>(strm, (const double*)a->cores[k], ra0, s.d[k], s.dj[k], ra1,
+                                 (const double*)b->cores[k], rb0, rb1, (double*)c->cores[k]);
+      else
+        e = contract_mpo<float>(strm, (const float*)a->cores[k], ra0, s.d[k], s.dj[k], ra1, (const float*)b->cores[k],
+                                rb0, rb1, (float*)c->cores[k]);
+    }
+    if (e != hipSuccess) return QTT_ERR_HIP;
+  }
+  return QTT_OK;
+}
+
+int qtt_orthogonalize(qtt_handle h, qtt_tt* t, double* norm_host, void* ws, size_t ws_bytes, void* stream) {
+  if (!h || !norm_host) return QTT_ERR_ARG;
+  int st = check_tt(t, 1);
+  if (st) return st;
+  if (t->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  Shape s;
+  shape_from_tt(t, s);
+  Plan P;
+  if ((st = make_plan(s, 0, P))) return st;
+  if (!ws || ws_bytes < ws_bytes_of(P)) return QTT_ERR_WORKSPACE;
+  Scoped sc(h->device);
+  Sweep w{h, (hipStream_t)stream, align_ws(ws), &s, &P, QTT_GEMM_FP64};
+  if ((st = qr_sweep(w, t, nullptr, nullptr))) return st;
+  const int n = s.n;
+  double* Z = w.ws + P.offZ;
+  // core k = Q_k (explicit): Q_k [I; 0]
+  for (int k = 0; k + 1 < n; ++k) {
+    const int m = (int)P.m[k], q = (int)P.rho[k + 1];
+    QTT_HIP(set_eye_rect(w.st, Z, m, q));
+    QTT_HIP(apply_q(w.st, w.ws + P.offM[k], m, q, s.rc[k + 1], w.ws + P.offT[k], Z, q, q, false));
+    QTT_HIP(copy_pad_rows(w.st, Z, m, q, q, (double*)t->cores[k], m, q));
+  }
+  QTT_HIP(copy_pad_rows(w.st, w.ws + P.offCenter, (int)(P.rho[n - 1] * s.d[n - 1]), 1, 1,
+                        (double*)t->cores[n - 1], (int)(P.rho[n - 1] * s.d[n - 1]), 1));
+  QTT_HIP(hipMemcpyAsync(h->pin_dbl, w.ws + P.offNorm, sizeof(double), hipMemcpyDeviceToHost, w.st));
+  QTT_HIP(hipStreamSynchronize(w.st));
+  *norm_host = h->pin_dbl[0];
+  if (!std::isfinite(*norm_host)) return QTT_ERR_NONFINITE;
+  for (int k = 1; k < n; ++k) t->ranks[k] = P.rho[k];
+  return QTT_OK;
+}
+
+static int round_common(qtt_handle h, const Shape& s, const qtt_tt* t, const qtt_tt* a, const qtt_tt* b,
+                        qtt_tt* out, double rel_tol, int64_t max_rank, int prec, qtt_round_info* info, void* ws,
+                        size_t ws_bytes, void* stream) {
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return QTT_ERR_ARG;
+  if (prec < QTT_GEMM_FP64 || prec > QTT_GEMM_BF16X6) return QTT_ERR_ARG;
+  Plan P;
+  int st = make_plan(s, max_rank, P);
+  if (st) return st;
+  if (!ws || ws_bytes < ws_bytes_of(P)) return QTT_ERR_WORKSPACE;
+  Scoped sc(h->device);
+  Sweep w{h, (hipStream_t)stream, align_ws(ws), &s, &P, prec};
+  if ((st = qr_sweep(w, t, a, b))) return st;
+  std::vector<long> newr;
+  if ((st = svd_sweep(w, out, rel_tol, max_rank, info, newr))) return st;
+  out->ranks[0] = 1;
+  out->ranks[s.n] = 1;
+  for (int k = 1; k < s.n; ++k) out->ranks[k] = newr[k];
+  return QTT_OK;
+}
+
+int qtt_round(qtt_handle h, qtt_tt* t, double rel_tol, int64_t max_rank, int prec, qtt_round_info* info, void* ws,
+              size_t ws_bytes, void* stream) {
+  if (!h) return QTT_ERR_ARG;
+  int st = check_tt(t, 1);
+  if (st) return st;
+  if (t->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  Shape s;
+  shape_from_tt(t, s);
+  return round_common(h, s, t, nullptr, nullptr, t, rel_tol, max_rank, prec, info, ws, ws_bytes, stream);
+}
+
+int qtt_contract_round(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* out,
+                       double rel_tol, int64_t max_rank, int prec, qtt_round_info* info, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (!h) return QTT_ERR_ARG;
+  Shape s;
+  int st = shape_from_pair(spec, a, b, s);
+  if (st) return st;
+  if (a->dtype != QTT_F64 || b->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  if (!out || !out->ranks || !out->cores || out->n != a->n || out->legs != 1) return QTT_ERR_ARG;
+  if (out->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  for (int k = 0; k < out->n; ++k)
+    if (!out->cores[k]) return QTT_ERR_ARG;
+  return round_common(h, s, nullptr, a, b, out, rel_tol, max_rank, prec, info, ws, ws_bytes, stream);
+}
+
+int qtt_inner(qtt_handle h, const qtt_tt* a, const qtt_tt* b, double* out_host, void* ws, size_t ws_bytes,
+              void* stream) {
+  if (!h || !out_host) return QTT_ERR_ARG;
+  int st;
+  if ((st = check_tt(a, 1)) || (st = check_tt(b, 1))) return st;
+  if ((st = same_layout(a, b))) return st;
+  const size_t need = (size_t)inner_plan(a, b).total * 8 + 256;
+  if (!ws || ws_bytes < need) return QTT_ERR_WORKSPACE;
+  Scoped sc(h->device);
+  if (a->dtype == QTT_F64) return inner_impl<double>(h, a, b, out_host, ws, (hipStream_t)stream);
+  return inner_impl<float>(h, a, b, out_host, ws, (hipStream_t)stream);
+}
+
+int qtt_inner_backward(qtt_handle h, const qtt_tt* a, const qtt_tt* b, double g, qtt_tt* da, qtt_tt* db, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (!h || (!da && !db)) return QTT_ERR_ARG;
+  int st;
+  if ((st = check_tt(a, 1)) || (st = check_tt(b, 1))) return st;
+  if ((st = same_layout(a, b))) return st;
+  if (da) {
+    if ((st = check_tt(da, 1))) return st;
+    if ((st = same_layout(a, da))) return st;
+    for (int k = 0; k <= a->n; ++k)
+      if (da->ranks[k] != a->ranks[k]) return QTT_ERR_SHAPE;
+  }
+  if (db) {
+    if ((st = check_tt(db, 1))) return st;
+    if ((st = same_layout(b, db))) return st;
+    for (int k = 0; k <= b->n; ++k)
+      if (db->ranks[k] != b->ranks[k]) return QTT_ERR_SHAPE;
+  }
+  const size_t need = (size_t)env_plan(a, b).total * 8 + 256;
+  if (!ws || ws_bytes < need) return QTT_ERR_WORKSPACE;
+  Scoped sc(h->device);
+  if (a->dtype == QTT_F64) return inner_backward_impl<double>(a, b, g, da, db, ws, (hipStream_t)stream);
+  return inner_backward_impl<float>(a, b, g, da, db, ws, (hipStream_t)stream);
+}
+
+int qtt_contract_backward(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt* dc,
+                          qtt_tt* da, qtt_tt* db, void* ws, size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (!h || (!da && !db)) return QTT_ERR_ARG;
+  Shape s;
+  int st = shape_from_pair(spec, a, b, s);
+  if (st) return st;
+  if ((st = check_tt(dc, 1))) return st;
+  if (dc->n != a->n || dc->dtype != a->dtype || b->dtype != a->dtype) return QTT_ERR_SHAPE;
+  for (int k = 0; k <= a->n; ++k)
+    if (dc->ranks[k] != a->ranks[k] * b->ranks[k]) return QTT_ERR_SHAPE;
+  if (da && (da->n != a->n || da->dtype != a->dtype)) return QTT_ERR_SHAPE;
+  if (db && (db->n != b->n || db->dtype != b->dtype)) return QTT_ERR_SHAPE;
+  Scoped sc(h->device);
+  hipStream_t strm = (hipStream_t)stream;
+  const bool mpo = s.kind == K_MPO;
+  for (int k = 0; k < a->n; ++k) {
+    const int ra0 = (int)a->ranks[k], ra1 = (int)a->ranks[k + 1], rb0 = (int)b->ranks[k], rb1 = (int)b->ranks[k + 1];
+    hipError_t e = hipSuccess;
+    if (db) {
+      if (a->dtype == QTT_F64)
+        e = contract_backward_x<double>(strm, mpo, (const double*)a->cores[k], ra0, s.d[k], s.dj[k], ra1,
+                                        (const double*)dc->cores[k], rb0, rb1, (double*)db->cores[k]);
+      else
+        e = contract_backward_x<float>(strm, mpo, (const float*)a->cores[k], ra0, s.d[k], s.dj[k], ra1,
+                                       (const float*)dc->cores[k], rb0, rb1, (float*)db->cores[k]);
+      if (e != hipSuccess) return QTT_ERR_HIP;
+    }
+    if (da) {
+      if (a->dtype == QTT_F64)
+        e = contract_backward_w<double>(strm, mpo, (const double*)b->cores[k], rb0, s.dj[k], rb1,
+                                        (const double*)dc->cores[k], ra0, s.d[k], ra1, (double*)da->cores[k]);
+      else
+        e = contract_backward_w<float>(strm, mpo, (const float*)b->cores[k], rb0, s.dj[k], rb1,
+                                       (const float*)dc->cores[k], ra0, s.d[k], ra1, (float*)da->cores[k]);
+      if (e != hipSuccess) return QTT_ERR_HIP;
+    }
+  }
+  return QTT_OK;
+}
+
+}  // extern "C"

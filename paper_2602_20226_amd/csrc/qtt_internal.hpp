@@ -1,0 +1,102 @@
+// Host-side declarations of the kernel launchers (internal to libqtt).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace qtt {
+
+// ---------------------------------------------------------------- GEMM
+// Row-major C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C.
+// op(A) = A (lda >= K) or A^T (A stored K x M, lda >= M); same for B.
+// Batched with element strides sA, sB, sC.  FP64 on MFMA f64 16x16x4.
+hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+                    const double* A, long lda, long sA, const double* B, long ldb, long sB,
+                    double beta, double* C, long ldc, long sC, int batch);
+hipError_t gemm_f32(hipStream_t s, bool ta, bool tb, int M, int N, int K, float alpha,
+                    const float* A, long lda, long sA, const float* B, long ldb, long sB,
+                    float beta, float* C, long ldc, long sC, int batch);
+// FP64 operands, each split into three bf16 pieces; `nprod` = 3 or 6 split
+// products accumulated in FP32 on MFMA bf16; result stored as FP64.
+hipError_t gemm_bf16split(hipStream_t s, bool ta, bool tb, int M, int N, int K,
+                          const double* A, long lda, const double* B, long ldb,
+                          double* C, long ldc, int nprod);
+// FP64 operands rounded to FP32, FP32 MFMA with FP32 accumulation, FP64 result.
+hipError_t gemm_f64_via_f32(hipStream_t s, bool ta, bool tb, int M, int N, int K,
+                            const double* A, long lda, const double* B, long ldb,
+                            double* C, long ldc);
+
+// ---------------------------------------------------------------- contraction
+template <typename T>
+hipError_t contract_hadamard(hipStream_t s, const T* A, int ra0, int d, int ra1,
+                             const T* B, int rb0, int rb1, T* C);
+template <typename T>
+hipError_t contract_mpo(hipStream_t s, const T* W, int rw0, int di, int dj, int rw1,
+                        const T* X, int rx0, int rx1, T* C);
+// M[(a,i),(mu',nu')] = sum_{mu,j} Y[a,mu,j,nu'] W[mu,i,j,mu']  (FP64)
+hipError_t bond_mpo_apply(hipStream_t s, const double* Y, int rho, int rw0, int dj, int rx1,
+                          const double* W, int di, int rw1, double* M);
+// M[(a,i),(mu',nu')] = sum_mu Y[a,mu,i,nu'] A[mu,i,mu']  (FP64, Hadamard factored)
+hipError_t bond_hadamard_apply(hipStream_t s, const double* Y, int rho, int ra0, int d, int rb1,
+                               const double* A, int ra1, double* M);
+template <typename T>
+hipError_t contract_backward_x(hipStream_t s, bool mpo, const T* W, int rw0, int di, int dj,
+                               int rw1, const T* dC, int rx0, int rx1, T* dX);
+template <typename T>
+hipError_t contract_backward_w(hipStream_t s, bool mpo, const T* X, int rx0, int dj, int rx1,
+                               const T* dC, int rw0, int di, int rw1, T* dW);
+
+// ---------------------------------------------------------------- QR
+constexpr int QR_PB = 16;  // panel width (reflectors per T block)
+// Blocked Householder QR of the m x n row-major matrix A (in place).  Reflector
+// vectors below the diagonal, R on and above; T blocks (QR_PB x QR_PB each,
+// one per panel) in Tbuf.  Supports m <= 4096.
+hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf);
+// Y[r0.., c0..c1) <- (I - V op(T) V^T) ... for every panel: Q*Y (trans=false,
+// panels in reverse order) or Q^T*Y (trans=true, forward order).  Y has m rows.
+hipError_t apply_q(hipStream_t s, const double* A, int m, int kref, long lda, const double* Tbuf,
+                   double* Y, int ncols, long ldy, bool trans);
+// R = upper trapezoid of A[0:kr, 0:n] (zeros below the diagonal) into Rout (ld n).
+hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, double* Rout);
+
+// ---------------------------------------------------------------- SVD
+// One-sided Jacobi on the rows of X (p x L, row-major, ld L): on return the
+// rows are mutually orthogonal (X <- Z^T X, Z orthogonal, not formed).
+// counter: 8 unsigned of device scratch (cleared by the routine).  Sweeps
+// used go to *sweeps_dev.
+hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
+                       int* sweeps_dev);
+// sigma_i = ||X_i||, perm = argsort descending (stable on ties).
+hipError_t row_norms_sorted(hipStream_t s, const double* X, int p, int L, double* sig_sorted,
+                            int* perm);
+
+// ---------------------------------------------------------------- small kernels
+hipError_t fill_f64(hipStream_t s, double* p, double v, long n);
+hipError_t fill_u32(hipStream_t s, unsigned* p, unsigned v, long n);
+hipError_t fill_f32(hipStream_t s, float* p, float v, long n);
+hipError_t set_identity(hipStream_t s, double* Z, int p);
+hipError_t set_eye_rect(hipStream_t s, double* Z, int m, int q);
+hipError_t copy_pad_rows(hipStream_t s, const double* src, int rows, int cols, long lds,
+                         double* dst, int rows_out, long ldd);
+hipError_t frob_norm(hipStream_t s, const double* x, long n, double* out);
+hipError_t transpose(hipStream_t s, const double* A, int rows, int cols, long lda, double* B, long ldb);
+
+struct TruncOut {
+  int rank;
+  int capped;
+  double tail_r;
+  double tail_rm1;
+  double norm;
+  double delta;
+};
+// Rank decision at one bond from sorted singular values (device).
+hipError_t truncate_decide(hipStream_t s, const double* sig, int cnt, const double* norm_dev,
+                           double rel_tol, int nbonds, long max_rank, TruncOut* out_dev);
+// Rows perm[0:r] of X scaled to unit norm -> out (r x L); r read from t on device,
+// rmax_host bounds the launch.
+hipError_t gather_rows_normalized(hipStream_t s, const double* X, int L, const int* perm, const double* sig,
+                                  const TruncOut* t, double* out, long ldo, int rmax_host);
+int qr_num_panels(int m, int n);
+
+}  // namespace qtt

@@ -1,0 +1,245 @@
+// One-sided Jacobi SVD and the device-side truncation decision (FP64).
+//
+// jacobi_rows orthogonalises the rows of X (p x L) by plane rotations,
+// X <- Z^T X with Z orthogonal.  Afterwards the rows of X are Sigma V^T up
+// to their order: normalising them gives the right singular vectors.  Z is
+// not accumulated: the caller forms U Sigma = X_orig V with one GEMM, which
+// keeps U Sigma V^T = X_orig V V^T exact up to the orthogonality of V
+// (a product of thousands of rounded rotations would drift from orthogonal).
+//
+// Parallel ordering: rows are grouped into blocks of 8; a persistent grid of
+// workgroups (one per block pair) runs the round-robin tournament over blocks,
+// with a grid barrier between rounds.  For its pair of blocks a workgroup
+// stages the 16 rows in LDS and runs one full inner sweep of plane rotations
+// over them (15 rounds of 8 disjoint pairs, one wave per pair).  A rotation of
+// rows a, c is skipped when |a.c| <= tol * ||a|| ||c|| with
+// tol = sqrt(L) * eps, and the iteration stops after the first sweep without
+// any rotation.
+#include "qtt_device.hpp"
+#include "qtt_internal.hpp"
+
+namespace qtt {
+
+namespace {
+
+constexpr int JB = 8;        // rows per block
+constexpr int JNT = 512;     // threads: one wave per row pair of the inner sweep
+
+__device__ __forceinline__ int rr_item(int pos, int round, int n) {
+  // circle method: position 0 fixed, the others rotate
+  return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (n - 1));
+}
+
+__global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, int L,
+                                                unsigned* __restrict__ ctr, int max_sweeps, int* sweeps_out,
+                                                double tol) {
+  extern __shared__ double sh[];  // [16][L]
+  __shared__ unsigned s_tot;
+  const int W = L;
+  const int nblk = (p + JB - 1) / JB;
+  const int nb2 = nblk + (nblk & 1);
+  const int npairs = nb2 / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  unsigned local_rot = 0;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    for (int round = 0; round < nb2 - 1; ++round) {
+      for (int pair = blockIdx.x; pair < npairs; pair += gridDim.x) {
+        const int b0 = rr_item(pair, round, nb2);
+        const int b1 = rr_item(nb2 - 1 - pair, round, nb2);
+        // stage rows: local row t < 8 -> block b0 row t, t >= 8 -> block b1 row t-8
+        for (int e = tid; e < 16 * W; e += JNT) {
+          const int t = e / W, c = e % W;
+          const int gr = (t < 8 ? b0 : b1) * JB + (t & 7);
+          double v = 0.0;
+          if (gr < p) v = X[(long)gr * L + c];
+          sh[t * W + c] = v;
+        }
+        __syncthreads();
+        for (int ir = 0; ir < 15; ++ir) {
+          const int ra = rr_item(wave, ir, 16);
+          const int rc = rr_item(15 - wave, ir, 16);
+          double* xa = sh + ra * W;
+          double* xc = sh + rc * W;
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int c = lane; c < L; c += 64) {
+            const double u = xa[c], w = xc[c];
+            al += u * u;
+            be += w * w;
+            ga += u * w;
+          }
+          al = wave_sum(al);
+          be = wave_sum(be);
+          ga = wave_sum(ga);
+          if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t);
+            const double sn = cs * t;
+            for (int c = lane; c < W; c += 64) {
+              const double u = xa[c], w = xc[c];
+              xa[c] = cs * u - sn * w;
+              xc[c] = sn * u + cs * w;
+            }
+            if (lane == 0) ++local_rot;
+          }
+          __syncthreads();
+        }
+        for (int e = tid; e < 16 * W; e += JNT) {
+          const int t = e / W, c = e % W;
+          const int gr = (t < 8 ? b0 : b1) * JB + (t & 7);
+          if (gr < p) X[(long)gr * L + c] = sh[t * W + c];
+        }
+        __syncthreads();
+      }
+      grid_barrier(ctr, gridDim.x);
+    }
+    // sweep bookkeeping: counter (sweep % 3) collects this sweep's rotations
+    if (lane == 0 && local_rot) atomicAdd(&ctr[2 + (sweep % 3)], local_rot);
+    local_rot = 0;
+    grid_barrier(ctr, gridDim.x);
+    if (tid == 0) {
+      s_tot = __hip_atomic_load(&ctr[2 + (sweep % 3)], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      if (blockIdx.x == 0)
+        __hip_atomic_store(&ctr[2 + ((sweep + 2) % 3)], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (s_tot == 0) {
+      ++sweep;
+      break;
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) sweeps_out[0] = sweep;
+}
+
+// sigma_i = ||X_i||, perm sorts them descending (ties by index).
+__global__ __launch_bounds__(1024) void k_norms_sort(const double* __restrict__ X, int p, int L,
+                                                     double* __restrict__ sig_sorted, int* __restrict__ perm) {
+  extern __shared__ double sg[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < p; i += 16) {
+    double s = 0.0;
+    for (int c = lane; c < L; c += 64) {
+      const double v = X[(long)i * L + c];
+      s += v * v;
+    }
+    s = wave_sum(s);
+    if (lane == 0) sg[i] = sqrt(s);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < p; i += 1024) {
+    const double si = sg[i];
+    int pos = 0;
+    for (int j = 0; j < p; ++j) {
+      const double sj = sg[j];
+      pos += (sj > si) || (sj == si && j < i);
+    }
+    perm[pos] = i;
+    sig_sorted[pos] = si;
+  }
+}
+
+__global__ void k_truncate(const double* __restrict__ sig, int cnt, const double* __restrict__ norm_dev,
+                           double rel_tol, int nbonds, long max_rank, TruncOut* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double nrm = norm_dev[0];
+  const double delta = (nbonds > 0) ? rel_tol * nrm / sqrt((double)nbonds) : 0.0;
+  // tail2(r) = sum_{i >= r} sigma_i^2, accumulated from the smallest value upwards
+  int r = cnt;
+  double acc = 0.0;
+  double tail_r = 0.0, tail_rm1 = 0.0;
+  // walk r from cnt down to 1; the smallest admissible r is the last one found
+  for (int cand = cnt; cand >= 1; --cand) {
+    // acc = tail2(cand)
+    if (sqrt(acc) <= delta) {
+      r = cand;
+    } else {
+      break;
+    }
+    acc += sig[cand - 1] * sig[cand - 1];
+  }
+  int capped = 0;
+  if (max_rank > 0 && r > max_rank) {
+    r = (int)max_rank;
+    capped = 1;
+  }
+  if (r < 1) r = 1;
+  if (r > cnt) r = cnt;
+  double t2 = 0.0;
+  for (int i = cnt - 1; i >= r; --i) t2 += sig[i] * sig[i];
+  tail_r = sqrt(t2);
+  tail_rm1 = sqrt(t2 + sig[r - 1] * sig[r - 1]);
+  out->rank = r;
+  out->capped = capped;
+  out->tail_r = tail_r;
+  out->tail_rm1 = tail_rm1;
+  out->norm = nrm;
+  out->delta = delta;
+}
+
+__global__ void k_gather_rows(const double* __restrict__ X, int L, const int* __restrict__ perm,
+                              const double* __restrict__ sig, const TruncOut* __restrict__ t,
+                              double* __restrict__ out, long ldo) {
+  const int r = t->rank;
+  const long total = (long)r * L;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / L), c = (int)(e % L);
+    const double s = sig[j];
+    out[(long)j * ldo + c] = (s > 0.0) ? X[(long)perm[j] * L + c] / s : 0.0;
+  }
+}
+
+inline int gsz(long n) {
+  long g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > (1 << 20)) g = 1 << 20;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
+                       int* sweeps_dev) {
+  if (p <= 0 || L <= 0) return hipSuccess;
+  const size_t shmem = (size_t)16 * L * sizeof(double);
+  if (shmem > 160 * 1024 - 1024) return hipErrorInvalidValue;
+  hipError_t e = fill_u32(s, counter, 0u, 8);
+  if (e != hipSuccess) return e;
+  const int nblk = (p + JB - 1) / JB;
+  const int npairs = (nblk + (nblk & 1)) / 2;
+  int grid = npairs < 1 ? 1 : npairs;
+  if (grid > 256) grid = 256;
+  static bool attr_set = false;
+  if (!attr_set) {
+    e = hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  // tolerance on |a.c| / (||a|| ||c||)
+  const double tol = 2.220446049250313e-16 * sqrt((double)L);
+  void* args[] = {&X, &p, &L, &counter, &max_sweeps, &sweeps_dev, (void*)&tol};
+  return hipLaunchCooperativeKernel((const void*)k_jacobi, dim3(grid), dim3(JNT), args, shmem, s);
+}
+
+hipError_t row_norms_sorted(hipStream_t s, const double* X, int p, int L, double* sig_sorted, int* perm) {
+  if (p <= 0) return hipSuccess;
+  const size_t shmem = (size_t)p * sizeof(double);
+  if (shmem > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_norms_sort, dim3(1), dim3(1024), shmem, s, X, p, L, sig_sorted, perm);
+  return hipGetLastError();
+}
+
+hipError_t truncate_decide(hipStream_t s, const double* sig, int cnt, const double* norm_dev, double rel_tol,
+                           int nbonds, long max_rank, TruncOut* out_dev) {
+  hipLaunchKernelGGL(k_truncate, dim3(1), dim3(64), 0, s, sig, cnt, norm_dev, rel_tol, nbonds, max_rank, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t gather_rows_normalized(hipStream_t s, const double* X, int L, const int* perm, const double* sig,
+                                  const TruncOut* t, double* out, long ldo, int rmax_host) {
+  hipLaunchKernelGGL(k_gather_rows, dim3(gsz((long)rmax_host * L)), dim3(256), 0, s, X, L, perm, sig, t, out, ldo);
+  return hipGetLastError();
+}
+
+
+}  // namespace qtt

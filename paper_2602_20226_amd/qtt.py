@@ -1,0 +1,430 @@
+"""Python binding of libqtt (ctypes).
+
+Argument marshalling only: every step of the contraction, rounding and
+inner-product path runs in the HIP kernels of libqtt.so.  PyTorch provides
+device buffers (torch.empty on a ROCm device) and the current stream.
+The names follow include/qtt.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqtt.so")
+
+QTT_OK = 0
+STATUS = {
+    0: "QTT_OK", -1: "QTT_ERR_ARG", -2: "QTT_ERR_SPEC", -3: "QTT_ERR_SHAPE", -4: "QTT_ERR_DTYPE",
+    -5: "QTT_ERR_WORKSPACE", -6: "QTT_ERR_NODEVICE", -7: "QTT_ERR_HIP", -8: "QTT_ERR_NONFINITE",
+    -9: "QTT_ERR_NOCONV", -10: "QTT_ERR_UNSUPPORTED",
+}
+F64, F32 = 0, 1
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
+OP_CONTRACT, OP_ORTHOGONALIZE, OP_ROUND, OP_CONTRACT_ROUND, OP_INNER, OP_INNER_BACKWARD, OP_CONTRACT_BACKWARD = range(7)
+
+EXPORTS = [
+    "qtt_create", "qtt_destroy", "qtt_status_string", "qtt_workspace_size", "qtt_contract",
+    "qtt_orthogonalize", "qtt_round", "qtt_contract_round", "qtt_inner", "qtt_inner_backward",
+    "qtt_contract_backward",
+]
+
+
+class QttError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({_status_string(status)})")
+
+
+class TT(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32),
+        ("legs", C.c_int32),
+        ("phys", C.POINTER(C.c_int32)),
+        ("ranks", C.POINTER(C.c_int64)),
+        ("cores", C.POINTER(C.c_void_p)),
+        ("dtype", C.c_int32),
+    ]
+
+
+class RoundInfoC(C.Structure):
+    _fields_ = [
+        ("norm", C.c_double),
+        ("delta", C.c_double),
+        ("err_bound", C.c_double),
+        ("tail", C.POINTER(C.c_double)),
+        ("margin_lo", C.POINTER(C.c_double)),
+        ("margin_hi", C.POINTER(C.c_double)),
+        ("maxrank_hit", C.POINTER(C.c_uint8)),
+        ("sigma", C.POINTER(C.c_double)),
+        ("sigma_ld", C.c_int64),
+        ("jacobi_sweeps_max", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib_available() -> bool:
+    return os.path.exists(LIB_PATH)
+
+
+def load_library():
+    """Load libqtt.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libqtt.so not built at {LIB_PATH}; run paper_2602_20226_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    P = C.POINTER
+    L.qtt_create.argtypes = [P(vp), C.c_int]
+    L.qtt_destroy.argtypes = [vp]
+    L.qtt_status_string.argtypes = [C.c_int]
+    L.qtt_status_string.restype = C.c_char_p
+    L.qtt_workspace_size.argtypes = [vp, C.c_int, C.c_char_p, P(TT), P(TT), C.c_int64, C.c_int, P(C.c_size_t)]
+    L.qtt_contract.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), vp, C.c_size_t, vp]
+    L.qtt_orthogonalize.argtypes = [vp, P(TT), P(C.c_double), vp, C.c_size_t, vp]
+    L.qtt_round.argtypes = [vp, P(TT), C.c_double, C.c_int64, C.c_int, P(RoundInfoC), vp, C.c_size_t, vp]
+    L.qtt_contract_round.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_double, C.c_int64, C.c_int,
+                                     P(RoundInfoC), vp, C.c_size_t, vp]
+    L.qtt_inner.argtypes = [vp, P(TT), P(TT), P(C.c_double), vp, C.c_size_t, vp]
+    L.qtt_inner_backward.argtypes = [vp, P(TT), P(TT), C.c_double, P(TT), P(TT), vp, C.c_size_t, vp]
+    L.qtt_contract_backward.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), P(TT), P(TT), vp, C.c_size_t, vp]
+    for name in EXPORTS:
+        if name != "qtt_status_string":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _status_string(st: int) -> str:
+    try:
+        return load_library().qtt_status_string(st).decode()
+    except Exception:
+        return ""
+
+
+def _check(st: int, where: str):
+    if st != QTT_OK:
+        raise QttError(st, where)
+
+
+class Handle:
+    """Owns a qtt_handle bound to one gfx950 device."""
+
+    def __init__(self, device: int = 0):
+        L = load_library()
+        self._h = C.c_void_p()
+        _check(L.qtt_create(C.byref(self._h), device), "qtt_create")
+        self.device = device
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().qtt_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles = {}
+
+
+def handle(device: Optional[int] = None) -> Handle:
+    if device is None:
+        device = torch.cuda.current_device()
+    h = _handles.get(device)
+    if h is None:
+        h = Handle(device)
+        _handles[device] = h
+    return h
+
+
+@dataclass
+class TTView:
+    """ctypes view of a list of device core tensors (kept alive by this object)."""
+    cores: List[torch.Tensor]
+    legs: int
+    ranks_override: Optional[Sequence[int]] = None
+    phys_override: Optional[Sequence[int]] = None
+    struct: TT = field(init=False)
+
+    def __post_init__(self):
+        n = len(self.cores)
+        self._phys = (C.c_int32 * (n * self.legs))()
+        self._ranks = (C.c_int64 * (n + 1))()
+        self._ptrs = (C.c_void_p * n)()
+        dt = self.cores[0].dtype
+        for k, c in enumerate(self.cores):
+            if c.device.type != "cuda":
+                raise ValueError("cores must be device tensors")
+            if c.dtype != dt:
+                raise ValueError("mixed core dtypes")
+            if not c.is_contiguous():
+                raise ValueError("cores must be contiguous")
+            if self.phys_override is not None:
+                self._phys[k] = int(self.phys_override[k])
+            elif self.legs == 1:
+                self._phys[k] = c.shape[1]
+            else:
+                self._phys[2 * k] = c.shape[1]
+                self._phys[2 * k + 1] = c.shape[2]
+            self._ptrs[k] = c.data_ptr()
+        if self.ranks_override is not None:
+            for k, r in enumerate(self.ranks_override):
+                self._ranks[k] = int(r)
+        else:
+            self._ranks[0] = self.cores[0].shape[0]
+            for k, c in enumerate(self.cores):
+                self._ranks[k + 1] = c.shape[-1]
+        dtype = F64 if dt == torch.float64 else F32 if dt == torch.float32 else None
+        if dtype is None:
+            raise ValueError(f"unsupported dtype {dt}")
+        self.struct = TT(n, self.legs, self._phys, self._ranks, self._ptrs, dtype)
+
+    def ranks(self) -> List[int]:
+        return [int(self._ranks[k]) for k in range(len(self.cores) + 1)]
+
+
+def _stream_ptr():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _legs(spec: str) -> int:
+    s = spec.replace(" ", "")
+    if s == "i,i->i":
+        return 1
+    if s == "ij,j->i":
+        return 2
+    raise ValueError(f"unsupported spec {spec!r}")
+
+
+def contract(spec: str, a: Sequence[torch.Tensor], b: Sequence[torch.Tensor]) -> List[torch.Tensor]:
+    """Exact core-by-core einsum; returns the contracted cores (device tensors)."""
+    L = load_library()
+    h = handle(a[0].device.index)
+    va, vb = TTView(list(a), _legs(spec)), TTView(list(b), 1)
+    dev = a[0].device
+    out = []
+    for ca, cb in zip(a, b):
+        shp = (ca.shape[0] * cb.shape[0], ca.shape[1], ca.shape[-1] * cb.shape[-1])
+        out.append(torch.empty(shp, dtype=ca.dtype, device=dev))
+    vc = TTView(out, 1)
+    _check(L.qtt_contract(h.ptr, spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(vc.struct),
+                          None, 0, _stream_ptr()), "qtt_contract")
+    return out
+
+
+def inner(a: Sequence[torch.Tensor], b: Sequence[torch.Tensor]) -> float:
+    L = load_library()
+    h = handle(a[0].device.index)
+    va, vb = TTView(list(a), 1), TTView(list(b), 1)
+    nb = C.c_size_t()
+    _check(L.qtt_workspace_size(h.ptr, OP_INNER, None, C.byref(va.struct), C.byref(vb.struct), 0, 0,
+                                C.byref(nb)), "qtt_workspace_size")
+    ws = _workspace(nb.value, a[0].device)
+    out = C.c_double()
+    _check(L.qtt_inner(h.ptr, C.byref(va.struct), C.byref(vb.struct), C.byref(out), C.c_void_p(ws.data_ptr()),
+                       ws.numel(), _stream_ptr()), "qtt_inner")
+    return out.value
+
+
+def inner_backward(a, b, g: float = 1.0, want_a: bool = True, want_b: bool = False):
+    L = load_library()
+    h = handle(a[0].device.index)
+    va, vb = TTView(list(a), 1), TTView(list(b), 1)
+    da = [torch.empty_like(c) for c in a] if want_a else None
+    db = [torch.empty_like(c) for c in b] if want_b else None
+    vda = TTView(da, 1) if da else None
+    vdb = TTView(db, 1) if db else None
+    nb = C.c_size_t()
+    _check(L.qtt_workspace_size(h.ptr, OP_INNER_BACKWARD, None, C.byref(va.struct), C.byref(vb.struct), 0, 0,
+                                C.byref(nb)), "qtt_workspace_size")
+    ws = _workspace(nb.value, a[0].device)
+    _check(L.qtt_inner_backward(h.ptr, C.byref(va.struct), C.byref(vb.struct), float(g),
+                                C.byref(vda.struct) if vda else None, C.byref(vdb.struct) if vdb else None,
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr()), "qtt_inner_backward")
+    return da, db
+
+
+def contract_backward(spec: str, a, b, dc, want_a: bool = False, want_b: bool = True):
+    L = load_library()
+    h = handle(a[0].device.index)
+    va, vb, vdc = TTView(list(a), _legs(spec)), TTView(list(b), 1), TTView(list(dc), 1)
+    da = [torch.empty_like(c) for c in a] if want_a else None
+    db = [torch.empty_like(c) for c in b] if want_b else None
+    vda = TTView(da, _legs(spec)) if da else None
+    vdb = TTView(db, 1) if db else None
+    _check(L.qtt_contract_backward(h.ptr, spec.encode(), C.byref(va.struct), C.byref(vb.struct),
+                                   C.byref(vdc.struct), C.byref(vda.struct) if vda else None,
+                                   C.byref(vdb.struct) if vdb else None, None, 0, _stream_ptr()),
+           "qtt_contract_backward")
+    return da, db
+
+
+@dataclass
+class RoundResult:
+    cores: List[torch.Tensor]
+    ranks: List[int]
+    norm: float
+    delta: float
+    err_bound: float
+    tails: List[float]
+    margin_lo: List[float]
+    margin_hi: List[float]
+    maxrank_hit: List[bool]
+    sigmas: Optional[List[List[float]]]
+    jacobi_sweeps_max: int
+
+
+def rank_bounds(rc: Sequence[int], d: Sequence[int], max_rank: int) -> List[int]:
+    """Upper bounds of the rounded ranks (what output buffers must hold)."""
+    n = len(d)
+    rho = [1] * (n + 1)
+    for k in range(n - 1):
+        rho[k + 1] = min(rho[k] * d[k], rc[k + 1])
+    out = [1] * (n + 1)
+    right = 1
+    for k in range(n - 1, 0, -1):
+        right = min(right * d[k], 1 << 40)
+        bnd = min(rho[k], right)
+        if max_rank and max_rank > 0:
+            bnd = min(bnd, max_rank)
+        out[k] = max(bnd, 1)
+    return out
+
+
+class _Info:
+    def __init__(self, n: int, sigma_ld: int = 0):
+        m = max(n - 1, 1)
+        self.tail = (C.c_double * m)()
+        self.mlo = (C.c_double * m)()
+        self.mhi = (C.c_double * m)()
+        self.hit = (C.c_uint8 * m)()
+        self.sigma_ld = sigma_ld
+        self.sigma = (C.c_double * (m * sigma_ld))() if sigma_ld > 0 else None
+        self.c = RoundInfoC()
+        self.c.tail = self.tail
+        self.c.margin_lo = self.mlo
+        self.c.margin_hi = self.mhi
+        self.c.maxrank_hit = self.hit
+        self.c.sigma = self.sigma if self.sigma is not None else None
+        self.c.sigma_ld = sigma_ld
+
+    def result(self, cores, ranks, n):
+        m = n - 1
+        sig = None
+        if self.sigma is not None:
+            sig = [[self.sigma[k * self.sigma_ld + i] for i in range(self.sigma_ld)] for k in range(m)]
+        return RoundResult(cores, ranks, self.c.norm, self.c.delta, self.c.err_bound,
+                           [self.tail[k] for k in range(m)], [self.mlo[k] for k in range(m)],
+                           [self.mhi[k] for k in range(m)], [bool(self.hit[k]) for k in range(m)], sig,
+                           self.c.jacobi_sweeps_max)
+
+
+def _views_of_compact(buffers: List[torch.Tensor], ranks: Sequence[int], d: Sequence[int]):
+    out = []
+    for k, buf in enumerate(buffers):
+        cnt = ranks[k] * d[k] * ranks[k + 1]
+        out.append(buf.reshape(-1)[:cnt].view(ranks[k], d[k], ranks[k + 1]))
+    return out
+
+
+def contract_round(spec: str, a, b, rel_tol: float, max_rank: int = 0, prec: str = "fp64",
+                   want_sigmas: bool = False, out_buffers: Optional[List[torch.Tensor]] = None,
+                   workspace: Optional[torch.Tensor] = None) -> RoundResult:
+    """Contraction + TT rounding without materialising the contracted cores."""
+    L = load_library()
+    h = handle(a[0].device.index)
+    legs = _legs(spec)
+    va, vb = TTView(list(a), legs), TTView(list(b), 1)
+    n = len(a)
+    d = [c.shape[1] for c in a]
+    rc = [x * y for x, y in zip(va.ranks(), vb.ranks())]
+    bnd = rank_bounds(rc, d, max_rank)
+    dev = a[0].device
+    if out_buffers is None:
+        out_buffers = [torch.empty(bnd[k] * d[k] * bnd[k + 1], dtype=torch.float64, device=dev) for k in range(n)]
+    vo = TTView([x.reshape(-1) for x in out_buffers], 1, ranks_override=bnd, phys_override=d)
+    nb = C.c_size_t()
+    _check(L.qtt_workspace_size(h.ptr, OP_CONTRACT_ROUND, spec.encode(), C.byref(va.struct), C.byref(vb.struct),
+                                int(max_rank), PREC[prec], C.byref(nb)), "qtt_workspace_size")
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = _workspace(nb.value, dev)
+    sig_ld = max(bnd) * 2 if want_sigmas else 0
+    if want_sigmas:
+        sig_ld = max(rc) if max(rc) < 8192 else 8192
+    info = _Info(n, sig_ld)
+    _check(L.qtt_contract_round(h.ptr, spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(vo.struct),
+                                float(rel_tol), int(max_rank), PREC[prec], C.byref(info.c),
+                                C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr()),
+           "qtt_contract_round")
+    ranks = vo.ranks()
+    cores = _views_of_compact(out_buffers, ranks, d)
+    return info.result(cores, ranks, n)
+
+
+def round_tt(cores, rel_tol: float, max_rank: int = 0, prec: str = "fp64", want_sigmas: bool = False,
+             inplace: bool = False) -> RoundResult:
+    """TT rounding of an FP64 MPS (copied unless inplace)."""
+    L = load_library()
+    h = handle(cores[0].device.index)
+    bufs = [c if inplace else c.clone() for c in cores]
+    d = [c.shape[1] for c in cores]
+    flat = [b.reshape(-1) for b in bufs]
+    v = TTView(flat, 1, ranks_override=[cores[0].shape[0]] + [c.shape[-1] for c in cores], phys_override=d)
+    nb = C.c_size_t()
+    _check(L.qtt_workspace_size(h.ptr, OP_ROUND, None, C.byref(v.struct), None, int(max_rank), PREC[prec],
+                                C.byref(nb)), "qtt_workspace_size")
+    ws = _workspace(nb.value, cores[0].device)
+    n = len(cores)
+    sig_ld = max(v.ranks()) if want_sigmas else 0
+    info = _Info(n, sig_ld)
+    _check(L.qtt_round(h.ptr, C.byref(v.struct), float(rel_tol), int(max_rank), PREC[prec], C.byref(info.c),
+                       C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr()), "qtt_round")
+    ranks = v.ranks()
+    return info.result(_views_of_compact(flat, ranks, d), ranks, n)
+
+
+def orthogonalize(cores, inplace: bool = False):
+    L = load_library()
+    h = handle(cores[0].device.index)
+    bufs = [c if inplace else c.clone() for c in cores]
+    d = [c.shape[1] for c in cores]
+    flat = [b.reshape(-1) for b in bufs]
+    v = TTView(flat, 1, ranks_override=[cores[0].shape[0]] + [c.shape[-1] for c in cores], phys_override=d)
+    nb = C.c_size_t()
+    _check(L.qtt_workspace_size(h.ptr, OP_ORTHOGONALIZE, None, C.byref(v.struct), None, 0, 0, C.byref(nb)),
+           "qtt_workspace_size")
+    ws = _workspace(nb.value, cores[0].device)
+    nrm = C.c_double()
+    _check(L.qtt_orthogonalize(h.ptr, C.byref(v.struct), C.byref(nrm), C.c_void_p(ws.data_ptr()), ws.numel(),
+                               _stream_ptr()), "qtt_orthogonalize")
+    ranks = v.ranks()
+    return _views_of_compact(flat, ranks, d), nrm.value
+
+
+def to_device(cores, device="cuda", dtype=torch.float64):
+    return [torch.as_tensor(c, dtype=dtype).contiguous().to(device) for c in cores]
+
+
+def to_host(cores):
+    return [c.detach().to("cpu").double().numpy() for c in cores]

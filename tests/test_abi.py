@@ -1,0 +1,122 @@
+"""C-ABI checks that need no GPU: exports, status codes, argument errors, planning."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2602_20226_amd import qtt as Q
+from paper_2602_20226_amd.build import LIB
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qtt.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libqtt.so not built (run __graft_entry__.build())")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qtt_[a-z_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = C.CDLL(LIB)
+    names = header_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(Q.EXPORTS)
+
+
+def test_status_strings():
+    L = Q.load_library()
+    for code in range(0, -11, -1):
+        s = L.qtt_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert L.qtt_status_string(-99).decode() == "unknown status"
+
+
+def test_create_without_gpu_or_bad_args():
+    L = Q.load_library()
+    h = C.c_void_p()
+    assert L.qtt_create(None, 0) == -1
+    st = L.qtt_create(C.byref(h), 10_000)
+    assert st == -6  # QTT_ERR_NODEVICE: no such device (none at all in the CPU container)
+    assert L.qtt_destroy(None) == -1
+
+
+def _fake_tt(ranks, phys, legs=1, null_core=False):
+    n = len(ranks) - 1
+    ph = (C.c_int32 * (n * legs))(*phys)
+    rk = (C.c_int64 * (n + 1))(*ranks)
+    ptrs = (C.c_void_p * n)(*([None] * n if null_core else [0x1000 + 64 * k for k in range(n)]))
+    t = Q.TT(n, legs, ph, rk, ptrs, Q.F64)
+    t._keep = (ph, rk, ptrs)
+    return t
+
+
+def test_null_handle_rejected_by_compute_calls():
+    L = Q.load_library()
+    a = _fake_tt([1, 2, 1], [2, 2])
+    out = C.c_double()
+    assert L.qtt_inner(None, C.byref(a), C.byref(a), C.byref(out), None, 0, None) == -1
+    assert L.qtt_contract(None, b"i,i->i", C.byref(a), C.byref(a), C.byref(a), None, 0, None) == -1
+    assert L.qtt_round(None, C.byref(a), 1e-8, 0, 0, None, None, 0, None) == -1
+
+
+def ws(op, a, b=None, spec=None, max_rank=0, prec=0):
+    L = Q.load_library()
+    nb = C.c_size_t()
+    st = L.qtt_workspace_size(None, op, spec, C.byref(a), C.byref(b) if b is not None else None, max_rank, prec,
+                              C.byref(nb))
+    return st, nb.value
+
+
+def test_workspace_planning_and_shape_errors():
+    a = _fake_tt([1, 2, 4, 2, 1], [2, 2, 2, 2])
+    st, nb = ws(Q.OP_ROUND, a)
+    assert st == 0 and nb > 0
+    st, _ = ws(Q.OP_INNER, a, a)
+    assert st == 0
+    # boundary rank must be 1
+    bad = _fake_tt([2, 2, 1], [2, 2])
+    assert ws(Q.OP_ROUND, bad)[0] == -3
+    # unsupported einsum string
+    assert ws(Q.OP_CONTRACT_ROUND, a, a, b"ij,jk->ik")[0] == -2
+    # MPO operand must have two legs
+    assert ws(Q.OP_CONTRACT_ROUND, a, a, b"ij,j->i")[0] == -3
+    # physical size mismatch in a Hadamard product
+    c = _fake_tt([1, 2, 4, 2, 1], [2, 3, 2, 2])
+    assert ws(Q.OP_CONTRACT_ROUND, a, c, b"i,i->i")[0] == -3
+    # null core pointer
+    z = _fake_tt([1, 2, 1], [2, 2], null_core=True)
+    assert ws(Q.OP_ROUND, z)[0] == -1
+
+
+def test_workspace_for_the_benchmark_shapes():
+    import qtt_inputs as I
+    from paper_2602_20226_amd.qtt import rank_bounds
+    w = I.config4()
+    ra = [1] + [c.shape[-1] for c in w.a]
+    rb = [1] + [c.shape[-1] for c in w.b]
+    n = len(w.a)
+    W = _fake_tt(ra, [2] * (2 * n), legs=2)
+    X = _fake_tt(rb, [2] * n)
+    st, nb = ws(Q.OP_CONTRACT_ROUND, W, X, b"ij,j->i", 256, 3)
+    assert st == 0
+    # QR-sweep factors (41 matrices up to 3584 x 1792) dominate: a few GB, well inside 288 GB HBM
+    assert 1e9 < nb < 1.2e10
+    bnd = rank_bounds([x * y for x, y in zip(ra, rb)], [2] * n, 256)
+    assert max(bnd) == 256 and bnd[0] == bnd[-1] == 1
+    # too-tall unfolding (rank 2049 * d = 4098 rows) is outside the implemented range
+    big = _fake_tt([1, 2, 4096, 2, 1], [2, 2048, 2, 2])
+    assert ws(Q.OP_ROUND, big)[0] in (-10, -3)
+
+
+def test_rank_bounds_match_profile():
+    from paper_2602_20226_amd.qtt import rank_bounds
+    b = rank_bounds([1, 4, 16, 64, 16, 4, 1], [2] * 6, 0)
+    assert b == [1, 2, 4, 8, 4, 2, 1]
+    b = rank_bounds([1, 4, 16, 64, 16, 4, 1], [2] * 6, 3)
+    assert b == [1, 2, 3, 3, 3, 2, 1]
