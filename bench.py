@@ -1,0 +1,166 @@
+"""Benchmark: QTT contract + round on one MI355X.
+
+Workload: 3D finite-difference Laplacian MPO (interleaved, 42 cores of
+physical size 2, interior rank 7) applied to a Gaussian rank-256 MPS
+(seed 3, variance-normalised), rounded back to max rank 256 at relative
+tolerance 1e-8.  A step is one call of the fused contract+round (QR sweep
+with BF16x6 bond GEMMs, FP64 Householder QR, FP64 Jacobi SVD sweep); the
+inputs are resident in HBM before the timed region.
+
+Prints one JSON line (see the design doc for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def geqrf_flops(m, n):
+    if m >= n:
+        return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+    return 2.0 * n * m * m - 2.0 * m ** 3 / 3.0
+
+
+def ormqr_flops(m, k, c):
+    """Apply k Householder reflectors of an m-row Q to an m x c matrix."""
+    return 4.0 * m * k * c - 2.0 * k * k * c
+
+
+def svd_nominal_flops(m, n):
+    """Nominal SVD count of an m x n matrix (fixed sweep count, not measured)."""
+    if m < n:
+        m, n = n, m
+    return geqrf_flops(m, n) + 8 * 9.0 * n ** 3 + 2.0 * m * n * n
+
+
+def contract_round_flops(ra, rb, d, dj, ranks_out, mpo=True):
+    """Algorithmic FLOP of contract + round under fixed conventions.
+
+    QR sweep: factored bond product R X_k (K = r_b) then the MPO core
+    (K = r_a d_in); Householder QR of the (rho d) x r_C unfolding.
+    SVD sweep: Q_k applied to [U Sigma; 0], nominal SVD of the
+    rho x (d r'') unfolding, U Sigma = F V product.
+    """
+    n = len(d)
+    rc = [x * y for x, y in zip(ra, rb)]
+    rho = [1] * (n + 1)
+    f = 0.0
+    for k in range(n):
+        m_rows = rho[k] * d[k]
+        cols = rc[k + 1]
+        # bond product
+        f += 2.0 * (rho[k] * ra[k]) * (dj[k] * rb[k + 1]) * rb[k]
+        f += 2.0 * (rho[k] * d[k]) * (ra[k + 1] * rb[k + 1]) * (ra[k] * dj[k]) if mpo else \
+            2.0 * rho[k] * d[k] * ra[k + 1] * rb[k + 1] * ra[k]
+        if k < n - 1:
+            f += geqrf_flops(m_rows, cols)
+            rho[k + 1] = min(m_rows, cols)
+    rnext = 1
+    for k in range(n - 1, 0, -1):
+        rows = rho[k]
+        D = d[k] * rnext
+        if k < n - 1:
+            f += ormqr_flops(rho[k] * d[k], rho[k + 1], rnext)
+        f += svd_nominal_flops(rows, D)
+        r = ranks_out[k]
+        f += 2.0 * min(rows, D) * r * D
+        rnext = r
+    f += ormqr_flops(d[0], rho[1], rnext)
+    return f
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
+    ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the single-chain rounding "
+              f"sweep does not shard across GPUs -- see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import qtt_inputs as I
+    from paper_2602_20226_amd import qtt as Q
+
+    Q.load_library()
+    dev = "cuda:0"
+    w = I.config4()
+    A = Q.to_device(w.a, dev)
+    B = Q.to_device(w.b, dev)
+    ra = [1] + [c.shape[-1] for c in w.a]
+    rb = [1] + [c.shape[-1] for c in w.b]
+    d = [c.shape[1] for c in w.a]
+    dj = [c.shape[2] for c in w.a]
+    bnd = Q.rank_bounds([x * y for x, y in zip(ra, rb)], d, w.max_rank)
+    outs = [torch.empty(bnd[k] * d[k] * bnd[k + 1], dtype=torch.float64, device=dev) for k in range(len(d))]
+    ws = None
+
+    def step(prec):
+        nonlocal ws
+        res = Q.contract_round(w.spec, A, B, w.rel_tol, w.max_rank, prec=prec, out_buffers=outs, workspace=ws)
+        return res
+
+    # workspace allocated once, outside the timed region
+    L = Q.load_library()
+    import ctypes as C
+    va, vb = Q.TTView(A, 2), Q.TTView(B, 1)
+    nb = C.c_size_t()
+    Q._check(L.qtt_workspace_size(None, Q.OP_CONTRACT_ROUND, w.spec.encode(), C.byref(va.struct),
+                                  C.byref(vb.struct), w.max_rank, Q.PREC[args.prec], C.byref(nb)), "ws")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+
+    def timed(prec, steps, warmup):
+        res = None
+        for _ in range(warmup):
+            res = step(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = step(prec)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, res
+
+    sec, res = timed(args.prec, args.steps, args.warmup)
+    flops = contract_round_flops(ra, rb, d, dj, res.ranks)
+    out = {
+        "metric": "QTT contract+round TFLOP/s (3D Laplacian MPO x rank-256 MPS, n=42, round to rank 256 at 1e-8)",
+        "value": flops / sec / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{args.prec}+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "cores": len(d), "mps_rank": 256, "mpo_rank": 7, "max_rank": w.max_rank,
+                   "rel_tol": w.rel_tol, "gemm": args.prec, "factorisations": "fp64"},
+        "algorithmic_gflop_per_step": flops / 1e9,
+        "ranks_out_max": max(res.ranks),
+        "jacobi_sweeps_max": res.jacobi_sweeps_max,
+    }
+    if not args.no_fp64_leg and args.prec != "fp64":
+        sec64, res64 = timed("fp64", max(1, args.steps // 2), 1)
+        out["fp64_ms_per_step"] = sec64 * 1e3
+        out["speedup_vs_fp64_path"] = sec64 / sec
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -151,7 +151,7 @@ int make_plan(const Shape& s, long max_rank, Plan& P) {
       maxX = std::max(maxX, rows * D);
       maxP = std::max(maxP, rows);
     }
-    if (16 * D > 20000) return QTT_ERR_UNSUPPORTED;  // Jacobi stages 16 rows of length D in LDS
+    if (32 * D > 20000) return QTT_ERR_UNSUPPORTED;  // Jacobi stages 32 rows of length D in LDS
     maxYn = std::max(maxYn, rows * rr[k]);
   }
   if (n >= 2) maxZ = std::max(maxZ, P.m[0] * rr[1]);

@@ -26,7 +26,7 @@ template <int NT, int RPT, int PW>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_qr_panel(double* __restrict__ A, long lda, int m, int j0, int pw,
                                                  double* __restrict__ Tout) {
   constexpr int NW = NT / 64;
-  __shared__ double red[NW * 16];
+  __shared__ double red[NT];
   __shared__ double bc[16];
   __shared__ double sc[NW];
   __shared__ double Ts[16][17];
@@ -127,83 +127,101 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 //   V: rows [r0, r0+mp) of A, columns [vc0, vc0+pw), unit lower trapezoidal.
 //   Y rows [yr0, yr0+mp), columns [c0, c0+ncols).
 //   trans: Y <- (I - V T^T V^T) Y  else  Y <- (I - V T V^T) Y.
-__global__ __launch_bounds__(256) void k_apply_panel(const double* __restrict__ A, long lda, int r0, int mp,
-                                                     int vc0, int pw, const double* __restrict__ T,
-                                                     double* __restrict__ Y, long ldy, int yr0, int c0,
-                                                     int ncols, int trans) {
-  __shared__ double part[16][257];
+// 512 threads: thread (g, c) owns column c of the tile and the rows
+// lr = g (mod 32); rows are streamed four at a time so that several loads
+// are in flight per thread.
+constexpr int AP_NT = 512, AP_G = AP_NT / 16;
+
+__device__ __forceinline__ void load_vrow(const double* __restrict__ arow, int lr, int pw, double (&v)[16]) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = (i >= pw) ? 0.0 : (lr > i ? arow[i] : (lr == i ? 1.0 : 0.0));
+}
+
+__global__ __launch_bounds__(AP_NT) void k_apply_panel(const double* __restrict__ A, long lda, int r0, int mp,
+                                                       int vc0, int pw, const double* __restrict__ T,
+                                                       double* __restrict__ Y, long ldy, int yr0, int c0,
+                                                       int ncols, int trans) {
+  __shared__ double part[AP_G][16][17];
   __shared__ double Ws[16][17];
   __shared__ double W2[16][17];
   __shared__ double Tsh[16][17];
   const int tid = threadIdx.x;
-  const int col0 = c0 + blockIdx.x * 16;
-  const int cend = c0 + ncols;
-  Tsh[tid >> 4][tid & 15] = T[tid];
+  const int c = tid & 15, g = tid >> 4;
+  const int gc = c0 + blockIdx.x * 16 + c;
+  const bool valid = gc < c0 + ncols;
+  if (tid < 256) Tsh[tid >> 4][tid & 15] = T[tid];
+  const double* Ab = A + (long)r0 * lda + vc0;
+  double* Yb = Y + (long)yr0 * ldy + gc;
 
-  // phase 1: partial W over 16 row groups
-  {
-    const int blk = tid & 15, ib = blk >> 2, cb = blk & 3, rg = tid >> 4;
-    double acc[4][4];
+  // phase 1: w[i] = sum_rows V[lr][i] * Y[lr][c]
+  double w[16];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+  for (int i = 0; i < 16; ++i) w[i] = 0.0;
+  int lr = g;
+  for (; lr + 3 * AP_G < mp; lr += 4 * AP_G) {
+    double y[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
-    for (int lr = rg; lr < mp; lr += 16) {
-      const double* arow = A + (long)(r0 + lr) * lda + vc0;
-      const double* yrow = Y + (long)(yr0 + lr) * ldy;
-      double v[4], y[4];
+    for (int q = 0; q < 4; ++q) y[q] = valid ? Yb[(long)(lr + q * AP_G) * ldy] : 0.0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = 4 * ib + q;
-        v[q] = (i >= pw) ? 0.0 : (lr > i ? arow[i] : (lr == i ? 1.0 : 0.0));
-        const int c = col0 + 4 * cb + q;
-        y[q] = (c < cend) ? yrow[c] : 0.0;
-      }
+    for (int q = 0; q < 4; ++q) {
+      double v[16];
+      load_vrow(Ab + (long)(lr + q * AP_G) * lda, lr + q * AP_G, pw, v);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[q][u] += v[q] * y[u];
+      for (int i = 0; i < 16; ++i) w[i] += v[i] * y[q];
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) part[rg][(4 * ib + q) * 16 + 4 * cb + u] = acc[q][u];
   }
+  for (; lr < mp; lr += AP_G) {
+    const double y = valid ? Yb[(long)lr * ldy] : 0.0;
+    double v[16];
+    load_vrow(Ab + (long)lr * lda, lr, pw, v);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w[i] += v[i] * y;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) part[g][i][c] = w[i];
   __syncthreads();
-  {
+  if (tid < 256) {
+    const int i = tid >> 4, cc = tid & 15;
     double s = 0.0;
 #pragma unroll
-    for (int g = 0; g < 16; ++g) s += part[g][tid];
-    Ws[tid >> 4][tid & 15] = s;
+    for (int q = 0; q < AP_G; ++q) s += part[q][i][cc];
+    Ws[i][cc] = s;
   }
   __syncthreads();
-  {
-    const int i = tid >> 4, c = tid & 15;
+  if (tid < 256) {
+    const int i = tid >> 4, cc = tid & 15;
     double s = 0.0;
 #pragma unroll
-    for (int l = 0; l < 16; ++l) s += (trans ? Tsh[l][i] : Tsh[i][l]) * Ws[l][c];
-    W2[i][c] = s;
+    for (int l = 0; l < 16; ++l) s += (trans ? Tsh[l][i] : Tsh[i][l]) * Ws[l][cc];
+    W2[i][cc] = s;
   }
   __syncthreads();
-  // phase 3: Y -= V W2
-  {
-    const int c = tid & 15, rg = tid >> 4;
-    const int gc = col0 + c;
-    if (gc < cend) {
-      double w[16];
+  if (!valid) return;
+  // phase 3: Y[lr][c] -= sum_i V[lr][i] W2[i][c]
 #pragma unroll
-      for (int i = 0; i < 16; ++i) w[i] = W2[i][c];
-      for (int lr = rg; lr < mp; lr += 16) {
-        const double* arow = A + (long)(r0 + lr) * lda + vc0;
-        double s = 0.0;
+  for (int i = 0; i < 16; ++i) w[i] = W2[i][c];
+  lr = g;
+  for (; lr + 3 * AP_G < mp; lr += 4 * AP_G) {
+    double y[4];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const double v = (i >= pw) ? 0.0 : (lr > i ? arow[i] : (lr == i ? 1.0 : 0.0));
-          s += v * w[i];
-        }
-        Y[(long)(yr0 + lr) * ldy + gc] -= s;
-      }
+    for (int q = 0; q < 4; ++q) y[q] = Yb[(long)(lr + q * AP_G) * ldy];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double v[16];
+      load_vrow(Ab + (long)(lr + q * AP_G) * lda, lr + q * AP_G, pw, v);
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s += v[i] * w[i];
+      Yb[(long)(lr + q * AP_G) * ldy] = y[q] - s;
     }
+  }
+  for (; lr < mp; lr += AP_G) {
+    double v[16];
+    load_vrow(Ab + (long)lr * lda, lr, pw, v);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += v[i] * w[i];
+    Yb[(long)lr * ldy] -= s;
   }
 }
 
@@ -277,7 +295,7 @@ hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, doub
     const int c0 = j0 + pw;
     const int nc = n - c0;
     if (nc > 0) {
-      hipLaunchKernelGGL(k_apply_panel, dim3((nc + 15) / 16), dim3(256), 0, s, (const double*)A, lda, j0, m - j0,
+      hipLaunchKernelGGL(k_apply_panel, dim3((nc + 15) / 16), dim3(AP_NT), 0, s, (const double*)A, lda, j0, m - j0,
                          j0, pw, (const double*)T, A, lda, j0, c0, nc, 1);
       e = hipGetLastError();
     }
@@ -299,7 +317,7 @@ hipError_t apply_q(hipStream_t s, const double* A, int m, int kref, long lda, co
   });
   for (int t = 0; t < np; ++t) {
     const P& q = trans ? list[t] : list[np - 1 - t];
-    hipLaunchKernelGGL(k_apply_panel, dim3((ncols + 15) / 16), dim3(256), 0, s, A, lda, q.j0, m - q.j0, q.j0, q.pw,
+    hipLaunchKernelGGL(k_apply_panel, dim3((ncols + 15) / 16), dim3(AP_NT), 0, s, A, lda, q.j0, m - q.j0, q.j0, q.pw,
                        Tbuf + (long)q.p * 256, Y, ldy, q.j0, 0, ncols, trans ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

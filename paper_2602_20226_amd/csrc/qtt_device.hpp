@@ -11,10 +11,38 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int WAVE = 64;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+// DPP lane exchange inside a row of 16 lanes (no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8
+constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15 - i within 16
+
+// Sum over the 16 lanes of each row; all 16 lanes get the same bits.
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp<DPP_XOR1>(v);
+  v += dpp<DPP_XOR2>(v);
+  v += dpp<DPP_HALF_MIRROR>(v);
+  v += dpp<DPP_MIRROR>(v);
   return v;
+}
+
+// Bit-exact read of one lane's double (the readlane builtin converts a
+// double operand to an integer, so the two 32-bit halves are read instead).
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave; uniform result.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row_sum(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -39,61 +67,68 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return s;
 }
 
-// Wave-level reduction of 16 values per lane into one value per lane.
-// After the call, lane L holds the wave sum of value index
-//   v(L) = 8*bit5 + 4*bit4 + 2*bit3 + bit2,
-// replicated over the four lanes that differ in bits 0..1.
-// 17 exchanges instead of 16 full butterflies.
-__device__ __forceinline__ double wave_sum16(const double (&x)[16], int& vidx) {
-  const int lane = threadIdx.x & (WAVE - 1);
+// Row-level transpose reduction of 16 values per lane: afterwards lane L
+// holds the sum over its row (16 lanes) of value index L % 16.  The pairing
+// order (mirror, half mirror, xor 2, xor 1) keeps partners' index sets
+// aligned: each step splits on one lane bit, 8 + 4 + 2 + 1 DPP exchanges.
+__device__ __forceinline__ double row_sum16(const double (&x)[16]) {
+  const int l = threadIdx.x & 15;
   double y[8];
-  const bool hi5 = (lane & 32) != 0;
+  const bool b3 = (l & 8) != 0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    double send = hi5 ? x[i] : x[i + 8];
-    double keep = hi5 ? x[i + 8] : x[i];
-    y[i] = keep + __shfl_xor(send, 32, WAVE);
+    const double send = b3 ? x[i] : x[i + 8];
+    const double keep = b3 ? x[i + 8] : x[i];
+    y[i] = keep + dpp<DPP_MIRROR>(send);
   }
   double z[4];
-  const bool hi4 = (lane & 16) != 0;
+  const bool b2 = (l & 4) != 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    double send = hi4 ? y[i] : y[i + 4];
-    double keep = hi4 ? y[i + 4] : y[i];
-    z[i] = keep + __shfl_xor(send, 16, WAVE);
+    const double send = b2 ? y[i] : y[i + 4];
+    const double keep = b2 ? y[i + 4] : y[i];
+    z[i] = keep + dpp<DPP_HALF_MIRROR>(send);
   }
   double u[2];
-  const bool hi3 = (lane & 8) != 0;
+  const bool b1 = (l & 2) != 0;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    double send = hi3 ? z[i] : z[i + 2];
-    double keep = hi3 ? z[i + 2] : z[i];
-    u[i] = keep + __shfl_xor(send, 8, WAVE);
+    const double send = b1 ? z[i] : z[i + 2];
+    const double keep = b1 ? z[i + 2] : z[i];
+    u[i] = keep + dpp<DPP_XOR2>(send);
   }
-  const bool hi2 = (lane & 4) != 0;
-  double send = hi2 ? u[0] : u[1];
-  double keep = hi2 ? u[1] : u[0];
-  double r = keep + __shfl_xor(send, 4, WAVE);
-  r += __shfl_xor(r, 2, WAVE);
-  r += __shfl_xor(r, 1, WAVE);
-  vidx = (hi5 ? 8 : 0) + (hi4 ? 4 : 0) + (hi3 ? 2 : 0) + (hi2 ? 1 : 0);
-  return r;
+  const bool b0 = (l & 1) != 0;
+  const double send = b0 ? u[0] : u[1];
+  const double keep = b0 ? u[1] : u[0];
+  return keep + dpp<DPP_XOR1>(send);
 }
 
 // Workgroup sum of 16 values per thread; result written to out[16] (LDS),
-// visible to all threads on return.  red must hold (NT/64)*16 doubles.
+// visible to all threads on return.  red must hold (NT/16)*16 doubles
+// (one slot per row of 16 lanes and value).
 template <int NT>
 __device__ __forceinline__ void block_sum16(const double (&x)[16], double* red, double* out) {
-  constexpr int NW = NT / WAVE;
-  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-  int v;
-  double r = wave_sum16(x, v);
-  if ((lane & 3) == 0) red[wid * 16 + v] = r;
+  constexpr int NR = NT / 16;  // rows of 16 lanes
+  const double r = row_sum16(x);
+  red[threadIdx.x] = r;  // row (threadIdx.x / 16), value (threadIdx.x % 16)
   __syncthreads();
+  if constexpr (NR > 16) {
+    // two levels: 16 groups of NR/16 rows, then the 16 group sums
+    constexpr int G = NR / 16;
+    double s = 0.0;
+    if (threadIdx.x < 256) {
+#pragma unroll
+      for (int w = 0; w < G; ++w) s += red[((threadIdx.x >> 4) * G + w) * 16 + (threadIdx.x & 15)];
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) red[threadIdx.x] = s;
+    __syncthreads();
+  }
+  constexpr int NR2 = NR > 16 ? 16 : NR;
   if (threadIdx.x < 16) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) s += red[w * 16 + threadIdx.x];
+    for (int w = 0; w < NR2; ++w) s += red[w * 16 + threadIdx.x];
     out[threadIdx.x] = s;
   }
   __syncthreads();

@@ -7,11 +7,11 @@
 // keeps U Sigma V^T = X_orig V V^T exact up to the orthogonality of V
 // (a product of thousands of rounded rotations would drift from orthogonal).
 //
-// Parallel ordering: rows are grouped into blocks of 8; a persistent grid of
+// Parallel ordering: rows are grouped into blocks of 16; a persistent grid of
 // workgroups (one per block pair) runs the round-robin tournament over blocks,
 // with a grid barrier between rounds.  For its pair of blocks a workgroup
-// stages the 16 rows in LDS and runs one full inner sweep of plane rotations
-// over them (15 rounds of 8 disjoint pairs, one wave per pair).  A rotation of
+// stages the 32 rows in LDS and runs one full inner sweep of plane rotations
+// over them (31 rounds of 16 disjoint pairs, one wave per pair).  A rotation of
 // rows a, c is skipped when |a.c| <= tol * ||a|| ||c|| with
 // tol = sqrt(L) * eps, and the iteration stops after the first sweep without
 // any rotation.
@@ -22,8 +22,9 @@ namespace qtt {
 
 namespace {
 
-constexpr int JB = 8;        // rows per block
-constexpr int JNT = 512;     // threads: one wave per row pair of the inner sweep
+constexpr int JB = 16;        // rows per block
+constexpr int JR = 2 * JB;    // rows staged per block pair
+constexpr int JNT = 64 * JB;  // threads: one wave per row pair of the inner sweep
 
 __device__ __forceinline__ int rr_item(int pos, int round, int n) {
   // circle method: position 0 fixed, the others rotate
@@ -33,7 +34,7 @@ __device__ __forceinline__ int rr_item(int pos, int round, int n) {
 __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, int L,
                                                 unsigned* __restrict__ ctr, int max_sweeps, int* sweeps_out,
                                                 double tol) {
-  extern __shared__ double sh[];  // [16][L]
+  extern __shared__ double sh[];  // [JR][L]
   __shared__ unsigned s_tot;
   const int W = L;
   const int nblk = (p + JB - 1) / JB;
@@ -47,18 +48,18 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
       for (int pair = blockIdx.x; pair < npairs; pair += gridDim.x) {
         const int b0 = rr_item(pair, round, nb2);
         const int b1 = rr_item(nb2 - 1 - pair, round, nb2);
-        // stage rows: local row t < 8 -> block b0 row t, t >= 8 -> block b1 row t-8
-        for (int e = tid; e < 16 * W; e += JNT) {
+        // stage rows: local row t < JB -> block b0 row t, t >= JB -> block b1 row t-JB
+        for (int e = tid; e < JR * W; e += JNT) {
           const int t = e / W, c = e % W;
-          const int gr = (t < 8 ? b0 : b1) * JB + (t & 7);
+          const int gr = (t < JB ? b0 : b1) * JB + (t % JB);
           double v = 0.0;
           if (gr < p) v = X[(long)gr * L + c];
           sh[t * W + c] = v;
         }
         __syncthreads();
-        for (int ir = 0; ir < 15; ++ir) {
-          const int ra = rr_item(wave, ir, 16);
-          const int rc = rr_item(15 - wave, ir, 16);
+        for (int ir = 0; ir < JR - 1; ++ir) {
+          const int ra = rr_item(wave, ir, JR);
+          const int rc = rr_item(JR - 1 - wave, ir, JR);
           double* xa = sh + ra * W;
           double* xc = sh + rc * W;
           double al = 0.0, be = 0.0, ga = 0.0;
@@ -85,9 +86,9 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
           }
           __syncthreads();
         }
-        for (int e = tid; e < 16 * W; e += JNT) {
+        for (int e = tid; e < JR * W; e += JNT) {
           const int t = e / W, c = e % W;
-          const int gr = (t < 8 ? b0 : b1) * JB + (t & 7);
+          const int gr = (t < JB ? b0 : b1) * JB + (t % JB);
           if (gr < p) X[(long)gr * L + c] = sh[t * W + c];
         }
         __syncthreads();
@@ -201,7 +202,7 @@ inline int gsz(long n) {
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
                        int* sweeps_dev) {
   if (p <= 0 || L <= 0) return hipSuccess;
-  const size_t shmem = (size_t)16 * L * sizeof(double);
+  const size_t shmem = (size_t)JR * L * sizeof(double);
   if (shmem > 160 * 1024 - 1024) return hipErrorInvalidValue;
   hipError_t e = fill_u32(s, counter, 0u, 8);
   if (e != hipSuccess) return e;

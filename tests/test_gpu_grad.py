@@ -1,0 +1,137 @@
+"""Differentiation form on the GPU: environment-sweep backward vs the oracle and finite differences."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+import qtt_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2602_20226_amd import autograd as AG
+    from paper_2602_20226_amd import qtt as Q
+
+DEV = "cuda:0"
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def leaves(cores, dtype=torch.float64, grad=True):
+    return [torch.as_tensor(c, dtype=dtype).to(DEV).requires_grad_(grad) for c in cores]
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_inner_backward_matches_oracle():
+    rng = np.random.default_rng(200)
+    A = [rng.standard_normal(s) for s in [(1, 2, 3), (3, 2, 5), (5, 2, 2), (2, 2, 1)]]
+    B = [rng.standard_normal(s) for s in [(1, 2, 2), (2, 2, 4), (4, 2, 3), (3, 2, 1)]]
+    ga = O.inner_grad(A, B)
+    gb = O.inner_grad(B, A)
+    a, b = leaves(A), leaves(B)
+    v = AG.inner(a, b)
+    assert abs(v.item() - O.inner(A, B)) <= 1e-13 * O.norm(A) * O.norm(B)
+    v.backward()
+    for k in range(len(A)):
+        assert rel(a[k].grad.cpu().numpy(), ga[k]) <= 1e-13
+        assert rel(b[k].grad.cpu().numpy(), gb[k]) <= 1e-13
+
+
+@pytest.mark.parametrize("spec", ["ij,j->i", "i,i->i"])
+def test_contract_backward_matches_oracle(spec):
+    rng = np.random.default_rng(201)
+    if spec == "ij,j->i":
+        W = [rng.standard_normal(s) for s in [(1, 2, 2, 3), (3, 2, 2, 2), (2, 2, 2, 1)]]
+    else:
+        W = [rng.standard_normal(s) for s in [(1, 2, 3), (3, 2, 2), (2, 2, 1)]]
+    X = [rng.standard_normal(s) for s in [(1, 2, 4), (4, 2, 3), (3, 2, 1)]]
+    C = O.contract(spec, W, X)
+    G = [rng.standard_normal(c.shape) for c in C]
+    dW, dX = O.contract_grad(spec, W, X, G)
+    w, x = leaves(W), leaves(X)
+    c = AG.contract(spec, w, x)
+    for ck, cr in zip(c, C):
+        assert np.abs(ck.detach().cpu().numpy() - cr).max() <= 1e-14 * np.abs(cr).max()
+    torch.autograd.backward(c, [torch.as_tensor(g).to(DEV) for g in G])
+    for k in range(len(W)):
+        assert rel(x[k].grad.cpu().numpy(), dX[k]) <= 1e-13
+        assert rel(w[k].grad.cpu().numpy(), dW[k]) <= 1e-13
+
+
+def _config5():
+    w = I.config5()
+    return w.a, w.b, w.extra["rhs"]
+
+
+def test_config5_gradient_fp64_vs_oracle_and_euler():
+    log("cfg5 fp64 gradient")
+    Wn, xn, bn = _config5()
+    g_ref = O.grad_axb(Wn, xn, bn)
+    W, x, b = leaves(Wn, grad=False), leaves(xn), leaves(bn, grad=False)
+    L = AG.residual_loss(W, x, b)
+    L_ref = O.loss_axb(Wn, xn, bn)
+    assert abs(L.item() - L_ref) <= 1e-11 * L_ref
+    L.backward()
+    worst = 0.0
+    for k in range(len(xn)):
+        e = rel(x[k].grad.cpu().numpy(), g_ref[k])
+        worst = max(worst, e)
+        assert e <= 1e-12, (k, e)
+    log(f"cfg5 fp64 worst per-core rel err {worst:.2e}")
+    # Euler identity: <dL/dx_k, x_k> = 2<y,y> - 2<y,b> for every core
+    y = O.contract("ij,j->i", Wn, xn)
+    rhs = 2 * O.inner(y, y) - 2 * O.inner(y, bn)
+    for k in range(len(xn)):
+        lhs = float(torch.sum(x[k].grad * x[k]).item())
+        assert abs(lhs - rhs) <= 1e-11 * abs(rhs)
+
+
+def test_config5_gradient_fp32():
+    log("cfg5 fp32 gradient")
+    Wn, xn, bn = _config5()
+    g_ref = O.grad_axb(Wn, xn, bn)
+    W, x, b = leaves(Wn, torch.float32, False), leaves(xn, torch.float32), leaves(bn, torch.float32, False)
+    L = AG.residual_loss(W, x, b)
+    L.backward()
+    worst = 0.0
+    for k in range(len(xn)):
+        e = rel(x[k].grad.double().cpu().numpy(), g_ref[k])
+        worst = max(worst, e)
+    log(f"cfg5 fp32 worst per-core rel err {worst:.2e}")
+    assert worst <= 1e-5
+
+
+def test_config5_central_differences():
+    """L is exactly quadratic in each core, so central FD has no truncation error."""
+    log("cfg5 finite differences")
+    Wn, xn, bn = _config5()
+    W, b = leaves(Wn, grad=False), leaves(bn, grad=False)
+    x = leaves(xn)
+    L = AG.residual_loss(W, x, b)
+    L.backward()
+    rng = np.random.default_rng(202)
+    h = 1e-6
+    for _ in range(12):
+        k = int(rng.integers(len(xn)))
+        idx = tuple(int(rng.integers(s)) for s in xn[k].shape)
+        xp = [c.copy() for c in xn]
+        xm = [c.copy() for c in xn]
+        xp[k][idx] += h
+        xm[k][idx] -= h
+        with torch.no_grad():
+            Lp = AG.residual_loss(W, leaves(xp, grad=False), b).item()
+            Lm = AG.residual_loss(W, leaves(xm, grad=False), b).item()
+        fd_gpu = (Lp - Lm) / (2 * h)
+        fd_ref = (O.loss_axb(Wn, xp, bn) - O.loss_axb(Wn, xm, bn)) / (2 * h)
+        g = x[k].grad[idx].item()
+        scale = max(abs(g), 1e-3 * L.item())
+        assert abs(fd_ref - g) <= 1e-6 * scale, (k, idx, fd_ref, g)
+        assert abs(fd_gpu - g) <= 1e-6 * scale, (k, idx, fd_gpu, g)

@@ -1,0 +1,78 @@
+"""Precision forms at the full 3D rank-256 size against the FP64 oracle.
+
+The oracle rounds the exact rank-1792 product once (about half a minute of
+LAPACK work); every GEMM arithmetic of the GPU path is compared with it.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+import qtt_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2602_20226_amd import qtt as Q
+
+DEV = "cuda:0"
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cfg4():
+    w = I.config4()
+    log("cfg4: oracle contract + round (FP64, LAPACK)")
+    C = O.contract(w.spec, w.a, w.b)
+    ref, info = O.round_tt(C, w.rel_tol, w.max_rank, return_info=True)
+    del C
+    A = Q.to_device(w.a, DEV)
+    B = Q.to_device(w.b, DEV)
+    return w, ref, info, A, B
+
+
+def _run(cfg4, prec):
+    w, ref, info, A, B = cfg4
+    got = Q.contract_round(w.spec, A, B, w.rel_tol, w.max_rank, prec=prec, want_sigmas=True)
+    err = O.rel_error(Q.to_host(got.cores), ref)
+    sig = 0.0
+    for k, s in enumerate(info.sigmas):
+        g = np.array(got.sigmas[k][: len(s)])
+        sig = max(sig, np.abs(g - s).max() / s[0])
+    log(f"cfg4 {prec}: rel err {err:.3e}  max sigma err/sigma1 {sig:.3e}  ranks equal {got.ranks == info.ranks}")
+    return got, err, sig
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_fp64_path(cfg4):
+    got, err, sig = _run(cfg4, "fp64")
+    _, _, info, _, _ = cfg4
+    assert got.ranks == info.ranks
+    assert sig <= 1e-12
+    assert err <= 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_bf16x6_path(cfg4):
+    got, err, sig = _run(cfg4, "bf16x6")
+    _, _, info, _, _ = cfg4
+    assert got.ranks == info.ranks
+    assert sig <= 1e-6
+    assert err <= 1e-6
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_bf16x3_and_fp32_reported(cfg4):
+    """Three-product split and FP32 GEMMs: ranks must match, errors are reported."""
+    _, _, info, _, _ = cfg4
+    for prec in ["bf16x3", "fp32"]:
+        got, err, sig = _run(cfg4, prec)
+        assert got.ranks == info.ranks
+        assert err <= 1e-4
