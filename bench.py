@@ -159,7 +159,47 @@ def main():
         sec64, res64 = timed("fp64", max(1, args.steps // 2), 1)
         out["fp64_ms_per_step"] = sec64 * 1e3
         out["speedup_vs_fp64_path"] = sec64 / sec
+
+    # Roofline of the dominant kernel (the Householder block-reflector
+    # application): one extra step with that kernel class bracketed by HIP
+    # events on its launch stream inside libqtt.
+    Q.profile_start("apply_panel", 200000)
+    step(args.prec)
+    launches, kms, kbytes, kflops = Q.profile_stop()
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    out["roofline"] = {
+        "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+        "traffic": None, "kernel": "k_apply_panel", "launches": launches,
+        "avg_us": 1e3 * kms / max(launches, 1), "share_of_step": kms / (sec * 1e3),
+        "alg_bytes_per_launch": kbytes / max(launches, 1), "alg_flop_per_launch": kflops / max(launches, 1),
+    }
+    Q.profile_start("jacobi", 1000)
+    step(args.prec)
+    jl, jms, _, _ = Q.profile_stop()
+    out["jacobi_ms_per_step"] = jms
+    out["jacobi_launches"] = jl
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, ra, rb, d, dj)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, ra, rb, d, dj):
+    """The FP64 oracle (NumPy + LAPACK) on this host's cores: one full contract+round."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    C = O.contract(w.spec, w.a, w.b)
+    Y, info = O.round_tt(C, w.rel_tol, w.max_rank, return_info=True)
+    dt = time.perf_counter() - t0
+    flops = contract_round_flops(ra, rb, d, dj, info.ranks)
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "one full contract+round of the same 42-core workload (NumPy FP64, LAPACK QR/SVD)",
+            "seconds": dt}
 
 
 if __name__ == "__main__":

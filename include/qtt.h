@@ -162,6 +162,56 @@ int qtt_contract_backward(qtt_handle h, const char *spec, const qtt_tt *a, const
                           const qtt_tt *dc, qtt_tt *da, qtt_tt *db, void *ws, size_t ws_bytes,
                           void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: `count` independent contract+round problems (arrays a[i],
+ * b[i], out[i] of qtt_tt; uneven ranks allowed) in one persistent launch.
+ * Each workgroup takes the next problem from a device work queue (largest
+ * estimated cost first) and runs the whole QR sweep / Jacobi SVD sweep for
+ * it with workgroup-level kernels; rank decisions stay on the device.
+ * Bond products and U Sigma = F V accumulate in FP32; Householder QR, the
+ * Jacobi SVD, norms and rank decisions are FP64.  Limits: <= 32 cores per
+ * problem, unfolding rows <= 512, Jacobi row length d*r <= 768.
+ *
+ * qtt_batch_plan_create validates the problems, writes the instance table
+ * into ws, selects a kernel variant (Jacobi block size x grid size) -- by
+ * timing all variants on this batch when `tune` is non-zero, cached in the
+ * file named by QTT_TUNE_CACHE (default ~/.cache/qtt/batched_tune.txt) --
+ * and captures the queue reset plus the persistent launch in a hipGraph.
+ * qtt_batch_plan_launch replays that graph on `stream` (asynchronous; out
+ * cores must stay allocated with room for the rank bounds of each problem).
+ * qtt_batch_plan_results synchronises `stream` and writes the rounded ranks
+ * of all problems, concatenated (problem i contributes n_i + 1 entries), and
+ * optionally the discarded tails (n_i - 1 per problem); it returns
+ * QTT_ERR_NONFINITE / QTT_ERR_NOCONV if any problem hit those conditions.
+ * The workspace must stay alive and unmodified for the life of the plan.
+ * ------------------------------------------------------------------------- */
+typedef struct qtt_batch *qtt_batch_plan;
+int qtt_batch_workspace_size(qtt_handle h, const char *spec, int32_t count, const qtt_tt *a, const qtt_tt *b,
+                             int64_t max_rank, size_t *bytes);
+int qtt_batch_plan_create(qtt_handle h, const char *spec, int32_t count, const qtt_tt *a, const qtt_tt *b,
+                          qtt_tt *out, double rel_tol, int64_t max_rank, int tune, void *ws, size_t ws_bytes,
+                          void *stream, qtt_batch_plan *plan);
+int qtt_batch_plan_launch(qtt_batch_plan plan, void *stream);
+int qtt_batch_plan_results(qtt_batch_plan plan, int64_t *ranks, double *tails, void *stream);
+/* Selected variant (bit 0: Jacobi blocks of 4 rows, bit 1: two workgroups per
+ * CU), grid size and the tuning times of the four variants (ms; 0 if the
+ * variant came from the cache). */
+int qtt_batch_plan_info(qtt_batch_plan plan, int32_t *variant, int32_t *grid, float *tuned_ms);
+int qtt_batch_plan_destroy(qtt_batch_plan plan);
+
+/* Launch profiling for roofline reports.  qtt_profile_start arms one kernel
+ * class (0 = block-reflector application of the Householder QR, 1 = Jacobi
+ * SVD, 2 = Householder panel): every following launch of that class, up to
+ * max_launches, is bracketed by HIP events on the stream it is launched on,
+ * and its algorithmic bytes and FLOP (from the launch shape) are summed.
+ * qtt_profile_stop waits for the last event and returns the launch count,
+ * the summed kernel time (ms) and the summed algorithmic bytes / FLOP.  One
+ * session per process at a time; not thread-safe.  Allocates HIP events
+ * (no device memory). */
+int qtt_profile_start(qtt_handle h, int kernel_class, int max_launches);
+int qtt_profile_stop(qtt_handle h, int64_t *launches, double *total_ms, double *alg_bytes,
+                     double *alg_flops);
+
 #ifdef __cplusplus
 }
 #endif

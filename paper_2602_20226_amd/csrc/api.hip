@@ -2,15 +2,23 @@
 // the contraction / QR sweep / SVD sweep / environment sweeps on the caller's
 // stream.  See include/qtt.h for the contract of every entry point.
 #include "../../include/qtt.h"
+#include "batched.hpp"
 #include "qtt_internal.hpp"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <numeric>
+#include <sstream>
 #include <string>
+#include <sys/stat.h>
 #include <vector>
 
 using namespace qtt;
@@ -81,7 +89,7 @@ struct Plan {
   std::vector<long> rho;   // rank after QR, rho[-1] = 1 stored at index 0 => rho[k+1]
   std::vector<long> offM, offT;
   long offCenter = 0, offR = 0, offY = 0, offZ = 0, offX = 0, offXc = 0, offYn = 0, offTB = 0;
-  long offSig = 0, offPerm = 0, offTrunc = 0, offCtr = 0, offNorm = 0, offSweeps = 0, offOne = 0;
+  long offSig = 0, offPerm = 0, offTrunc = 0, offCtr = 0, offNorm = 0, offSweeps = 0, offOne = 0, offScr = 0;
   long total = 0;
   long maxr_bound = 0;
 };
@@ -151,7 +159,7 @@ int make_plan(const Shape& s, long max_rank, Plan& P) {
       maxX = std::max(maxX, rows * D);
       maxP = std::max(maxP, rows);
     }
-    if (32 * D > 20000) return QTT_ERR_UNSUPPORTED;  // Jacobi stages 32 rows of length D in LDS
+    if (D > 1024) return QTT_ERR_UNSUPPORTED;  // Jacobi keeps 16 row slices of length D per lane group
     maxYn = std::max(maxYn, rows * rr[k]);
   }
   if (n >= 2) maxZ = std::max(maxZ, P.m[0] * rr[1]);
@@ -168,6 +176,12 @@ int make_plan(const Shape& s, long max_rank, Plan& P) {
   P.offNorm = take(1);
   P.offSweeps = take(1);
   P.offOne = take(1);
+  {
+    long maxc = 1;
+    for (int k = 0; k <= n; ++k) maxc = std::max(maxc, s.rc[k]);
+    for (int k = 0; k < n; ++k) maxc = std::max(maxc, (long)s.d[k] * std::max(rr[k], rr[k + 1]));
+    P.offScr = take(qr_scratch_doubles(maxc));
+  }
   P.total = off;
   P.maxr_bound = 0;
   for (int k = 0; k <= n; ++k) P.maxr_bound = std::max(P.maxr_bound, rr[k]);
@@ -303,7 +317,7 @@ int qr_sweep(Sweep& w, const qtt_tt* t, const qtt_tt* a, const qtt_tt* b) {
     }
     if (!last) {
       const long m = P.m[k];
-      QTT_HIP(householder_qr(w.st, M, (int)m, (int)cols, ldm, ws + P.offT[k]));
+      QTT_HIP(householder_qr(w.st, M, (int)m, (int)cols, ldm, ws + P.offT[k], ws + P.offScr));
       QTT_HIP(extract_r(w.st, M, (int)P.rho[k + 1], (int)cols, ldm, R));
     }
   }
@@ -354,7 +368,7 @@ int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_in
       // Z = Q_k [Y_{k+1}; 0]  (m_k x r''_{k+1}) = B_k as rows x D
       QTT_HIP(copy_pad_rows(w.st, Yn, (int)P.rho[k + 1], (int)rnext, rnext, Z, (int)P.m[k], rnext));
       QTT_HIP(apply_q(w.st, ws + P.offM[k], (int)P.m[k], (int)P.rho[k + 1], s.rc[k + 1], ws + P.offT[k], Z,
-                      (int)rnext, rnext, false));
+                      (int)rnext, rnext, false, ws + P.offScr));
       B = Z;
     }
     // Jacobi acts on the rows of F: F = R (D x D) from a QR of B when B is
@@ -364,14 +378,18 @@ int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_in
     const int L = (int)D;
     if (tall) {
       if (B != Z) QTT_HIP(copy_pad_rows(w.st, B, (int)rows, (int)D, D, Z, (int)rows, D));
-      QTT_HIP(householder_qr(w.st, Z, (int)rows, (int)D, D, TB));
+      QTT_HIP(householder_qr(w.st, Z, (int)rows, (int)D, D, TB, ws + P.offScr));
       QTT_HIP(extract_r(w.st, Z, (int)D, (int)D, D, X));
       p = (int)D;
     } else {
       QTT_HIP(copy_pad_rows(w.st, B, (int)rows, (int)D, D, X, (int)rows, D));
       p = (int)rows;
     }
+    // F kept in Xc; Jacobi starts from F's rows in descending-norm order
+    // (a row permutation changes neither V nor U Sigma = F V)
     QTT_HIP(copy_pad_rows(w.st, X, p, L, L, Xc, p, L));
+    QTT_HIP(row_norms_sorted(w.st, Xc, p, L, sig, perm));
+    QTT_HIP(permute_rows(w.st, Xc, p, L, perm, X));
     QTT_HIP(jacobi_rows(w.st, X, p, L, ctr, kMaxSweeps, sweeps));
     QTT_HIP(row_norms_sorted(w.st, X, p, L, sig, perm));
     QTT_HIP(truncate_decide(w.st, sig, p, ws + P.offNorm, rel_tol, n - 1, max_rank, tr));
@@ -404,7 +422,7 @@ int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_in
     if (tall) {
       QTT_HIP(gemm_f64(w.st, false, true, p, r, L, 1.0, Xc, L, 0, core, L, 0, 0.0, Yn, r, 0, 1));
       if (rows > p) QTT_HIP(fill_f64(w.st, Yn + (long)p * r, 0.0, (rows - p) * r));
-      QTT_HIP(apply_q(w.st, Z, (int)rows, p, D, TB, Yn, r, r, false));
+      QTT_HIP(apply_q(w.st, Z, (int)rows, p, D, TB, Yn, r, r, false, ws + P.offScr));
     } else {
       QTT_HIP(gemm_f64(w.st, false, true, p, r, L, 1.0, Xc, L, 0, core, L, 0, 0.0, Yn, r, 0, 1));
     }
@@ -417,7 +435,7 @@ int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_in
   } else {
     QTT_HIP(copy_pad_rows(w.st, Yn, (int)P.rho[1], (int)rnext, rnext, Z, (int)P.m[0], rnext));
     QTT_HIP(apply_q(w.st, ws + P.offM[0], (int)P.m[0], (int)P.rho[1], s.rc[1], ws + P.offT[0], Z, (int)rnext,
-                    rnext, false));
+                    rnext, false, ws + P.offScr));
     QTT_HIP(copy_pad_rows(w.st, Z, (int)P.m[0], (int)rnext, rnext, (double*)out->cores[0], (int)P.m[0], rnext));
   }
   QTT_HIP(hipStreamSynchronize(w.st));
@@ -593,6 +611,139 @@ int same_layout(const qtt_tt* a, const qtt_tt* b) {
   return QTT_OK;
 }
 
+// ---------------------------------------------------------------- batched form
+struct BatchLayout {
+  long offTab, offOrder, offQueue, offRanks, offTails, offStatus, offInst;
+  std::vector<long> instOff;  // per-instance workspace offset (bytes from the aligned base)
+  std::vector<Plan> plans;
+  std::vector<Shape> shapes;
+  long total;  // bytes
+  int maxL;
+};
+
+long align256(long b) { return (b + 255) / 256 * 256; }
+
+int batch_layout(const char* spec, int count, const qtt_tt* a, const qtt_tt* b, long max_rank, BatchLayout& Lo) {
+  if (count < 1 || !a || !b) return QTT_ERR_ARG;
+  Lo.shapes.resize(count);
+  Lo.plans.resize(count);
+  Lo.instOff.resize(count);
+  long off = 0;
+  Lo.offTab = off;
+  off = align256(off + (long)count * sizeof(BInst));
+  Lo.offOrder = off;
+  off = align256(off + (long)count * sizeof(int));
+  Lo.offQueue = off;
+  off = align256(off + 16);
+  Lo.offRanks = off;
+  off = align256(off + (long)count * (QTT_BATCH_MAXN + 1) * sizeof(long));
+  Lo.offTails = off;
+  off = align256(off + (long)count * QTT_BATCH_MAXN * sizeof(double));
+  Lo.offStatus = off;
+  off = align256(off + (long)count * sizeof(int));
+  Lo.offInst = off;
+  Lo.maxL = 1;
+  for (int i = 0; i < count; ++i) {
+    int st = shape_from_pair(spec, &a[i], &b[i], Lo.shapes[i]);
+    if (st) return st;
+    if (a[i].dtype != QTT_F64 || b[i].dtype != QTT_F64) return QTT_ERR_DTYPE;
+    const Shape& sh = Lo.shapes[i];
+    if (sh.n > QTT_BATCH_MAXN) return QTT_ERR_UNSUPPORTED;
+    if ((st = make_plan(sh, max_rank, Lo.plans[i]))) return st;
+    const Plan& P = Lo.plans[i];
+    for (int k = 0; k + 1 < sh.n; ++k)
+      if (P.m[k] > 512) return QTT_ERR_UNSUPPORTED;  // register panel of the workgroup QR
+    long rnext = 1;
+    for (int k = sh.n - 1; k >= 1; --k) {
+      long bnd = std::min<long>(P.rho[k], max_rank > 0 ? max_rank : P.rho[k]);
+      const long D = (long)sh.d[k] * std::min<long>(rnext, 1L << 20);
+      if (P.rho[k] > 512) return QTT_ERR_UNSUPPORTED;
+      Lo.maxL = (int)std::max<long>(Lo.maxL, D);
+      rnext = std::max<long>(1, std::min(bnd, D));
+    }
+    Lo.instOff[i] = off;
+    off = align256(off + P.total * (long)sizeof(double));
+  }
+  if (16L * Lo.maxL * 8 > 96 * 1024) return QTT_ERR_UNSUPPORTED;  // Jacobi staging in LDS
+  Lo.total = off + 256;
+  return QTT_OK;
+}
+
+std::string tune_path() {
+  const char* e = std::getenv("QTT_TUNE_CACHE");
+  if (e && *e) return std::string(e);
+  const char* home = std::getenv("HOME");
+  std::string dir = std::string(home ? home : "/tmp") + "/.cache";
+  mkdir(dir.c_str(), 0755);
+  dir += "/qtt";
+  mkdir(dir.c_str(), 0755);
+  return dir + "/batched_tune.txt";
+}
+
+// Tuning cache: one line per workload signature, "signature variant".
+int tune_lookup(const std::string& sig) {
+  std::ifstream f(tune_path());
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string k;
+    int v;
+    if ((is >> k >> v) && k == sig) return v;
+  }
+  return -1;
+}
+
+void tune_store(const std::string& sig, int v) {
+  std::ofstream f(tune_path(), std::ios::app);
+  if (f) f << sig << " " << v << "\n";
+}
+
+}  // namespace
+
+struct qtt_batch {
+  qtt_context* h = nullptr;
+  int count = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BInst* dtab = nullptr;
+  int* dorder = nullptr;
+  unsigned* dqueue = nullptr;
+  long* dranks = nullptr;
+  double* dtails = nullptr;
+  int* dstatus = nullptr;
+  long* hranks = nullptr;
+  double* htails = nullptr;
+  int* hstatus = nullptr;
+  std::vector<int> ncores;
+  int variant = 0, grid = 0, maxL = 1;
+  double tol = 0.0;
+  long max_rank = 0;
+  float tuned_ms[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+void batch_free(qtt_batch* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  if (p->hranks) (void)hipHostFree(p->hranks);
+  if (p->htails) (void)hipHostFree(p->htails);
+  if (p->hstatus) (void)hipHostFree(p->hstatus);
+  delete p;
+}
+
+hipError_t batch_run(qtt_batch* p, hipStream_t s, int variant) {
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->h->device);
+  const int grid = std::min(p->count, cus * ((variant & 2) ? 2 : 1));
+  p->grid = grid;
+  return batched_launch(s, variant, grid, p->dtab, p->dorder, p->count, p->dqueue, p->tol, p->max_rank, p->dranks,
+                        p->dtails, p->dstatus, p->maxL);
+}
+
 }  // namespace
 
 extern "C" {
@@ -749,7 +900,7 @@ int qtt_orthogonalize(qtt_handle h, qtt_tt* t, double* norm_host, void* ws, size
   for (int k = 0; k + 1 < n; ++k) {
     const int m = (int)P.m[k], q = (int)P.rho[k + 1];
     QTT_HIP(set_eye_rect(w.st, Z, m, q));
-    QTT_HIP(apply_q(w.st, w.ws + P.offM[k], m, q, s.rc[k + 1], w.ws + P.offT[k], Z, q, q, false));
+    QTT_HIP(apply_q(w.st, w.ws + P.offM[k], m, q, s.rc[k + 1], w.ws + P.offT[k], Z, q, q, false, w.ws + P.offScr));
     QTT_HIP(copy_pad_rows(w.st, Z, m, q, q, (double*)t->cores[k], m, q));
   }
   QTT_HIP(copy_pad_rows(w.st, w.ws + P.offCenter, (int)(P.rho[n - 1] * s.d[n - 1]), 1, 1,
@@ -885,6 +1036,225 @@ int qtt_contract_backward(qtt_handle h, const char* spec, const qtt_tt* a, const
       if (e != hipSuccess) return QTT_ERR_HIP;
     }
   }
+  return QTT_OK;
+}
+
+int qtt_profile_start(qtt_handle h, int kernel_class, int max_launches) {
+  if (!h || kernel_class < 0 || kernel_class > 2 || max_launches < 1 || max_launches > (1 << 22)) return QTT_ERR_ARG;
+  Scoped sc(h->device);
+  return prof::start(kernel_class, max_launches) == hipSuccess ? QTT_OK : QTT_ERR_HIP;
+}
+
+int qtt_profile_stop(qtt_handle h, int64_t* launches, double* total_ms, double* alg_bytes, double* alg_flops) {
+  if (!h || !launches || !total_ms || !alg_bytes || !alg_flops) return QTT_ERR_ARG;
+  Scoped sc(h->device);
+  long l = 0;
+  if (prof::stop(&l, total_ms, alg_bytes, alg_flops) != hipSuccess) return QTT_ERR_HIP;
+  *launches = l;
+  return QTT_OK;
+}
+
+int qtt_batch_workspace_size(qtt_handle h, const char* spec, int32_t count, const qtt_tt* a, const qtt_tt* b,
+                             int64_t max_rank, size_t* bytes) {
+  (void)h;
+  if (!bytes) return QTT_ERR_ARG;
+  BatchLayout Lo;
+  int st = batch_layout(spec, count, a, b, max_rank, Lo);
+  if (st) return st;
+  *bytes = (size_t)Lo.total;
+  return QTT_OK;
+}
+
+int qtt_batch_plan_create(qtt_handle h, const char* spec, int32_t count, const qtt_tt* a, const qtt_tt* b,
+                          qtt_tt* out, double rel_tol, int64_t max_rank, int tune, void* ws, size_t ws_bytes,
+                          void* stream, qtt_batch_plan* plan) {
+  if (!h || !plan || !out) return QTT_ERR_ARG;
+  *plan = nullptr;
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return QTT_ERR_ARG;
+  BatchLayout Lo;
+  int st = batch_layout(spec, count, a, b, max_rank, Lo);
+  if (st) return st;
+  if (!ws || ws_bytes < (size_t)Lo.total) return QTT_ERR_WORKSPACE;
+  for (int i = 0; i < count; ++i) {
+    if (!out[i].cores || !out[i].ranks || out[i].n != a[i].n) return QTT_ERR_ARG;
+    for (int k = 0; k < out[i].n; ++k)
+      if (!out[i].cores[k]) return QTT_ERR_ARG;
+  }
+  Scoped sc(h->device);
+  char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  // host instance table
+  std::vector<BInst> tab(count);
+  std::vector<double> cost(count, 0.0);
+  for (int i = 0; i < count; ++i) {
+    const Shape& sh = Lo.shapes[i];
+    const Plan& P = Lo.plans[i];
+    BInst& I = tab[i];
+    std::memset(&I, 0, sizeof(BInst));
+    I.n = sh.n;
+    I.mpo = sh.kind == K_MPO ? 1 : 0;
+    I.ws = (double*)(base + Lo.instOff[i]);
+    for (int k = 0; k < sh.n; ++k) {
+      I.a[k] = (const double*)a[i].cores[k];
+      I.b[k] = (const double*)b[i].cores[k];
+      I.out[k] = (double*)out[i].cores[k];
+      I.offM[k] = P.offM[k];
+      I.offT[k] = P.offT[k];
+      I.d[k] = sh.d[k];
+      I.dj[k] = sh.dj[k];
+      I.m[k] = (int)P.m[k];
+    }
+    for (int k = 0; k <= sh.n; ++k) {
+      I.ra[k] = (int)sh.ra[k];
+      I.rb[k] = (int)sh.rb[k];
+      I.rho[k] = (int)P.rho[k];
+    }
+    I.offCenter = P.offCenter;
+    I.offR = P.offR;
+    I.offY = P.offY;
+    I.offZ = P.offZ;
+    I.offX = P.offX;
+    I.offXc = P.offXc;
+    I.offYn = P.offYn;
+    I.offTB = P.offTB;
+    I.offSig = P.offSig;
+    I.offPerm = P.offPerm;
+    I.offTmp = P.offScr;
+    I.offOne = P.offOne;
+    for (int k = 0; k + 1 < sh.n; ++k) {
+      const double m = (double)P.m[k], c = (double)sh.rc[k + 1];
+      cost[i] += m * c * std::min(m, c) + std::pow(std::min(m, c), 3.0);
+    }
+  }
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  qtt_batch* p = new (std::nothrow) qtt_batch();
+  if (!p) return QTT_ERR_ARG;
+  p->h = h;
+  p->count = count;
+  p->tol = rel_tol;
+  p->max_rank = max_rank;
+  p->maxL = Lo.maxL;
+  p->dtab = (BInst*)(base + Lo.offTab);
+  p->dorder = (int*)(base + Lo.offOrder);
+  p->dqueue = (unsigned*)(base + Lo.offQueue);
+  p->dranks = (long*)(base + Lo.offRanks);
+  p->dtails = (double*)(base + Lo.offTails);
+  p->dstatus = (int*)(base + Lo.offStatus);
+  p->ncores.resize(count);
+  for (int i = 0; i < count; ++i) p->ncores[i] = a[i].n;
+  hipStream_t us = (hipStream_t)stream;
+  auto fail = [&](int code) {
+    batch_free(p);
+    return code;
+  };
+  if (hipHostMalloc((void**)&p->hranks, (size_t)count * (QTT_BATCH_MAXN + 1) * sizeof(long), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&p->htails, (size_t)count * QTT_BATCH_MAXN * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&p->hstatus, (size_t)count * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return fail(QTT_ERR_HIP);
+  if (hipMemcpyAsync(p->dtab, tab.data(), (size_t)count * sizeof(BInst), hipMemcpyHostToDevice, us) != hipSuccess ||
+      hipMemcpyAsync(p->dorder, order.data(), (size_t)count * sizeof(int), hipMemcpyHostToDevice, us) != hipSuccess ||
+      hipStreamSynchronize(us) != hipSuccess)
+    return fail(QTT_ERR_HIP);
+  // variant: cached tuning result, measured now, or the default
+  std::ostringstream sig;
+  sig << spec << "|" << count << "|" << rel_tol << "|" << max_rank;
+  {
+    unsigned long long hsh = 1469598103934665603ull;
+    for (int i = 0; i < count; ++i)
+      for (int k = 0; k <= a[i].n; ++k) {
+        hsh ^= (unsigned long long)(a[i].ranks[k] * 131 + b[i].ranks[k]);
+        hsh *= 1099511628211ull;
+      }
+    sig << "|" << std::hex << hsh;
+  }
+  int variant = tune ? tune_lookup(sig.str()) : 0;
+  if (variant < 0) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(QTT_ERR_HIP);
+    float best = 1e30f;
+    variant = 0;
+    for (int v = 0; v < 4; ++v) {
+      if (hipEventRecord(e0, us) != hipSuccess || batch_run(p, us, v) != hipSuccess ||
+          hipEventRecord(e1, us) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return fail(QTT_ERR_HIP);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      p->tuned_ms[v] = ms;
+      if (ms < best) {
+        best = ms;
+        variant = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tune_store(sig.str(), variant);
+  } else {
+    // one eager run: sets kernel attributes before capture and validates the launch
+    if (batch_run(p, us, variant) != hipSuccess || hipStreamSynchronize(us) != hipSuccess) return fail(QTT_ERR_HIP);
+  }
+  p->variant = variant;
+  // capture [queue reset, persistent kernel] into a graph on a private stream
+  if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) return fail(QTT_ERR_HIP);
+  if (hipStreamSynchronize(us) != hipSuccess) return fail(QTT_ERR_HIP);
+  if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(QTT_ERR_HIP);
+  hipError_t le = batch_run(p, p->cap, variant);
+  hipError_t ce = hipStreamEndCapture(p->cap, &p->graph);
+  if (le != hipSuccess || ce != hipSuccess) return fail(QTT_ERR_HIP);
+  if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) return fail(QTT_ERR_HIP);
+  *plan = p;
+  return QTT_OK;
+}
+
+int qtt_batch_plan_launch(qtt_batch_plan plan, void* stream) {
+  if (!plan || !plan->exec) return QTT_ERR_ARG;
+  Scoped sc(plan->h->device);
+  return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? QTT_OK : QTT_ERR_HIP;
+}
+
+int qtt_batch_plan_results(qtt_batch_plan plan, int64_t* ranks, double* tails, void* stream) {
+  if (!plan || !ranks) return QTT_ERR_ARG;
+  Scoped sc(plan->h->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int c = plan->count;
+  if (hipMemcpyAsync(plan->hranks, plan->dranks, (size_t)c * (QTT_BATCH_MAXN + 1) * sizeof(long),
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(plan->htails, plan->dtails, (size_t)c * QTT_BATCH_MAXN * sizeof(double), hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
+      hipMemcpyAsync(plan->hstatus, plan->dstatus, (size_t)c * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return QTT_ERR_HIP;
+  long o = 0, ot = 0;
+  int status = QTT_OK;
+  for (int i = 0; i < c; ++i) {
+    const int n = plan->ncores[i];
+    for (int k = 0; k <= n; ++k) ranks[o + k] = plan->hranks[(long)i * (QTT_BATCH_MAXN + 1) + k];
+    o += n + 1;
+    if (tails) {
+      for (int k = 0; k + 1 < n; ++k) tails[ot + k] = plan->htails[(long)i * QTT_BATCH_MAXN + k];
+      ot += std::max(n - 1, 0);
+    }
+    if (plan->hstatus[i] == QTT_BSTATUS_NONFINITE) status = QTT_ERR_NONFINITE;
+    if (plan->hstatus[i] == QTT_BSTATUS_NOCONV && status == QTT_OK) status = QTT_ERR_NOCONV;
+  }
+  return status;
+}
+
+int qtt_batch_plan_info(qtt_batch_plan plan, int32_t* variant, int32_t* grid, float* tuned_ms) {
+  if (!plan || !variant || !grid) return QTT_ERR_ARG;
+  *variant = plan->variant;
+  *grid = plan->grid;
+  if (tuned_ms)
+    for (int v = 0; v < 4; ++v) tuned_ms[v] = plan->tuned_ms[v];
+  return QTT_OK;
+}
+
+int qtt_batch_plan_destroy(qtt_batch_plan plan) {
+  if (!plan) return QTT_ERR_ARG;
+  Scoped sc(plan->h->device);
+  batch_free(plan);
   return QTT_OK;
 }
 

@@ -1,0 +1,440 @@
+// Batched contract + round: many independent QTT products of uneven ranks in
+// one persistent launch.
+//
+// A grid of persistent workgroups (256 threads each) pulls instance indices
+// from an atomic work queue; instances are queued in decreasing order of an
+// estimated cost (sum over cores of rho^2 r_C + p^3), so that the largest
+// ones start first and the small ones fill the tail.  A workgroup runs the
+// whole pipeline of its instance with workgroup-level versions of the
+// single-chain steps:
+//   QR sweep:  bond product R_{k-1} C_k (factored, FP32 accumulation),
+//              blocked Householder QR (qr_panel_dev + apply_tile_dev);
+//   SVD sweep: Q_k [U Sigma; 0], QR of tall unfoldings, one-sided block
+//              Jacobi on the rows, device-side rank decision, V^T into the
+//              output core and U Sigma = F V (FP32 accumulation).
+// Ranks never leave the device during the launch, so the launch (with the
+// queue reset before it) can be captured in a hipGraph and replayed.
+#include "qtt_device.hpp"
+#include "qtt_internal.hpp"
+#include "qr_device.hpp"
+#include "batched.hpp"
+
+namespace qtt {
+
+namespace {
+
+constexpr int BNT = 256;
+
+struct Smem {
+  double red[BNT / 16][16][17];
+  double wsh[16][17];
+  double w2sh[16][17];
+  double tsh[16][17];
+  double scal[16];
+  int iscal[8];
+};
+
+__device__ __forceinline__ void wg_sync() { __syncthreads(); }
+
+// Y = R (rows x K, ld ldr) * B (K x N, ld N)  accumulated in FP32, stored FP64
+__device__ void wg_gemm_nn_f32(int rows, int N, int K, const double* __restrict__ R, long ldr,
+                               const double* __restrict__ B, double* __restrict__ Y) {
+  const long total = (long)rows * N;
+  for (long e = threadIdx.x; e < total; e += BNT) {
+    const long i = e / N;
+    const int j = (int)(e % N);
+    float acc = 0.f;
+    for (int k = 0; k < K; ++k) acc += (float)R[i * ldr + k] * (float)B[(long)k * N + j];
+    Y[e] = (double)acc;
+  }
+  wg_sync();
+}
+
+// Y (p x r) = F (p x L) * V^T, V = out core rows (r x L); FP32 accumulation
+__device__ void wg_gemm_nt_f32(int p, int r, int L, const double* __restrict__ F, const double* __restrict__ V,
+                               double* __restrict__ Y) {
+  const long total = (long)p * r;
+  for (long e = threadIdx.x; e < total; e += BNT) {
+    const long i = e / r;
+    const int j = (int)(e % r);
+    float acc = 0.f;
+    for (int c = 0; c < L; ++c) acc += (float)F[i * L + c] * (float)V[(long)j * L + c];
+    Y[e] = (double)acc;
+  }
+  wg_sync();
+}
+
+// Hadamard bond: M[(a,i),(b,dd)] = sum_mu Y[a,mu,i,dd] A[mu,i,b]
+// MPO bond:      M[(a,i),(b,dd)] = sum_{mu,j} Y[a,mu,j,dd] W[mu,i,j,b]
+__device__ void wg_bond_apply(bool mpo, const double* __restrict__ Y, int rho, int ra0, int d, int dj, int rb1,
+                              const double* __restrict__ A, int ra1, double* __restrict__ M) {
+  const long total = (long)rho * d * ra1 * rb1;
+  for (long e = threadIdx.x; e < total; e += BNT) {
+    long t = e;
+    const int dd = t % rb1;
+    t /= rb1;
+    const int b = t % ra1;
+    t /= ra1;
+    const int i = t % d;
+    const long a = t / d;
+    float acc = 0.f;
+    if (mpo) {
+      for (int mu = 0; mu < ra0; ++mu)
+        for (int j = 0; j < dj; ++j)
+          acc += (float)Y[((a * ra0 + mu) * dj + j) * rb1 + dd] * (float)A[(((long)mu * d + i) * dj + j) * ra1 + b];
+    } else {
+      for (int mu = 0; mu < ra0; ++mu)
+        acc += (float)Y[((a * ra0 + mu) * d + i) * rb1 + dd] * (float)A[((long)mu * d + i) * ra1 + b];
+    }
+    M[e] = (double)acc;
+  }
+  wg_sync();
+}
+
+__device__ void wg_copy_pad(const double* __restrict__ src, int rows, int cols, long lds, double* __restrict__ dst,
+                            int rows_out, long ldd) {
+  const long n = (long)rows_out * cols;
+  for (long e = threadIdx.x; e < n; e += BNT) {
+    const long r = e / cols;
+    const int c = (int)(e % cols);
+    dst[r * ldd + c] = (r < rows) ? src[r * lds + c] : 0.0;
+  }
+  wg_sync();
+}
+
+__device__ void wg_extract_r(const double* __restrict__ A, int kr, int n, long lda, double* __restrict__ R) {
+  const long total = (long)kr * n;
+  for (long e = threadIdx.x; e < total; e += BNT) {
+    const long i = e / n;
+    const int j = (int)(e % n);
+    R[e] = (j >= i) ? A[i * lda + j] : 0.0;
+  }
+  wg_sync();
+}
+
+// Householder QR of A (m x n, m <= 512) by this workgroup, T blocks in Tbuf.
+__device__ void wg_householder_qr(double* __restrict__ A, int m, int n, long lda, double* __restrict__ Tbuf, Smem& sm) {
+  const int kmax = min(m, n);
+  for (int j0 = 0, p = 0; j0 < kmax; j0 += 16, ++p) {
+    const int pw = min(16, kmax - j0);
+    double* T = Tbuf + (long)p * 256;
+    if (m - j0 <= 256)
+      qr_panel_dev<BNT, 1, 16>(A, lda, m, j0, pw, T);
+    else
+      qr_panel_dev<BNT, 2, 16>(A, lda, m, j0, pw, T);
+    wg_sync();
+    for (int c0 = j0 + pw; c0 < n; c0 += 16)
+      apply_tile_dev<BNT>(A + (long)j0 * lda + j0, lda, m - j0, pw, T, A + (long)j0 * lda, lda, c0, n, 1, sm.red,
+                          sm.wsh, sm.w2sh, sm.tsh);
+  }
+}
+
+// Y <- Q Y for the reflectors stored in A (m rows, kref reflectors).
+__device__ void wg_apply_q(const double* __restrict__ A, int m, int kref, long lda, const double* __restrict__ Tbuf,
+                           double* __restrict__ Y, int ncols, long ldy, Smem& sm) {
+  const int np = (kref + 15) / 16;
+  for (int p = np - 1; p >= 0; --p) {
+    const int j0 = 16 * p, pw = min(16, kref - j0);
+    for (int c0 = 0; c0 < ncols; c0 += 16)
+      apply_tile_dev<BNT>(A + (long)j0 * lda + j0, lda, m - j0, pw, Tbuf + (long)p * 256, Y + (long)j0 * ldy, ldy, c0,
+                          ncols, 0, sm.red, sm.wsh, sm.w2sh, sm.tsh);
+  }
+}
+
+__device__ __forceinline__ int rr_item(int pos, int round, int n) {
+  return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (n - 1));
+}
+
+// One-sided Jacobi on the rows of X (p x L) by this workgroup; blocks of JB
+// rows, block pairs visited sequentially, each pair staged in LDS.  Returns
+// the sweep count (max_sweeps when not converged).
+template <int JB>
+__device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restrict__ sh, int max_sweeps, double tol,
+                         Smem& sm) {
+  constexpr int JR = 2 * JB;
+  const int nblk = (p + JB - 1) / JB;
+  const int nb2 = nblk + (nblk & 1);
+  const int npairs = nb2 / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) sm.iscal[0] = 0;
+    wg_sync();
+    for (int round = 0; round < max(nb2 - 1, 1); ++round) {
+      for (int pair = 0; pair < npairs; ++pair) {
+        const int b0 = rr_item(pair, round, nb2);
+        const int b1 = (nb2 > 1) ? rr_item(nb2 - 1 - pair, round, nb2) : 1;
+        for (int e = tid; e < JR * L; e += BNT) {
+          const int t = e / L, c = e % L;
+          const int gr = (t < JB ? b0 : b1) * JB + (t % JB);
+          sh[t * L + c] = (gr < p) ? X[(long)gr * L + c] : 0.0;
+        }
+        wg_sync();
+        int rot = 0;
+        for (int ir = 0; ir < JR - 1; ++ir) {
+          for (int q = wave; q < JB; q += BNT / 64) {
+            const int ra = rr_item(q, ir, JR);
+            const int rc = rr_item(JR - 1 - q, ir, JR);
+            double* xa = sh + ra * L;
+            double* xc = sh + rc * L;
+            double al = 0.0, be = 0.0, ga = 0.0;
+            for (int c = lane; c < L; c += 64) {
+              const double u = xa[c], w = xc[c];
+              al += u * u;
+              be += w * w;
+              ga += u * w;
+            }
+            al = wave_sum(al);
+            be = wave_sum(be);
+            ga = wave_sum(ga);
+            if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+              const double zeta = (be - al) / (2.0 * ga);
+              const double t = (fabs(zeta) > 1e150) ? 0.5 / zeta
+                                                    : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+              const double cs = 1.0 / sqrt(1.0 + t * t);
+              const double sn = cs * t;
+              for (int c = lane; c < L; c += 64) {
+                const double u = xa[c], w = xc[c];
+                xa[c] = cs * u - sn * w;
+                xc[c] = sn * u + cs * w;
+              }
+              ++rot;
+            }
+          }
+          wg_sync();
+        }
+        if (lane == 0 && rot) atomicAdd(&sm.iscal[0], rot);
+        for (int e = tid; e < JR * L; e += BNT) {
+          const int t = e / L, c = e % L;
+          const int gr = (t < JB ? b0 : b1) * JB + (t % JB);
+          if (gr < p) X[(long)gr * L + c] = sh[t * L + c];
+        }
+        wg_sync();
+      }
+    }
+    const int tot = sm.iscal[0];
+    wg_sync();
+    if (tot == 0) {
+      ++sweep;
+      break;
+    }
+  }
+  return sweep;
+}
+
+// sigma (sorted descending) and perm of the row norms of X (p x L).
+__device__ void wg_norms_sort(const double* __restrict__ X, int p, int L, double* __restrict__ sig,
+                              int* __restrict__ perm, double* __restrict__ tmp) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < p; i += BNT / 64) {
+    double s = 0.0;
+    for (int c = lane; c < L; c += 64) {
+      const double v = X[(long)i * L + c];
+      s += v * v;
+    }
+    s = wave_sum(s);
+    if (lane == 0) tmp[i] = sqrt(s);
+  }
+  wg_sync();
+  for (int i = threadIdx.x; i < p; i += BNT) {
+    const double si = tmp[i];
+    int pos = 0;
+    for (int j = 0; j < p; ++j) {
+      const double sj = tmp[j];
+      pos += (sj > si) || (sj == si && j < i);
+    }
+    perm[pos] = i;
+    sig[pos] = si;
+  }
+  wg_sync();
+}
+
+template <int JB>
+__device__ void process_instance(const BInst& I, double rel_tol, long max_rank, double* __restrict__ sh, Smem& sm,
+                                 long* __restrict__ ranks_out, double* __restrict__ tail_out, int* __restrict__ status) {
+  const int n = I.n;
+  double* ws = I.ws;
+  double* R = ws + I.offR;
+  double* Yb = ws + I.offY;
+  double* one = ws + I.offOne;
+  const bool mpo = I.mpo != 0;
+  const int tid = threadIdx.x;
+  // ---------------- QR sweep
+  for (int k = 0; k < n; ++k) {
+    const int rho0 = I.rho[k];
+    const int cols = I.ra[k + 1] * I.rb[k + 1];
+    const bool last = (k == n - 1);
+    double* M = last ? ws + I.offCenter : ws + I.offM[k];
+    const int ra0 = I.ra[k], ra1 = I.ra[k + 1], rb0 = I.rb[k], rb1 = I.rb[k + 1];
+    const int d = I.d[k], dj = I.dj[k];
+    const double* Rk = R;
+    if (k == 0) {
+      if (tid == 0) one[0] = 1.0;
+      wg_sync();
+      Rk = one;
+    }
+    wg_gemm_nn_f32(rho0 * ra0, dj * rb1, rb0, Rk, rb0, I.b[k], Yb);
+    wg_bond_apply(mpo, Yb, rho0, ra0, d, dj, rb1, I.a[k], ra1, M);
+    if (!last) {
+      const int m = rho0 * d;
+      wg_householder_qr(M, m, cols, cols, ws + I.offT[k], sm);
+      wg_extract_r(M, I.rho[k + 1], cols, cols, R);
+    }
+  }
+  // norm of the centre
+  {
+    const double* c = ws + I.offCenter;
+    const long cnt = (long)I.rho[n - 1] * I.d[n - 1];
+    double s = 0.0;
+    for (long e = tid; e < cnt; e += BNT) s += c[e] * c[e];
+    s = block_sum<BNT>(s, sm.scal);
+    if (tid == 0) sm.scal[8] = sqrt(s);
+    wg_sync();
+  }
+  const double nrm = sm.scal[8];
+  if (!(nrm == nrm) || nrm > 1.7e308) {
+    if (tid == 0) status[0] = QTT_BSTATUS_NONFINITE;
+    return;
+  }
+  const double delta = (n > 1) ? rel_tol * nrm / sqrt((double)(n - 1)) : 0.0;
+  double* Z = ws + I.offZ;
+  double* X = ws + I.offX;
+  double* Xc = ws + I.offXc;
+  double* Yn = ws + I.offYn;
+  double* TB = ws + I.offTB;
+  double* sig = ws + I.offSig;
+  int* perm = (int*)(ws + I.offPerm);
+  double* tmp = ws + I.offTmp;
+  const double eps = 2.220446049250313e-16;
+  int rnext = 1;
+  if (tid == 0) {
+    ranks_out[0] = 1;
+    ranks_out[n] = 1;
+    status[0] = QTT_BSTATUS_OK;
+  }
+  for (int k = n - 1; k >= 1; --k) {
+    const int rows = I.rho[k];
+    const int D = I.d[k] * rnext;
+    const double* B;
+    if (k == n - 1) {
+      B = ws + I.offCenter;
+    } else {
+      wg_copy_pad(Yn, I.rho[k + 1], rnext, rnext, Z, I.m[k], rnext);
+      wg_apply_q(ws + I.offM[k], I.m[k], I.rho[k + 1], (long)I.ra[k + 1] * I.rb[k + 1], ws + I.offT[k], Z, rnext,
+                 rnext, sm);
+      B = Z;
+    }
+    const bool tall = rows >= D;
+    const int L = D;
+    int p;
+    if (tall) {
+      if (B != Z) wg_copy_pad(B, rows, D, D, Z, rows, D);
+      wg_householder_qr(Z, rows, D, D, TB, sm);
+      wg_extract_r(Z, D, D, D, X);
+      p = D;
+    } else {
+      wg_copy_pad(B, rows, D, D, X, rows, D);
+      p = rows;
+    }
+    wg_copy_pad(X, p, L, L, Xc, p, L);
+    const int sweeps = wg_jacobi<JB>(X, p, L, sh, QTT_BATCH_MAX_SWEEPS, eps * sqrt((double)L), sm);
+    if (sweeps >= QTT_BATCH_MAX_SWEEPS && tid == 0) status[0] = QTT_BSTATUS_NOCONV;
+    wg_norms_sort(X, p, L, sig, perm, tmp);
+    // rank decision (smallest r with discarded 2-norm <= delta, capped)
+    if (tid == 0) {
+      int r = p;
+      double acc = 0.0;
+      for (int cand = p; cand >= 1; --cand) {
+        if (sqrt(acc) <= delta)
+          r = cand;
+        else
+          break;
+        acc += sig[cand - 1] * sig[cand - 1];
+      }
+      if (max_rank > 0 && r > max_rank) r = (int)max_rank;
+      if (r < 1) r = 1;
+      double t2 = 0.0;
+      for (int i = p - 1; i >= r; --i) t2 += sig[i] * sig[i];
+      sm.iscal[1] = r;
+      tail_out[k - 1] = sqrt(t2);
+    }
+    wg_sync();
+    const int r = sm.iscal[1];
+    double* core = I.out[k];
+    for (long e = tid; e < (long)r * L; e += BNT) {
+      const int j = (int)(e / L), c = (int)(e % L);
+      const double s = sig[j];
+      core[(long)j * L + c] = (s > 0.0) ? X[(long)perm[j] * L + c] / s : 0.0;
+    }
+    wg_sync();
+    wg_gemm_nt_f32(p, r, L, Xc, core, Yn);
+    if (tall) {
+      for (long e = tid; e < (long)(rows - p) * r; e += BNT) Yn[(long)p * r + e] = 0.0;
+      wg_sync();
+      wg_apply_q(Z, rows, p, D, TB, Yn, r, r, sm);
+    }
+    if (tid == 0) ranks_out[k] = r;
+    rnext = r;
+  }
+  if (n == 1) {
+    wg_copy_pad(ws + I.offCenter, 1, I.d[0], I.d[0], I.out[0], 1, I.d[0]);
+  } else {
+    wg_copy_pad(Yn, I.rho[1], rnext, rnext, Z, I.m[0], rnext);
+    wg_apply_q(ws + I.offM[0], I.m[0], I.rho[1], (long)I.ra[1] * I.rb[1], ws + I.offT[0], Z, rnext, rnext, sm);
+    wg_copy_pad(Z, I.m[0], rnext, rnext, I.out[0], I.m[0], rnext);
+  }
+}
+
+template <int JB>
+__global__ __launch_bounds__(BNT) void k_batched(const BInst* __restrict__ insts, const int* __restrict__ order,
+                                                 int count, unsigned* __restrict__ queue, double rel_tol,
+                                                 long max_rank, long* __restrict__ ranks_out,
+                                                 double* __restrict__ tails_out, int* __restrict__ status) {
+  extern __shared__ double sh[];
+  __shared__ Smem sm;
+  __shared__ int s_idx;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int idx = s_idx;
+    __syncthreads();
+    if (idx >= count) break;
+    const int inst = order[idx];
+    process_instance<JB>(insts[inst], rel_tol, max_rank, sh, sm, ranks_out + (long)inst * (QTT_BATCH_MAXN + 1),
+                         tails_out + (long)inst * QTT_BATCH_MAXN, status + inst);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t batched_launch(hipStream_t s, int variant, int grid, const BInst* insts, const int* order, int count,
+                          unsigned* queue, double rel_tol, long max_rank, long* ranks_out, double* tails_out,
+                          int* status, int max_L) {
+  hipError_t e = fill_u32(s, queue, 0u, 1);
+  if (e != hipSuccess) return e;
+  const int jb = (variant & 1) ? 4 : 8;
+  const size_t shmem = (size_t)2 * jb * max_L * sizeof(double);
+  if (shmem > 96 * 1024) return hipErrorInvalidValue;
+  static bool attr4 = false, attr8 = false;
+  if (jb == 4) {
+    if (!attr4) {
+      e = hipFuncSetAttribute((const void*)k_batched<4>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+      if (e != hipSuccess) return e;
+      attr4 = true;
+    }
+    hipLaunchKernelGGL(k_batched<4>, dim3(grid), dim3(BNT), shmem, s, insts, order, count, queue, rel_tol, max_rank,
+                       ranks_out, tails_out, status);
+  } else {
+    if (!attr8) {
+      e = hipFuncSetAttribute((const void*)k_batched<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+      if (e != hipSuccess) return e;
+      attr8 = true;
+    }
+    hipLaunchKernelGGL(k_batched<8>, dim3(grid), dim3(BNT), shmem, s, insts, order, count, queue, rel_tol, max_rank,
+                       ranks_out, tails_out, status);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qtt

@@ -1,0 +1,33 @@
+// Instance descriptor of the batched persistent kernel (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace qtt {
+
+constexpr int QTT_BATCH_MAXN = 32;        // cores per instance
+constexpr int QTT_BATCH_MAX_SWEEPS = 40;  // Jacobi sweep cap
+constexpr int QTT_BSTATUS_OK = 0, QTT_BSTATUS_NONFINITE = 1, QTT_BSTATUS_NOCONV = 2;
+
+struct BInst {
+  const double* a[QTT_BATCH_MAXN];
+  const double* b[QTT_BATCH_MAXN];
+  double* out[QTT_BATCH_MAXN];
+  double* ws;  // this instance's workspace (offsets below are in doubles)
+  long offM[QTT_BATCH_MAXN], offT[QTT_BATCH_MAXN];
+  long offCenter, offR, offY, offZ, offX, offXc, offYn, offTB, offSig, offPerm, offTmp, offOne;
+  int ra[QTT_BATCH_MAXN + 1], rb[QTT_BATCH_MAXN + 1];
+  int rho[QTT_BATCH_MAXN + 1];
+  int m[QTT_BATCH_MAXN];
+  int d[QTT_BATCH_MAXN], dj[QTT_BATCH_MAXN];
+  int n;
+  int mpo;
+};
+
+// Reset the work queue and launch the persistent kernel (variant bit 0:
+// Jacobi blocks of 4 rows instead of 8).  max_L bounds the Jacobi row length.
+hipError_t batched_launch(hipStream_t s, int variant, int grid, const BInst* insts, const int* order, int count,
+                          unsigned* queue, double rel_tol, long max_rank, long* ranks_out, double* tails_out,
+                          int* status, int max_L);
+
+}  // namespace qtt

@@ -1,20 +1,13 @@
 // Blocked Householder QR for the rounding sweep (FP64).
 //
-// Row-major A (m x n).  Panels of up to 16 columns are factored by a single
-// workgroup holding the panel in registers (each thread owns RPT rows of
-// the panel), one Householder reflector per column:
-//     x = A[j:m, j], beta = -sign(x0) ||x||, tau = (beta - x0)/beta,
-//     v = x / (x0 - beta) with v0 = 1,   H = I - tau v v^T,   H x = beta e0
-// (tau = 0, H = I when x has no entries below the diagonal).  The same
-// workgroup reduction that forms v^T A for the update also yields the
-// column V^T v_j, from which the compact-WY factor T (H_1..H_b = I - V T V^T,
-// T upper triangular) is built column by column.
-//
-// The trailing update and every later application of Q or Q^T use one fused
-// kernel: each workgroup owns 16 columns of the target and all its rows, so
-// W = V^T Y, W <- op(T) W and Y <- Y - V W need no grid-wide reduction.
+// Panels of up to 16 columns are factored by one workgroup (qr_panel_dev in
+// qr_device.hpp).  The trailing update and every later application of Q or
+// Q^T go through apply_block: a pair of kernels split over 16-column tiles
+// and 256-row chunks (W = V^T Y per chunk, then reduction, op(T) and the
+// rank-pw update), so that narrow targets still occupy the whole GPU.
 #include "qtt_device.hpp"
 #include "qtt_internal.hpp"
+#include "qr_device.hpp"
 
 #include <algorithm>
 
@@ -23,142 +16,47 @@ namespace qtt {
 namespace {
 
 template <int NT, int RPT, int PW>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_qr_panel(double* __restrict__ A, long lda, int m, int j0, int pw,
-                                                 double* __restrict__ Tout) {
-  constexpr int NW = NT / 64;
-  __shared__ double red[NT];
-  __shared__ double bc[16];
-  __shared__ double sc[NW];
-  __shared__ double Ts[16][17];
-  __shared__ double alphaS;
-  const int tid = threadIdx.x;
-  const int mp = m - j0;
-  double a[RPT][PW];
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int lr = tid + r * NT;
-#pragma unroll
-    for (int c = 0; c < PW; ++c) a[r][c] = (lr < mp && c < pw) ? A[(long)(j0 + lr) * lda + j0 + c] : 0.0;
-  }
-  for (int t = tid; t < 16 * 17; t += NT) (&Ts[0][0])[t] = 0.0;
-
-#pragma unroll
-  for (int j = 0; j < PW; ++j) {
-    if (j < pw) {
-      double s = 0.0;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int lr = tid + r * NT;
-        if (lr > j && lr < mp) s += a[r][j] * a[r][j];
-      }
-      if (tid == j) alphaS = a[0][j];
-      s = block_sum<NT>(s, sc);
-      const double alpha = alphaS;
-      double tau, beta, scale;
-      if (s == 0.0) {
-        tau = 0.0;
-        beta = alpha;
-        scale = 0.0;
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + s), alpha);
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int lr = tid + r * NT;
-        if (lr > j && lr < mp) a[r][j] *= scale;
-      }
-      if (tid == j) a[0][j] = beta;
-      // p[c] (c > j): v_j^T A[:, c];  p[c] (c < j): v_c^T v_j  (column j of V^T V)
-      double p[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) p[c] = 0.0;
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int lr = tid + r * NT;
-        if (lr >= j && lr < mp) {
-          const double v = (lr == j) ? 1.0 : a[r][j];
-#pragma unroll
-          for (int c = 0; c < PW; ++c) {
-            if (c > j) {
-              p[c] += v * a[r][c];
-            } else if (c < j) {
-              const double vc = (lr > c) ? a[r][c] : (lr == c ? 1.0 : 0.0);
-              p[c] += v * vc;
-            }
-          }
-        }
-      }
-      block_sum16<NT>(p, red, bc);
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int lr = tid + r * NT;
-        if (lr >= j && lr < mp) {
-          const double v = (lr == j) ? 1.0 : a[r][j];
-#pragma unroll
-          for (int c = 0; c < PW; ++c)
-            if (c > j) a[r][c] -= tau * v * bc[c];
-        }
-      }
-      // T[0:j, j] = -tau T[0:j, 0:j] (V^T v_j)[0:j],  T[j][j] = tau
-      if (tid < j) {
-        double acc = 0.0;
-        for (int l = tid; l < j; ++l) acc += Ts[tid][l] * bc[l];
-        Ts[tid][j] = -tau * acc;
-      }
-      if (tid == j) Ts[j][j] = tau;
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int lr = tid + r * NT;
-    if (lr < mp) {
-#pragma unroll
-      for (int c = 0; c < PW; ++c)
-        if (c < pw) A[(long)(j0 + lr) * lda + j0 + c] = a[r][c];
-    }
-  }
-  for (int t = tid; t < 256; t += NT) Tout[t] = Ts[t >> 4][t & 15];
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_qr_panel(
+    double* __restrict__ A, long lda, int m, int j0, int pw, double* __restrict__ Tout) {
+  qr_panel_dev<NT, RPT, PW>(A, lda, m, j0, pw, Tout);
 }
 
-// Apply the block reflector of one panel to 16-column tiles of Y.
-//   V: rows [r0, r0+mp) of A, columns [vc0, vc0+pw), unit lower trapezoidal.
-//   Y rows [yr0, yr0+mp), columns [c0, c0+ncols).
-//   trans: Y <- (I - V T^T V^T) Y  else  Y <- (I - V T V^T) Y.
-// 512 threads: thread (g, c) owns column c of the tile and the rows
-// lr = g (mod 32); rows are streamed four at a time so that several loads
-// are in flight per thread.
-constexpr int AP_NT = 512, AP_G = AP_NT / 16;
+inline void apply_cost(int mp, int pw, int ncols, double& bytes, double& flops);
+
+// Block-reflector application, split over (16-column tile) x (row chunk)
+// workgroups so that even a narrow target keeps the whole GPU busy:
+//   k_apply_w:   W_chunk = V_chunk^T Y_chunk  (16 x 16 per workgroup, stored
+//                per chunk in scratch[chunk][16][ncols]);
+//   k_apply_upd: W = sum_chunk W_chunk, W <- op(T) W, Y_chunk -= V_chunk W.
+// V: rows [r0, r0+mp) of A, columns [vc0, vc0+pw), unit lower trapezoidal.
+// Y rows [yr0, yr0+mp), columns [c0, c0+ncols).
+// trans: Y <- (I - V T^T V^T) Y, else Y <- (I - V T V^T) Y.
+// 256 threads: thread (g, c) owns column c of the tile and rows g (mod 16)
+// of the chunk; rows are streamed four at a time.
+constexpr int AP_NT = 256, AP_G = AP_NT / 16, AP_CHUNK = 256;
 
 __device__ __forceinline__ void load_vrow(const double* __restrict__ arow, int lr, int pw, double (&v)[16]) {
 #pragma unroll
   for (int i = 0; i < 16; ++i) v[i] = (i >= pw) ? 0.0 : (lr > i ? arow[i] : (lr == i ? 1.0 : 0.0));
 }
 
-__global__ __launch_bounds__(AP_NT) void k_apply_panel(const double* __restrict__ A, long lda, int r0, int mp,
-                                                       int vc0, int pw, const double* __restrict__ T,
-                                                       double* __restrict__ Y, long ldy, int yr0, int c0,
-                                                       int ncols, int trans) {
-  __shared__ double part[AP_G][16][17];
-  __shared__ double Ws[16][17];
-  __shared__ double W2[16][17];
-  __shared__ double Tsh[16][17];
+__global__ __launch_bounds__(AP_NT) void k_apply_w(const double* __restrict__ A, long lda, int r0, int mp, int vc0,
+                                                   int pw, const double* __restrict__ Y, long ldy, int yr0, int c0,
+                                                   int ncols, int ntiles, double* __restrict__ part) {
+  __shared__ double red[AP_G][16][17];
   const int tid = threadIdx.x;
   const int c = tid & 15, g = tid >> 4;
-  const int gc = c0 + blockIdx.x * 16 + c;
-  const bool valid = gc < c0 + ncols;
-  if (tid < 256) Tsh[tid >> 4][tid & 15] = T[tid];
+  const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
+  const int col = tile * 16 + c;
+  const bool valid = col < ncols;
+  const int rbeg = chunk * AP_CHUNK, rend = min(mp, rbeg + AP_CHUNK);
   const double* Ab = A + (long)r0 * lda + vc0;
-  double* Yb = Y + (long)yr0 * ldy + gc;
-
-  // phase 1: w[i] = sum_rows V[lr][i] * Y[lr][c]
+  const double* Yb = Y + (long)yr0 * ldy + c0 + col;
   double w[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) w[i] = 0.0;
-  int lr = g;
-  for (; lr + 3 * AP_G < mp; lr += 4 * AP_G) {
+  int lr = rbeg + g;
+  for (; lr + 3 * AP_G < rend; lr += 4 * AP_G) {
     double y[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) y[q] = valid ? Yb[(long)(lr + q * AP_G) * ldy] : 0.0;
@@ -170,7 +68,7 @@ __global__ __launch_bounds__(AP_NT) void k_apply_panel(const double* __restrict_
       for (int i = 0; i < 16; ++i) w[i] += v[i] * y[q];
     }
   }
-  for (; lr < mp; lr += AP_G) {
+  for (; lr < rend; lr += AP_G) {
     const double y = valid ? Yb[(long)lr * ldy] : 0.0;
     double v[16];
     load_vrow(Ab + (long)lr * lda, lr, pw, v);
@@ -178,30 +76,55 @@ __global__ __launch_bounds__(AP_NT) void k_apply_panel(const double* __restrict_
     for (int i = 0; i < 16; ++i) w[i] += v[i] * y;
   }
 #pragma unroll
-  for (int i = 0; i < 16; ++i) part[g][i][c] = w[i];
+  for (int i = 0; i < 16; ++i) red[g][i][c] = w[i];
   __syncthreads();
-  if (tid < 256) {
+  {
     const int i = tid >> 4, cc = tid & 15;
-    double s = 0.0;
+    double sum = 0.0;
 #pragma unroll
-    for (int q = 0; q < AP_G; ++q) s += part[q][i][cc];
-    Ws[i][cc] = s;
+    for (int q = 0; q < AP_G; ++q) sum += red[q][i][cc];
+    if (tile * 16 + cc < ncols) part[((long)chunk * 16 + i) * ncols + tile * 16 + cc] = sum;
+  }
+}
+
+__global__ __launch_bounds__(AP_NT) void k_apply_upd(const double* __restrict__ A, long lda, int r0, int mp, int vc0,
+                                                     int pw, const double* __restrict__ T, double* __restrict__ Y,
+                                                     long ldy, int yr0, int c0, int ncols, int ntiles, int nchunks,
+                                                     const double* __restrict__ part, int trans) {
+  __shared__ double Ws[16][17];
+  __shared__ double W2[16][17];
+  __shared__ double Tsh[16][17];
+  const int tid = threadIdx.x;
+  const int c = tid & 15, g = tid >> 4;
+  const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
+  const int col = tile * 16 + c;
+  const bool valid = col < ncols;
+  Tsh[tid >> 4][tid & 15] = T[tid];
+  {
+    const int i = tid >> 4, cc = tid & 15;
+    double sum = 0.0;
+    if (tile * 16 + cc < ncols)
+      for (int q = 0; q < nchunks; ++q) sum += part[((long)q * 16 + i) * ncols + tile * 16 + cc];
+    Ws[i][cc] = sum;
   }
   __syncthreads();
-  if (tid < 256) {
+  {
     const int i = tid >> 4, cc = tid & 15;
-    double s = 0.0;
+    double sum = 0.0;
 #pragma unroll
-    for (int l = 0; l < 16; ++l) s += (trans ? Tsh[l][i] : Tsh[i][l]) * Ws[l][cc];
-    W2[i][cc] = s;
+    for (int l = 0; l < 16; ++l) sum += (trans ? Tsh[l][i] : Tsh[i][l]) * Ws[l][cc];
+    W2[i][cc] = sum;
   }
   __syncthreads();
   if (!valid) return;
-  // phase 3: Y[lr][c] -= sum_i V[lr][i] W2[i][c]
+  double w[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) w[i] = W2[i][c];
-  lr = g;
-  for (; lr + 3 * AP_G < mp; lr += 4 * AP_G) {
+  const int rbeg = chunk * AP_CHUNK, rend = min(mp, rbeg + AP_CHUNK);
+  const double* Ab = A + (long)r0 * lda + vc0;
+  double* Yb = Y + (long)yr0 * ldy + c0 + col;
+  int lr = rbeg + g;
+  for (; lr + 3 * AP_G < rend; lr += 4 * AP_G) {
     double y[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) y[q] = Yb[(long)(lr + q * AP_G) * ldy];
@@ -209,20 +132,42 @@ __global__ __launch_bounds__(AP_NT) void k_apply_panel(const double* __restrict_
     for (int q = 0; q < 4; ++q) {
       double v[16];
       load_vrow(Ab + (long)(lr + q * AP_G) * lda, lr + q * AP_G, pw, v);
-      double s = 0.0;
+      double sum = 0.0;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) s += v[i] * w[i];
-      Yb[(long)(lr + q * AP_G) * ldy] = y[q] - s;
+      for (int i = 0; i < 16; ++i) sum += v[i] * w[i];
+      Yb[(long)(lr + q * AP_G) * ldy] = y[q] - sum;
     }
   }
-  for (; lr < mp; lr += AP_G) {
+  for (; lr < rend; lr += AP_G) {
     double v[16];
     load_vrow(Ab + (long)lr * lda, lr, pw, v);
-    double s = 0.0;
+    double sum = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) s += v[i] * w[i];
-    Yb[(long)lr * ldy] -= s;
+    for (int i = 0; i < 16; ++i) sum += v[i] * w[i];
+    Yb[(long)lr * ldy] -= sum;
   }
+}
+
+// One block-reflector application (two launches).
+hipError_t apply_block(hipStream_t s, const double* A, long lda, int r0, int mp, int vc0, int pw, const double* T,
+                       double* Y, long ldy, int yr0, int c0, int ncols, int trans, double* scratch) {
+  const int ntiles = (ncols + 15) / 16;
+  const int nchunks = (mp + AP_CHUNK - 1) / AP_CHUNK;
+  if (prof::active(prof::APPLY_PANEL)) {
+    double b, f;
+    apply_cost(mp, pw, ncols, b, f);
+    prof::begin(s, prof::APPLY_PANEL, b, f);
+  }
+  hipLaunchKernelGGL(k_apply_w, dim3(ntiles * nchunks), dim3(AP_NT), 0, s, A, lda, r0, mp, vc0, pw, (const double*)Y,
+                     ldy, yr0, c0, ncols, ntiles, scratch);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_apply_upd, dim3(ntiles * nchunks), dim3(AP_NT), 0, s, A, lda, r0, mp, vc0, pw, T, Y, ldy,
+                       yr0, c0, ncols, ntiles, nchunks, (const double*)scratch, trans);
+    e = hipGetLastError();
+  }
+  prof::end(s);
+  return e;
 }
 
 __global__ void k_extract_r(const double* __restrict__ A, int kr, int n, long lda, double* __restrict__ R) {
@@ -232,6 +177,14 @@ __global__ void k_extract_r(const double* __restrict__ A, int kr, int n, long ld
     const int j = (int)(e % n);
     R[e] = (j >= i) ? A[i * lda + j] : 0.0;
   }
+}
+
+// Algorithmic cost of one block-reflector application to an mp x ncols
+// block: read and write the block once, read V and T once;
+// W = V^T Y, W <- op(T) W, Y <- Y - V W.
+inline void apply_cost(int mp, int pw, int ncols, double& bytes, double& flops) {
+  bytes = 8.0 * (2.0 * mp * ncols + (double)mp * pw + 256.0);
+  flops = 4.0 * mp * pw * (double)ncols + 2.0 * pw * pw * (double)ncols;
 }
 
 struct PanelCfg {
@@ -274,12 +227,16 @@ int qr_num_panels(int m, int n) {
   return cnt;
 }
 
-hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf) {
+hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf, double* scratch) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (m > 4096) return hipErrorInvalidValue;
   const int kmax = std::min(m, n);
   return for_each_panel(m, kmax, [&](int p, int j0, int pw, PanelCfg c) -> hipError_t {
     double* T = Tbuf + (long)p * 256;
+    if (prof::active(prof::QR_PANEL)) {
+      const double mp = m - j0;
+      prof::begin(s, prof::QR_PANEL, 8.0 * 2.0 * mp * pw, 4.0 * mp * pw * pw);
+    }
     if (c.nt == 256 && c.rpt == 1)
       hipLaunchKernelGGL((k_qr_panel<256, 1, 16>), dim3(1), dim3(256), 0, s, A, lda, m, j0, pw, T);
     else if (c.nt == 256 && c.rpt == 2)
@@ -291,20 +248,17 @@ hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, doub
     else
       hipLaunchKernelGGL((k_qr_panel<1024, 4, 8>), dim3(1), dim3(1024), 0, s, A, lda, m, j0, pw, T);
     hipError_t e = hipGetLastError();
+    prof::end(s);
     if (e != hipSuccess) return e;
     const int c0 = j0 + pw;
     const int nc = n - c0;
-    if (nc > 0) {
-      hipLaunchKernelGGL(k_apply_panel, dim3((nc + 15) / 16), dim3(AP_NT), 0, s, (const double*)A, lda, j0, m - j0,
-                         j0, pw, (const double*)T, A, lda, j0, c0, nc, 1);
-      e = hipGetLastError();
-    }
+    if (nc > 0) e = apply_block(s, A, lda, j0, m - j0, j0, pw, T, A, lda, j0, c0, nc, 1, scratch);
     return e;
   });
 }
 
 hipError_t apply_q(hipStream_t s, const double* A, int m, int kref, long lda, const double* Tbuf, double* Y,
-                   int ncols, long ldy, bool trans) {
+                   int ncols, long ldy, bool trans, double* scratch) {
   if (m <= 0 || ncols <= 0 || kref <= 0) return hipSuccess;
   struct P {
     int p, j0, pw;
@@ -317,9 +271,8 @@ hipError_t apply_q(hipStream_t s, const double* A, int m, int kref, long lda, co
   });
   for (int t = 0; t < np; ++t) {
     const P& q = trans ? list[t] : list[np - 1 - t];
-    hipLaunchKernelGGL(k_apply_panel, dim3((ncols + 15) / 16), dim3(AP_NT), 0, s, A, lda, q.j0, m - q.j0, q.j0, q.pw,
-                       Tbuf + (long)q.p * 256, Y, ldy, q.j0, 0, ncols, trans ? 1 : 0);
-    hipError_t e = hipGetLastError();
+    hipError_t e = apply_block(s, A, lda, q.j0, m - q.j0, q.j0, q.pw, Tbuf + (long)q.p * 256, Y, ldy, q.j0, 0, ncols,
+                               trans ? 1 : 0, scratch);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

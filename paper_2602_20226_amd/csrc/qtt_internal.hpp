@@ -51,12 +51,14 @@ hipError_t contract_backward_w(hipStream_t s, bool mpo, const T* X, int rx0, int
 constexpr int QR_PB = 16;  // panel width (reflectors per T block)
 // Blocked Householder QR of the m x n row-major matrix A (in place).  Reflector
 // vectors below the diagonal, R on and above; T blocks (QR_PB x QR_PB each,
-// one per panel) in Tbuf.  Supports m <= 4096.
-hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf);
-// Y[r0.., c0..c1) <- (I - V op(T) V^T) ... for every panel: Q*Y (trans=false,
-// panels in reverse order) or Q^T*Y (trans=true, forward order).  Y has m rows.
+// one per panel) in Tbuf.  Supports m <= 4096.  scratch: qr_scratch_doubles(n).
+hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf, double* scratch);
+// Y <- Q Y (trans=false, panels in reverse order) or Q^T Y (trans=true,
+// forward order); Y has m rows.  scratch: qr_scratch_doubles(ncols).
 hipError_t apply_q(hipStream_t s, const double* A, int m, int kref, long lda, const double* Tbuf,
-                   double* Y, int ncols, long ldy, bool trans);
+                   double* Y, int ncols, long ldy, bool trans, double* scratch);
+// Partial-product scratch of one block-reflector application on ncols columns.
+inline long qr_scratch_doubles(long ncols) { return 16L * 16L * (ncols < 1 ? 1 : ncols); }
 // R = upper trapezoid of A[0:kr, 0:n] (zeros below the diagonal) into Rout (ld n).
 hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, double* Rout);
 
@@ -67,6 +69,8 @@ hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, do
 // used go to *sweeps_dev.
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
                        int* sweeps_dev);
+// dst[j] = src[perm[j]] (row gather).
+hipError_t permute_rows(hipStream_t s, const double* src, int p, int L, const int* perm, double* dst);
 // sigma_i = ||X_i||, perm = argsort descending (stable on ties).
 hipError_t row_norms_sorted(hipStream_t s, const double* X, int p, int L, double* sig_sorted,
                             int* perm);
@@ -98,5 +102,15 @@ hipError_t truncate_decide(hipStream_t s, const double* sig, int cnt, const doub
 hipError_t gather_rows_normalized(hipStream_t s, const double* X, int L, const int* perm, const double* sig,
                                   const TruncOut* t, double* out, long ldo, int rmax_host);
 int qr_num_panels(int m, int n);
+
+// ---------------------------------------------------------------- launch profiling
+namespace prof {
+enum Class { APPLY_PANEL = 0, JACOBI = 1, QR_PANEL = 2 };
+bool active(int cls);
+void begin(hipStream_t st, int cls, double bytes, double flops);
+void end(hipStream_t st);
+hipError_t start(int cls, int max_launches);
+hipError_t stop(long* launches, double* total_ms, double* bytes, double* flops);
+}  // namespace prof
 
 }  // namespace qtt

@@ -7,11 +7,13 @@
 // keeps U Sigma V^T = X_orig V V^T exact up to the orthogonality of V
 // (a product of thousands of rounded rotations would drift from orthogonal).
 //
-// Parallel ordering: rows are grouped into blocks of 16; a persistent grid of
+// Parallel ordering: rows are grouped into blocks of 8; a persistent grid of
 // workgroups (one per block pair) runs the round-robin tournament over blocks,
 // with a grid barrier between rounds.  For its pair of blocks a workgroup
-// stages the 32 rows in LDS and runs one full inner sweep of plane rotations
-// over them (31 rounds of 16 disjoint pairs, one wave per pair).  A rotation of
+// stages the 16 rows in LDS and runs one full inner sweep of plane rotations
+// over them (15 rounds of 8 disjoint pairs, one wave per pair); each lane
+// keeps its slice of the two rows in registers for the three dot products
+// and the rotation.  A rotation of
 // rows a, c is skipped when |a.c| <= tol * ||a|| ||c|| with
 // tol = sqrt(L) * eps, and the iteration stops after the first sweep without
 // any rotation.
@@ -22,9 +24,10 @@ namespace qtt {
 
 namespace {
 
-constexpr int JB = 16;        // rows per block
+constexpr int JB = 8;         // rows per block
 constexpr int JR = 2 * JB;    // rows staged per block pair
 constexpr int JNT = 64 * JB;  // threads: one wave per row pair of the inner sweep
+constexpr int JMAXE = 16;     // row elements per lane held in registers: L <= 1024
 
 __device__ __forceinline__ int rr_item(int pos, int round, int n) {
   // circle method: position 0 fixed, the others rotate
@@ -62,25 +65,36 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
           const int rc = rr_item(JR - 1 - wave, ir, JR);
           double* xa = sh + ra * W;
           double* xc = sh + rc * W;
+          double u[JMAXE], v[JMAXE];
+#pragma unroll
+          for (int q = 0; q < JMAXE; ++q) {
+            const int c = lane + 64 * q;
+            u[q] = (c < L) ? xa[c] : 0.0;
+            v[q] = (c < L) ? xc[c] : 0.0;
+          }
           double al = 0.0, be = 0.0, ga = 0.0;
-          for (int c = lane; c < L; c += 64) {
-            const double u = xa[c], w = xc[c];
-            al += u * u;
-            be += w * w;
-            ga += u * w;
+#pragma unroll
+          for (int q = 0; q < JMAXE; ++q) {
+            al += u[q] * u[q];
+            be += v[q] * v[q];
+            ga += u[q] * v[q];
           }
           al = wave_sum(al);
           be = wave_sum(be);
           ga = wave_sum(ga);
           if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
             const double zeta = (be - al) / (2.0 * ga);
-            const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double t = (fabs(zeta) > 1e150) ? 0.5 / zeta
+                                                  : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double cs = 1.0 / sqrt(1.0 + t * t);
             const double sn = cs * t;
-            for (int c = lane; c < W; c += 64) {
-              const double u = xa[c], w = xc[c];
-              xa[c] = cs * u - sn * w;
-              xc[c] = sn * u + cs * w;
+#pragma unroll
+            for (int q = 0; q < JMAXE; ++q) {
+              const int c = lane + 64 * q;
+              if (c < L) {
+                xa[c] = cs * u[q] - sn * v[q];
+                xc[c] = sn * u[q] + cs * v[q];
+              }
             }
             if (lane == 0) ++local_rot;
           }
@@ -178,6 +192,16 @@ __global__ void k_truncate(const double* __restrict__ sig, int cnt, const double
   out->delta = delta;
 }
 
+// dst[j][:] = src[perm[j]][:]  (rows in descending-norm order)
+__global__ void k_permute_rows(const double* __restrict__ src, int p, int L, const int* __restrict__ perm,
+                               double* __restrict__ dst) {
+  const long total = (long)p * L;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / L), c = (int)(e % L);
+    dst[e] = src[(long)perm[j] * L + c];
+  }
+}
+
 __global__ void k_gather_rows(const double* __restrict__ X, int L, const int* __restrict__ perm,
                               const double* __restrict__ sig, const TruncOut* __restrict__ t,
                               double* __restrict__ out, long ldo) {
@@ -202,6 +226,7 @@ inline int gsz(long n) {
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
                        int* sweeps_dev) {
   if (p <= 0 || L <= 0) return hipSuccess;
+  if (L > 64 * JMAXE) return hipErrorInvalidValue;
   const size_t shmem = (size_t)JR * L * sizeof(double);
   if (shmem > 160 * 1024 - 1024) return hipErrorInvalidValue;
   hipError_t e = fill_u32(s, counter, 0u, 8);
@@ -219,7 +244,14 @@ hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter
   // tolerance on |a.c| / (||a|| ||c||)
   const double tol = 2.220446049250313e-16 * sqrt((double)L);
   void* args[] = {&X, &p, &L, &counter, &max_sweeps, &sweeps_dev, (void*)&tol};
-  return hipLaunchCooperativeKernel((const void*)k_jacobi, dim3(grid), dim3(JNT), args, shmem, s);
+  if (prof::active(prof::JACOBI)) {
+    // one nominal sweep over all row pairs: 3 dots + one rotation of length L each
+    const double pairs = 0.5 * (double)p * (p - 1);
+    prof::begin(s, prof::JACOBI, 8.0 * 2.0 * p * (double)L, pairs * 12.0 * L);
+  }
+  e = hipLaunchCooperativeKernel((const void*)k_jacobi, dim3(grid), dim3(JNT), args, shmem, s);
+  prof::end(s);
+  return e;
 }
 
 hipError_t row_norms_sorted(hipStream_t s, const double* X, int p, int L, double* sig_sorted, int* perm) {
@@ -227,6 +259,12 @@ hipError_t row_norms_sorted(hipStream_t s, const double* X, int p, int L, double
   const size_t shmem = (size_t)p * sizeof(double);
   if (shmem > 64 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_norms_sort, dim3(1), dim3(1024), shmem, s, X, p, L, sig_sorted, perm);
+  return hipGetLastError();
+}
+
+hipError_t permute_rows(hipStream_t s, const double* src, int p, int L, const int* perm, double* dst) {
+  if (p <= 0 || L <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute_rows, dim3(gsz((long)p * L)), dim3(256), 0, s, src, p, L, perm, dst);
   return hipGetLastError();
 }
 

@@ -31,7 +31,9 @@ OP_CONTRACT, OP_ORTHOGONALIZE, OP_ROUND, OP_CONTRACT_ROUND, OP_INNER, OP_INNER_B
 EXPORTS = [
     "qtt_create", "qtt_destroy", "qtt_status_string", "qtt_workspace_size", "qtt_contract",
     "qtt_orthogonalize", "qtt_round", "qtt_contract_round", "qtt_inner", "qtt_inner_backward",
-    "qtt_contract_backward",
+    "qtt_contract_backward", "qtt_profile_start", "qtt_profile_stop", "qtt_batch_workspace_size",
+    "qtt_batch_plan_create", "qtt_batch_plan_launch", "qtt_batch_plan_results", "qtt_batch_plan_info",
+    "qtt_batch_plan_destroy",
 ]
 
 
@@ -97,6 +99,15 @@ def load_library():
     L.qtt_inner.argtypes = [vp, P(TT), P(TT), P(C.c_double), vp, C.c_size_t, vp]
     L.qtt_inner_backward.argtypes = [vp, P(TT), P(TT), C.c_double, P(TT), P(TT), vp, C.c_size_t, vp]
     L.qtt_contract_backward.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), P(TT), P(TT), vp, C.c_size_t, vp]
+    L.qtt_batch_workspace_size.argtypes = [vp, C.c_char_p, C.c_int32, P(TT), P(TT), C.c_int64, P(C.c_size_t)]
+    L.qtt_batch_plan_create.argtypes = [vp, C.c_char_p, C.c_int32, P(TT), P(TT), P(TT), C.c_double, C.c_int64,
+                                        C.c_int, vp, C.c_size_t, vp, P(vp)]
+    L.qtt_batch_plan_launch.argtypes = [vp, vp]
+    L.qtt_batch_plan_results.argtypes = [vp, P(C.c_int64), P(C.c_double), vp]
+    L.qtt_batch_plan_info.argtypes = [vp, P(C.c_int32), P(C.c_int32), P(C.c_float)]
+    L.qtt_batch_plan_destroy.argtypes = [vp]
+    L.qtt_profile_start.argtypes = [vp, C.c_int, C.c_int]
+    L.qtt_profile_stop.argtypes = [vp, P(C.c_int64), P(C.c_double), P(C.c_double), P(C.c_double)]
     for name in EXPORTS:
         if name != "qtt_status_string":
             getattr(L, name).restype = C.c_int
@@ -420,6 +431,104 @@ def orthogonalize(cores, inplace: bool = False):
                                _stream_ptr()), "qtt_orthogonalize")
     ranks = v.ranks()
     return _views_of_compact(flat, ranks, d), nrm.value
+
+
+class BatchPlan:
+    """Batched contract+round of many independent problems in one persistent launch.
+
+    The plan owns the output buffers (sized by the rank bounds), the workspace
+    and a captured hipGraph; launch() replays it, results() reads the ranks.
+    """
+
+    def __init__(self, spec: str, A: Sequence[Sequence[torch.Tensor]], B: Sequence[Sequence[torch.Tensor]],
+                 rel_tol: float, max_rank: int = 0, tune: bool = True):
+        L = load_library()
+        self.spec = spec
+        self.count = len(A)
+        legs = _legs(spec)
+        dev = A[0][0].device
+        self.h = handle(dev.index)
+        self.va = [TTView(list(a), legs) for a in A]
+        self.vb = [TTView(list(b), 1) for b in B]
+        self.d = [[c.shape[1] for c in a] for a in A]
+        self.bounds, self.out_buffers, self.vo = [], [], []
+        for i in range(self.count):
+            rc = [x * y for x, y in zip(self.va[i].ranks(), self.vb[i].ranks())]
+            bnd = rank_bounds(rc, self.d[i], max_rank)
+            bufs = [torch.empty(bnd[k] * self.d[i][k] * bnd[k + 1], dtype=torch.float64, device=dev)
+                    for k in range(len(self.d[i]))]
+            self.bounds.append(bnd)
+            self.out_buffers.append(bufs)
+            self.vo.append(TTView(bufs, 1, ranks_override=bnd, phys_override=self.d[i]))
+        ta = (TT * self.count)(*[v.struct for v in self.va])
+        tb = (TT * self.count)(*[v.struct for v in self.vb])
+        to = (TT * self.count)(*[v.struct for v in self.vo])
+        self._arrays = (ta, tb, to)
+        nb = C.c_size_t()
+        _check(L.qtt_batch_workspace_size(self.h.ptr, spec.encode(), self.count, ta, tb, int(max_rank), C.byref(nb)),
+               "qtt_batch_workspace_size")
+        self.ws = _workspace(nb.value + 256, dev)
+        self._plan = C.c_void_p()
+        _check(L.qtt_batch_plan_create(self.h.ptr, spec.encode(), self.count, ta, tb, to, float(rel_tol),
+                                       int(max_rank), 1 if tune else 0, C.c_void_p(self.ws.data_ptr()),
+                                       self.ws.numel(), _stream_ptr(), C.byref(self._plan)), "qtt_batch_plan_create")
+
+    def launch(self):
+        _check(load_library().qtt_batch_plan_launch(self._plan, _stream_ptr()), "qtt_batch_plan_launch")
+
+    def results(self):
+        """(ranks per problem, tails per problem) after the last launch."""
+        tot = sum(len(d) + 1 for d in self.d)
+        tt = sum(max(len(d) - 1, 0) for d in self.d)
+        r = (C.c_int64 * tot)()
+        t = (C.c_double * max(tt, 1))()
+        _check(load_library().qtt_batch_plan_results(self._plan, r, t, _stream_ptr()), "qtt_batch_plan_results")
+        ranks, tails, o, ot = [], [], 0, 0
+        for d in self.d:
+            ranks.append([int(r[o + k]) for k in range(len(d) + 1)])
+            tails.append([t[ot + k] for k in range(len(d) - 1)])
+            o += len(d) + 1
+            ot += max(len(d) - 1, 0)
+        self.ranks = ranks
+        return ranks, tails
+
+    def info(self):
+        v, g = C.c_int32(), C.c_int32()
+        ms = (C.c_float * 4)()
+        _check(load_library().qtt_batch_plan_info(self._plan, C.byref(v), C.byref(g), ms), "qtt_batch_plan_info")
+        return {"variant": v.value, "grid": g.value, "tuned_ms": [ms[i] for i in range(4)]}
+
+    def cores(self, i: int) -> List[torch.Tensor]:
+        return _views_of_compact(self.out_buffers[i], self.ranks[i], self.d[i])
+
+    def close(self):
+        if self._plan:
+            load_library().qtt_batch_plan_destroy(self._plan)
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+PROFILE_CLASSES = {"apply_panel": 0, "jacobi": 1, "qr_panel": 2}
+
+
+def profile_start(kernel_class: str, max_launches: int = 100000, device: Optional[int] = None):
+    L = load_library()
+    _check(L.qtt_profile_start(handle(device).ptr, PROFILE_CLASSES[kernel_class], max_launches), "qtt_profile_start")
+
+
+def profile_stop(device: Optional[int] = None):
+    """Returns (launches, total_ms, algorithmic_bytes, algorithmic_flops)."""
+    L = load_library()
+    n = C.c_int64()
+    ms, b, f = C.c_double(), C.c_double(), C.c_double()
+    _check(L.qtt_profile_stop(handle(device).ptr, C.byref(n), C.byref(ms), C.byref(b), C.byref(f)),
+           "qtt_profile_stop")
+    return n.value, ms.value, b.value, f.value
 
 
 def to_device(cores, device="cuda", dtype=torch.float64):

@@ -1,0 +1,79 @@
+"""Batched form: one persistent launch over many uneven-rank problems, replayed from a hipGraph."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+import qtt_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2602_20226_amd import qtt as Q
+
+DEV = "cuda:0"
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def check_instance(plan, i, A, B, tol, max_rank, err_tol):
+    C = O.contract("i,i->i", A, B)
+    ref, info = O.round_tt(C, tol, max_rank, return_info=True)
+    got = Q.to_host(plan.cores(i))
+    assert plan.ranks[i] == info.ranks, (i, plan.ranks[i], info.ranks)
+    err = O.rel_error(got, ref)
+    assert err <= err_tol, (i, err)
+    for c in got[1:]:
+        M = c.reshape(c.shape[0], -1)
+        assert np.abs(M @ M.T - np.eye(M.shape[0])).max() <= 1e-12
+    return err
+
+
+def test_small_uneven_batch_all_instances():
+    log("batched small")
+    rng = np.random.default_rng(300)
+    A, B = [], []
+    for i in range(12):
+        r = int(rng.integers(2, 20))
+        L = int(rng.integers(3, 10))
+        A.append(I.random_mps(L, r, rng))
+        B.append(I.random_mps(L, 2, rng))
+    plan = Q.BatchPlan("i,i->i", [Q.to_device(a) for a in A], [Q.to_device(b) for b in B], 1e-8, 0, tune=False)
+    plan.launch()
+    plan.results()
+    worst = max(check_instance(plan, i, A[i], B[i], 1e-8, 0, 1e-5) for i in range(len(A)))
+    log(f"batched small worst rel err {worst:.2e}")
+
+
+def test_config3_sampled_parity_and_graph_replay():
+    log("batched cfg3")
+    w = I.config3()
+    A = [Q.to_device(a) for a in w.a]
+    B = [Q.to_device(b) for b in w.b]
+    plan = Q.BatchPlan(w.spec, A, B, w.rel_tol, 0, tune=True)
+    log(f"plan info {plan.info()}")
+    plan.launch()
+    ranks0, tails0 = plan.results()
+    first = [c.clone() for c in plan.cores(5)]
+    # replays with eager work and synchronisations in between must reproduce the result
+    for rep in range(3):
+        torch.cuda.synchronize()
+        _ = (torch.ones(1000, device=DEV) * 2).sum().item()
+        plan.launch()
+        ranks, _ = plan.results()
+        assert ranks == ranks0
+        for a, b in zip(first, plan.cores(5)):
+            assert torch.equal(a, b)
+    rs = w.extra["ranks"]
+    sample = sorted(set([int(np.argmax(rs)), int(np.argmin(rs)), 0, 1, 100, 255, 511]))
+    worst = 0.0
+    for i in sample:
+        worst = max(worst, check_instance(plan, i, w.a[i], w.b[i], w.rel_tol, 0, 1e-5))
+    log(f"cfg3 sampled worst rel err {worst:.2e}")
+    # every problem: rank bounds and right-orthonormal cores
+    for i in range(len(w.a)):
+        assert ranks0[i][0] == 1 and ranks0[i][-1] == 1
+        assert max(ranks0[i]) <= 2 * rs[i]
