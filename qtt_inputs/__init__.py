@@ -37,11 +37,11 @@ __all__ = [
     "laplacian_mpo",
     "embed_axis",
     "Workload",
-    "config1",
-    "config2",
-    "config3",
-    "config4",
-    "config5",
+    "sin_noise_1d",
+    "laplacian2d_r64",
+    "hadamard_batch",
+    "laplacian3d_r256",
+    "residual_grad_2d",
 ]
 
 
@@ -327,24 +327,24 @@ class Workload:
     extra: dict = field(default_factory=dict)
 
 
-def config1() -> Workload:
+def sin_noise_1d() -> Workload:
     """1D, L=10: sin(2 pi x) (rank 2) times a raw Gaussian rank-4 QTT (seed 0)."""
     rng = np.random.default_rng(0)
     f = sin_unit_interval(10)
     g = random_mps(10, 4, rng, scale="raw")
-    return Workload("cfg1_1d_L10_hadamard_f64", "i,i->i", f, g, 1e-12, 0)
+    return Workload("sin_noise_1d_L10_r4", "i,i->i", f, g, 1e-12, 0)
 
 
-def config2(seed: int = 1, m: int = 16, rmax: int = 64) -> Workload:
+def laplacian2d_r64(seed: int = 1, m: int = 16, rmax: int = 64) -> Workload:
     """2D 2^16 x 2^16 grid (32 cores): Laplacian MPO times a rank-64 MPS."""
     rng = np.random.default_rng(seed)
     W = laplacian_mpo(m, 2)
     X = random_mps(2 * m, rmax, rng)
-    return Workload("cfg2_2d_n32_r64_f64", "ij,j->i", W, X, 1e-10, rmax)
+    return Workload("laplacian2d_n32_r64", "ij,j->i", W, X, 1e-10, rmax)
 
 
-def config3(count: int = 512, L: int = 24, seed: int = 2,
-            rlo: int = 8, rhi: int = 128) -> Workload:
+def hadamard_batch(count: int = 512, L: int = 24, seed: int = 2,
+                   rlo: int = 8, rhi: int = 128) -> Workload:
     """512 independent 1D Hadamard products; rank_A ~ U{8..128}, rank_B = 2.
 
     All instance ranks are drawn first, then A_i and B_i per instance.
@@ -355,22 +355,22 @@ def config3(count: int = 512, L: int = 24, seed: int = 2,
     for i in range(count):
         A.append(random_mps(L, int(ranks[i]), rng))
         B.append(random_mps(L, 2, rng))
-    return Workload("cfg3_batched512_L24_hadamard", "i,i->i", A, B, 1e-8, 0,
+    return Workload("hadamard_batch512_L24_r8to128", "i,i->i", A, B, 1e-8, 0,
                     {"ranks": [int(r) for r in ranks]})
 
 
-def config4(seed: int = 3, m: int = 14, rmax: int = 256) -> Workload:
+def laplacian3d_r256(seed: int = 3, m: int = 14, rmax: int = 256) -> Workload:
     """3D 2^14 per axis (42 cores): Laplacian MPO (rank 7) times a rank-256 MPS."""
     rng = np.random.default_rng(seed)
     W = laplacian_mpo(m, 3)
     X = random_mps(3 * m, rmax, rng)
-    return Workload("cfg4_3d_n42_r256", "ij,j->i", W, X, 1e-8, rmax)
+    return Workload("laplacian3d_n42_r256", "ij,j->i", W, X, 1e-8, rmax)
 
 
-def config5(seed: int = 4, m: int = 12, rx: int = 32, rb: int = 16) -> Workload:
+def residual_grad_2d(seed: int = 4, m: int = 12, rx: int = 32, rb: int = 16) -> Workload:
     """2D 2^12 x 2^12 (24 cores): loss ||A x - b||^2, x rank 32, b rank 16."""
     rng = np.random.default_rng(seed)
     W = laplacian_mpo(m, 2)
     x = random_mps(2 * m, rx, rng)
     b = random_mps(2 * m, rb, rng)
-    return Workload("cfg5_2d_n24_grad", "ij,j->i", W, x, 0.0, 0, {"rhs": b})
+    return Workload("residual_grad2d_n24_r32", "ij,j->i", W, x, 0.0, 0, {"rhs": b})

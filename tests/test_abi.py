@@ -97,7 +97,7 @@ def test_workspace_planning_and_shape_errors():
 def test_workspace_for_the_benchmark_shapes():
     import qtt_inputs as I
     from paper_2602_20226_amd.qtt import rank_bounds
-    w = I.config4()
+    w = I.laplacian3d_r256()
     ra = [1] + [c.shape[-1] for c in w.a]
     rb = [1] + [c.shape[-1] for c in w.b]
     n = len(w.a)

@@ -48,9 +48,9 @@ def test_small_uneven_batch_all_instances():
     log(f"batched small worst rel err {worst:.2e}")
 
 
-def test_config3_sampled_parity_and_graph_replay():
-    log("batched cfg3")
-    w = I.config3()
+def test_hadamard_batch_sampled_parity_and_graph_replay():
+    log("batched hadamard_batch")
+    w = I.hadamard_batch()
     A = [Q.to_device(a) for a in w.a]
     B = [Q.to_device(b) for b in w.b]
     plan = Q.BatchPlan(w.spec, A, B, w.rel_tol, 0, tune=True)
@@ -72,7 +72,7 @@ def test_config3_sampled_parity_and_graph_replay():
     worst = 0.0
     for i in sample:
         worst = max(worst, check_instance(plan, i, w.a[i], w.b[i], w.rel_tol, 0, 1e-5))
-    log(f"cfg3 sampled worst rel err {worst:.2e}")
+    log(f"hadamard_batch sampled worst rel err {worst:.2e}")
     # every problem: rank bounds and right-orthonormal cores
     for i in range(len(w.a)):
         assert ranks0[i][0] == 1 and ranks0[i][-1] == 1

@@ -66,14 +66,14 @@ def test_contract_backward_matches_oracle(spec):
         assert rel(w[k].grad.cpu().numpy(), dW[k]) <= 1e-13
 
 
-def _config5():
-    w = I.config5()
+def _residual_inputs():
+    w = I.residual_grad_2d()
     return w.a, w.b, w.extra["rhs"]
 
 
-def test_config5_gradient_fp64_vs_oracle_and_euler():
-    log("cfg5 fp64 gradient")
-    Wn, xn, bn = _config5()
+def test_residual_inputs_gradient_fp64_vs_oracle_and_euler():
+    log("residual_grad fp64 gradient")
+    Wn, xn, bn = _residual_inputs()
     g_ref = O.grad_axb(Wn, xn, bn)
     W, x, b = leaves(Wn, grad=False), leaves(xn), leaves(bn, grad=False)
     L = AG.residual_loss(W, x, b)
@@ -85,7 +85,7 @@ def test_config5_gradient_fp64_vs_oracle_and_euler():
         e = rel(x[k].grad.cpu().numpy(), g_ref[k])
         worst = max(worst, e)
         assert e <= 1e-12, (k, e)
-    log(f"cfg5 fp64 worst per-core rel err {worst:.2e}")
+    log(f"residual_grad fp64 worst per-core rel err {worst:.2e}")
     # Euler identity: <dL/dx_k, x_k> = 2<y,y> - 2<y,b> for every core
     y = O.contract("ij,j->i", Wn, xn)
     rhs = 2 * O.inner(y, y) - 2 * O.inner(y, bn)
@@ -94,9 +94,9 @@ def test_config5_gradient_fp64_vs_oracle_and_euler():
         assert abs(lhs - rhs) <= 1e-11 * abs(rhs)
 
 
-def test_config5_gradient_fp32():
-    log("cfg5 fp32 gradient")
-    Wn, xn, bn = _config5()
+def test_residual_inputs_gradient_fp32():
+    log("residual_grad fp32 gradient")
+    Wn, xn, bn = _residual_inputs()
     g_ref = O.grad_axb(Wn, xn, bn)
     W, x, b = leaves(Wn, torch.float32, False), leaves(xn, torch.float32), leaves(bn, torch.float32, False)
     L = AG.residual_loss(W, x, b)
@@ -105,14 +105,14 @@ def test_config5_gradient_fp32():
     for k in range(len(xn)):
         e = rel(x[k].grad.double().cpu().numpy(), g_ref[k])
         worst = max(worst, e)
-    log(f"cfg5 fp32 worst per-core rel err {worst:.2e}")
+    log(f"residual_grad fp32 worst per-core rel err {worst:.2e}")
     assert worst <= 1e-5
 
 
-def test_config5_central_differences():
+def test_residual_inputs_central_differences():
     """L is exactly quadratic in each core, so central FD has no truncation error."""
-    log("cfg5 finite differences")
-    Wn, xn, bn = _config5()
+    log("residual_grad finite differences")
+    Wn, xn, bn = _residual_inputs()
     W, b = leaves(Wn, grad=False), leaves(bn, grad=False)
     x = leaves(xn)
     L = AG.residual_loss(W, x, b)

@@ -40,12 +40,12 @@ def rand_mpo(rng, ranks, d=2):
 
 
 # ------------------------------------------------------------------ contraction (a1, a2)
-@pytest.mark.parametrize("case", ["cfg1", "ragged", "mpo_ragged"])
+@pytest.mark.parametrize("case", ["sin_noise", "ragged", "mpo_ragged"])
 def test_contract_elementwise(case):
     log(f"contract {case}")
     rng = np.random.default_rng(100)
-    if case == "cfg1":
-        w = I.config1()
+    if case == "sin_noise":
+        w = I.sin_noise_1d()
         spec, A, B = w.spec, w.a, w.b
     elif case == "ragged":
         spec = "i,i->i"
@@ -62,10 +62,10 @@ def test_contract_elementwise(case):
         assert np.abs(g - r).max() <= 2e-16 * max(np.abs(r).max(), 1e-300) * 4
 
 
-def test_contract_config4_sampled_cores():
+def test_contract_laplacian3d_r256_sampled_cores():
     """Full-size 3D Laplacian (rank 7) times the rank-256 MPS: sampled cores, element-wise."""
-    log("contract cfg4 sampled")
-    w = I.config4()
+    log("contract laplacian3d sampled")
+    w = I.laplacian3d_r256()
     got = Q.contract(w.spec, dev(w.a), dev(w.b))
     for k in [0, 1, 9, 20, 33, 41]:
         ref = O.contract(w.spec, [w.a[k]], [w.b[k]])[0]
@@ -208,9 +208,9 @@ def test_contract_round_random(spec):
         check_round(got, ref, info)
 
 
-def test_config1_contract_round():
-    log("cfg1 contract_round")
-    w = I.config1()
+def test_sin_noise_1d_contract_round():
+    log("sin_noise_1d contract_round")
+    w = I.sin_noise_1d()
     C = O.contract(w.spec, w.a, w.b)
     ref, info = O.round_tt(C, w.rel_tol, 0, return_info=True)
     got = Q.contract_round(w.spec, dev(w.a), dev(w.b), w.rel_tol, 0, want_sigmas=True)
@@ -220,14 +220,14 @@ def test_config1_contract_round():
     assert np.linalg.norm(O.to_dense(host(got.cores)) - dense) <= 1e-14 * np.linalg.norm(dense)
 
 
-def test_config2_contract_round():
-    log("cfg2 contract_round")
-    w = I.config2()
+def test_laplacian2d_r64_contract_round():
+    log("laplacian2d contract_round")
+    w = I.laplacian2d_r64()
     C = O.contract(w.spec, w.a, w.b)
     ref, info = O.round_tt(C, w.rel_tol, w.max_rank, return_info=True)
     got = Q.contract_round(w.spec, dev(w.a), dev(w.b), w.rel_tol, w.max_rank, want_sigmas=True)
     err = check_round(got, ref, info, tol=1e-12, sig_tol=1e-12)
-    log(f"cfg2 rel err {err:.3e} ranks {got.ranks}")
+    log(f"laplacian2d rel err {err:.3e} ranks {got.ranks}")
 
 
 @pytest.mark.parametrize("m,D", [(16, 2), (14, 3)])

@@ -27,9 +27,9 @@ def log(msg):
 
 
 @pytest.fixture(scope="module")
-def cfg4():
-    w = I.config4()
-    log("cfg4: oracle contract + round (FP64, LAPACK)")
+def lap3d():
+    w = I.laplacian3d_r256()
+    log("laplacian3d: oracle contract + round (FP64, LAPACK)")
     C = O.contract(w.spec, w.a, w.b)
     ref, info = O.round_tt(C, w.rel_tol, w.max_rank, return_info=True)
     del C
@@ -38,41 +38,41 @@ def cfg4():
     return w, ref, info, A, B
 
 
-def _run(cfg4, prec):
-    w, ref, info, A, B = cfg4
+def _run(lap3d, prec):
+    w, ref, info, A, B = lap3d
     got = Q.contract_round(w.spec, A, B, w.rel_tol, w.max_rank, prec=prec, want_sigmas=True)
     err = O.rel_error(Q.to_host(got.cores), ref)
     sig = 0.0
     for k, s in enumerate(info.sigmas):
         g = np.array(got.sigmas[k][: len(s)])
         sig = max(sig, np.abs(g - s).max() / s[0])
-    log(f"cfg4 {prec}: rel err {err:.3e}  max sigma err/sigma1 {sig:.3e}  ranks equal {got.ranks == info.ranks}")
+    log(f"laplacian3d {prec}: rel err {err:.3e}  max sigma err/sigma1 {sig:.3e}  ranks equal {got.ranks == info.ranks}")
     return got, err, sig
 
 
 @pytest.mark.timeout(900)
-def test_cfg4_fp64_path(cfg4):
-    got, err, sig = _run(cfg4, "fp64")
-    _, _, info, _, _ = cfg4
+def test_lap3d_fp64_path(lap3d):
+    got, err, sig = _run(lap3d, "fp64")
+    _, _, info, _, _ = lap3d
     assert got.ranks == info.ranks
     assert sig <= 1e-12
     assert err <= 1e-12
 
 
 @pytest.mark.timeout(900)
-def test_cfg4_bf16x6_path(cfg4):
-    got, err, sig = _run(cfg4, "bf16x6")
-    _, _, info, _, _ = cfg4
+def test_lap3d_bf16x6_path(lap3d):
+    got, err, sig = _run(lap3d, "bf16x6")
+    _, _, info, _, _ = lap3d
     assert got.ranks == info.ranks
     assert sig <= 1e-6
     assert err <= 1e-6
 
 
 @pytest.mark.timeout(900)
-def test_cfg4_bf16x3_and_fp32_reported(cfg4):
+def test_lap3d_bf16x3_and_fp32_reported(lap3d):
     """Three-product split and FP32 GEMMs: ranks must match, errors are reported."""
-    _, _, info, _, _ = cfg4
+    _, _, info, _, _ = lap3d
     for prec in ["bf16x3", "fp32"]:
-        got, err, sig = _run(cfg4, prec)
+        got, err, sig = _run(lap3d, prec)
         assert got.ranks == info.ranks
         assert err <= 1e-4

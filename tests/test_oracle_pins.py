@@ -261,8 +261,8 @@ def test_round_max_rank_is_best_rank_r_at_last_bond():
     assert any(info.maxrank_hit)
 
 
-def test_config1_ranks_and_dense_error():
-    w = Q.config1()
+def test_sin_noise_1d_ranks_and_dense_error():
+    w = Q.sin_noise_1d()
     C = O.contract(w.spec, w.a, w.b)
     Y, info = O.round_tt(C, w.rel_tol, 0, return_info=True)
     assert info.ranks == [1, 2, 4, 8, 8, 8, 8, 8, 4, 2, 1]
