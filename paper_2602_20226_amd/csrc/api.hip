@@ -172,7 +172,7 @@ int make_plan(const Shape& s, long max_rank, Plan& P) {
   P.offSig = take(maxP);
   P.offPerm = take(maxP / 2 + 1);
   P.offTrunc = take(8);
-  P.offCtr = take(8);
+  P.offCtr = take(96);  // Jacobi: 8 counter words + one version per 8-row block (p <= 1024)
   P.offNorm = take(1);
   P.offSweeps = take(1);
   P.offOne = take(1);

@@ -5,18 +5,20 @@
 // to their order: normalising them gives the right singular vectors.  Z is
 // not accumulated: the caller forms U Sigma = X_orig V with one GEMM, which
 // keeps U Sigma V^T = X_orig V V^T exact up to the orthogonality of V
-// (a product of thousands of rounded rotations would drift from orthogonal).
+// (a product of thousands of rounded plane rotations drifts from orthogonal).
 //
-// Parallel ordering: rows are grouped into blocks of 8; a persistent grid of
-// workgroups (one per block pair) runs the round-robin tournament over blocks,
-// with a grid barrier between rounds.  For its pair of blocks a workgroup
-// stages the 16 rows in LDS and runs one full inner sweep of plane rotations
-// over them (15 rounds of 8 disjoint pairs, one wave per pair); each lane
-// keeps its slice of the two rows in registers for the three dot products
-// and the rotation.  A rotation of
-// rows a, c is skipped when |a.c| <= tol * ||a|| ||c|| with
-// tol = sqrt(L) * eps, and the iteration stops after the first sweep without
-// any rotation.
+// Parallel ordering (block cyclic Jacobi): rows form blocks of 8; a
+// persistent grid with one workgroup per block pair runs the round-robin
+// tournament over blocks.  In a round a workgroup rotates the 64 cross pairs
+// of its two blocks (8 steps of 8 disjoint pairs, one wave per pair, both
+// rows held in registers, bottom rows passed between waves through LDS);
+// in the first round of every sweep it also rotates the 28 + 28 pairs inside
+// each block.  Every row pair is thus visited once per sweep.  Rounds are
+// ordered by per-block version counters (a workgroup waits only for the two
+// workgroups that produced its blocks), sweeps by a grid barrier that also
+// sums the sweep's rotation count.  A rotation of rows a, c is skipped when
+// |a.c| <= tol ||a|| ||c|| with tol = sqrt(L) eps; the iteration stops after
+// the first sweep without any rotation.
 #include "qtt_device.hpp"
 #include "qtt_internal.hpp"
 
@@ -25,89 +27,152 @@ namespace qtt {
 namespace {
 
 constexpr int JB = 8;         // rows per block
-constexpr int JR = 2 * JB;    // rows staged per block pair
-constexpr int JNT = 64 * JB;  // threads: one wave per row pair of the inner sweep
-constexpr int JMAXE = 16;     // row elements per lane held in registers: L <= 1024
+constexpr int JNT = 64 * JB;  // one wave per row of the top block
+constexpr int JCTR = 8;       // counter words before the block versions
 
 __device__ __forceinline__ int rr_item(int pos, int round, int n) {
   // circle method: position 0 fixed, the others rotate
   return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (n - 1));
 }
 
-__global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, int L,
-                                                unsigned* __restrict__ ctr, int max_sweeps, int* sweeps_out,
-                                                double tol) {
-  extern __shared__ double sh[];  // [JR][L]
+// Rotate the pair (u, v) of rows (E elements per lane, zero past the row end)
+// so that they become orthogonal; returns true when a rotation was applied.
+template <int E>
+__device__ __forceinline__ bool rotate_pair(double (&u)[E], double (&v)[E], double tol) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    al += u[q] * u[q];
+    be += v[q] * v[q];
+    ga += u[q] * v[q];
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (fabs(zeta) > 1e150) ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t);
+  const double sn = cs * t;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const double a = u[q], c = v[q];
+    u[q] = cs * a - sn * c;
+    v[q] = sn * a + cs * c;
+  }
+  return true;
+}
+
+template <int E>
+__device__ __forceinline__ void load_row(const double* __restrict__ src, int L, bool ok, double (&r)[E]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int c = lane + 64 * q;
+    r[q] = (ok && c < L) ? src[c] : 0.0;
+  }
+}
+
+template <int E>
+__device__ __forceinline__ void store_row(double* __restrict__ dst, int L, bool ok, const double (&r)[E]) {
+  const int lane = threadIdx.x & 63;
+  if (!ok) return;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int c = lane + 64 * q;
+    if (c < L) dst[c] = r[q];
+  }
+}
+
+// LDS row slots hold 64 E doubles (row elements lane + 64 q).
+template <int E>
+__device__ __forceinline__ void lds_put(double* slot, const double (&r)[E]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < E; ++q) slot[lane + 64 * q] = r[q];
+}
+template <int E>
+__device__ __forceinline__ void lds_get(const double* slot, double (&r)[E]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < E; ++q) r[q] = slot[lane + 64 * q];
+}
+
+// ctr[0..1]: grid barrier; ctr[2..4]: rotation counts of three consecutive
+// sweeps; ctr[JCTR + b]: rounds completed by block b.
+template <int E>
+__global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, int L, unsigned* __restrict__ ctr,
+                                                int max_sweeps, int* sweeps_out, double tol) {
+  extern __shared__ double sh[];  // 16 row slots of 64 E doubles
   __shared__ unsigned s_tot;
-  const int W = L;
+  constexpr int RS = 64 * E;
   const int nblk = (p + JB - 1) / JB;
   const int nb2 = nblk + (nblk & 1);
-  const int npairs = nb2 / 2;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nrounds = nb2 - 1;
+  const int pair = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  unsigned* ver = ctr + JCTR;
   unsigned local_rot = 0;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
-    for (int round = 0; round < nb2 - 1; ++round) {
-      for (int pair = blockIdx.x; pair < npairs; pair += gridDim.x) {
-        const int b0 = rr_item(pair, round, nb2);
-        const int b1 = rr_item(nb2 - 1 - pair, round, nb2);
-        // stage rows: local row t < JB -> block b0 row t, t >= JB -> block b1 row t-JB
-        for (int e = tid; e < JR * W; e += JNT) {
-          const int t = e / W, c = e % W;
-          const int gr = (t < JB ? b0 : b1) * JB + (t % JB);
-          double v = 0.0;
-          if (gr < p) v = X[(long)gr * L + c];
-          sh[t * W + c] = v;
-        }
+    for (int round = 0; round < nrounds; ++round) {
+      const int b0 = rr_item(pair, round, nb2);
+      const int b1 = rr_item(nb2 - 1 - pair, round, nb2);
+      const unsigned expect = (unsigned)(sweep * nrounds + round);
+      if (tid == 0) {
+        while (__hip_atomic_load(&ver[b0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != expect)
+          __builtin_amdgcn_s_sleep(1);
+        while (__hip_atomic_load(&ver[b1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != expect)
+          __builtin_amdgcn_s_sleep(1);
+      }
+      __syncthreads();
+      const int rt = b0 * JB + w;  // top row held by this wave
+      const bool okt = rt < p;
+      double top[E], bot[E];
+      load_row<E>(X + (long)rt * L, L, okt, top);
+      load_row<E>(X + (long)(b1 * JB + w) * L, L, b1 * JB + w < p, bot);
+      if (round == 0) {
+        // pairs inside each block: 7 steps, waves 0-3 on the top block, 4-7 on the bottom
+        lds_put<E>(sh + w * RS, top);
+        lds_put<E>(sh + (JB + w) * RS, bot);
         __syncthreads();
-        for (int ir = 0; ir < JR - 1; ++ir) {
-          const int ra = rr_item(wave, ir, JR);
-          const int rc = rr_item(JR - 1 - wave, ir, JR);
-          double* xa = sh + ra * W;
-          double* xc = sh + rc * W;
-          double u[JMAXE], v[JMAXE];
-#pragma unroll
-          for (int q = 0; q < JMAXE; ++q) {
-            const int c = lane + 64 * q;
-            u[q] = (c < L) ? xa[c] : 0.0;
-            v[q] = (c < L) ? xc[c] : 0.0;
-          }
-          double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-          for (int q = 0; q < JMAXE; ++q) {
-            al += u[q] * u[q];
-            be += v[q] * v[q];
-            ga += u[q] * v[q];
-          }
-          al = wave_sum(al);
-          be = wave_sum(be);
-          ga = wave_sum(ga);
-          if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double t = (fabs(zeta) > 1e150) ? 0.5 / zeta
-                                                  : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + t * t);
-            const double sn = cs * t;
-#pragma unroll
-            for (int q = 0; q < JMAXE; ++q) {
-              const int c = lane + 64 * q;
-              if (c < L) {
-                xa[c] = cs * u[q] - sn * v[q];
-                xc[c] = sn * u[q] + cs * v[q];
-              }
-            }
+        const int blk = w >> 2, i = w & 3;
+        for (int st = 0; st < JB - 1; ++st) {
+          double* sa = sh + (blk * JB + rr_item(i, st, JB)) * RS;
+          double* sc = sh + (blk * JB + rr_item(JB - 1 - i, st, JB)) * RS;
+          double u[E], v[E];
+          lds_get<E>(sa, u);
+          lds_get<E>(sc, v);
+          if (rotate_pair<E>(u, v, tol)) {
+            lds_put<E>(sa, u);
+            lds_put<E>(sc, v);
             if (lane == 0) ++local_rot;
           }
           __syncthreads();
         }
-        for (int e = tid; e < JR * W; e += JNT) {
-          const int t = e / W, c = e % W;
-          const int gr = (t < JB ? b0 : b1) * JB + (t % JB);
-          if (gr < p) X[(long)gr * L + c] = sh[t * W + c];
-        }
+        lds_get<E>(sh + w * RS, top);
+        lds_get<E>(sh + (JB + w) * RS, bot);
         __syncthreads();
       }
-      grid_barrier(ctr, gridDim.x);
+      // cross pairs: at step s wave w rotates top row w with bottom row (w + s) % 8
+      for (int s = 0; s < JB; ++s) {
+        if (rotate_pair<E>(top, bot, tol) && lane == 0) ++local_rot;
+        if (s + 1 < JB) {
+          double* buf = sh + (s & 1) * JB * RS;
+          lds_put<E>(buf + ((w + s) % JB) * RS, bot);
+          __syncthreads();
+          lds_get<E>(buf + ((w + s + 1) % JB) * RS, bot);
+        }
+      }
+      store_row<E>(X + (long)rt * L, L, okt, top);
+      const int rb = b1 * JB + (w + JB - 1) % JB;
+      store_row<E>(X + (long)rb * L, L, rb < p, bot);
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) {
+        __hip_atomic_store(&ver[b0], expect + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ver[b1], expect + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     // sweep bookkeeping: counter (sweep % 3) collects this sweep's rotations
     if (lane == 0 && local_rot) atomicAdd(&ctr[2 + (sweep % 3)], local_rot);
@@ -226,30 +291,43 @@ inline int gsz(long n) {
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
                        int* sweeps_dev) {
   if (p <= 0 || L <= 0) return hipSuccess;
-  if (L > 64 * JMAXE) return hipErrorInvalidValue;
-  const size_t shmem = (size_t)JR * L * sizeof(double);
-  if (shmem > 160 * 1024 - 1024) return hipErrorInvalidValue;
-  hipError_t e = fill_u32(s, counter, 0u, 8);
-  if (e != hipSuccess) return e;
+  if (L > 1024 || p > 1024) return hipErrorInvalidValue;
   const int nblk = (p + JB - 1) / JB;
-  const int npairs = (nblk + (nblk & 1)) / 2;
-  int grid = npairs < 1 ? 1 : npairs;
-  if (grid > 256) grid = 256;
-  static bool attr_set = false;
-  if (!attr_set) {
-    e = hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  const int nb2 = nblk + (nblk & 1);
+  hipError_t e = fill_u32(s, counter, 0u, JCTR + nb2);
+  if (e != hipSuccess) return e;
+  const int grid = nb2 / 2;
   // tolerance on |a.c| / (||a|| ||c||)
   const double tol = 2.220446049250313e-16 * sqrt((double)L);
   void* args[] = {&X, &p, &L, &counter, &max_sweeps, &sweeps_dev, (void*)&tol};
+  const void* fn;
+  int E;
+  if (L <= 64) {
+    fn = (const void*)k_jacobi<1>, E = 1;
+  } else if (L <= 128) {
+    fn = (const void*)k_jacobi<2>, E = 2;
+  } else if (L <= 256) {
+    fn = (const void*)k_jacobi<4>, E = 4;
+  } else if (L <= 512) {
+    fn = (const void*)k_jacobi<8>, E = 8;
+  } else {
+    fn = (const void*)k_jacobi<16>, E = 16;
+  }
+  const size_t shmem = (size_t)2 * JB * 64 * E * sizeof(double);
+  if (shmem > 64 * 1024) {
+    static bool attr_set = false;  // only the E = 16 instance needs more than 64 KiB
+    if (!attr_set) {
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+  }
   if (prof::active(prof::JACOBI)) {
     // one nominal sweep over all row pairs: 3 dots + one rotation of length L each
     const double pairs = 0.5 * (double)p * (p - 1);
     prof::begin(s, prof::JACOBI, 8.0 * 2.0 * p * (double)L, pairs * 12.0 * L);
   }
-  e = hipLaunchCooperativeKernel((const void*)k_jacobi, dim3(grid), dim3(JNT), args, shmem, s);
+  e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(JNT), args, shmem, s);
   prof::end(s);
   return e;
 }
