@@ -200,8 +200,10 @@ int qtt_batch_plan_info(qtt_batch_plan plan, int32_t *variant, int32_t *grid, fl
 int qtt_batch_plan_destroy(qtt_batch_plan plan);
 
 /* Launch profiling for roofline reports.  qtt_profile_start arms one kernel
- * class (0 = block-reflector application of the Householder QR, 1 = Jacobi
- * SVD, 2 = Householder panel): every following launch of that class, up to
+ * class (0 = 16-column block-reflector application inside a 64-column
+ * block of the Householder QR, 1 = Jacobi SVD, 2 = Householder panel,
+ * 3 = V^T Y product of a 64-column block reflector, 4 = its Y += V W
+ * update): every following launch of that class, up to
  * max_launches, is bracketed by HIP events on the stream it is launched on,
  * and its algorithmic bytes and FLOP (from the launch shape) are summed.
  * qtt_profile_stop waits for the last event and returns the launch count,

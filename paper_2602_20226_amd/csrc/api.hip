@@ -1040,7 +1040,7 @@ int qtt_contract_backward(qtt_handle h, const char* spec, const qtt_tt* a, const
 }
 
 int qtt_profile_start(qtt_handle h, int kernel_class, int max_launches) {
-  if (!h || kernel_class < 0 || kernel_class > 2 || max_launches < 1 || max_launches > (1 << 22)) return QTT_ERR_ARG;
+  if (!h || kernel_class < 0 || kernel_class > 4 || max_launches < 1 || max_launches > (1 << 22)) return QTT_ERR_ARG;
   Scoped sc(h->device);
   return prof::start(kernel_class, max_launches) == hipSuccess ? QTT_OK : QTT_ERR_HIP;
 }

@@ -1,10 +1,18 @@
 // Blocked Householder QR for the rounding sweep (FP64).
 //
-// Panels of up to 16 columns are factored by one workgroup (qr_panel_dev in
-// qr_device.hpp).  The trailing update and every later application of Q or
-// Q^T go through apply_block: a pair of kernels split over 16-column tiles
-// and 256-row chunks (W = V^T Y per chunk, then reduction, op(T) and the
-// rank-pw update), so that narrow targets still occupy the whole GPU.
+// Two levels.  Inner panels of up to 16 columns are factored by one
+// workgroup each (qr_panel_dev in qr_device.hpp) and applied to the rest of
+// their 64-column outer block by apply_block (a pair of kernels split over
+// 16-column tiles and 256-row chunks).  The reflectors of an outer block are
+// then aggregated into one compact-WY pair (V, T) with T of order <= 64,
+// built from S = V^T V and the reflector coefficients, and the trailing
+// matrix -- and every later application of Q or Q^T -- is updated once per
+// outer block by three kernels on FP64 MFMA tiles:
+//     P_c = V_c^T Y_c          (split over 256-row chunks c),
+//     W   = -op(T) sum_c P_c,
+//     Y  += V W.
+// V is never copied: the kernels read it from the unit lower trapezoid of
+// the factored matrix.
 #include "qtt_device.hpp"
 #include "qtt_internal.hpp"
 #include "qr_device.hpp"
@@ -17,8 +25,246 @@ namespace {
 
 template <int NT, int RPT, int PW>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_qr_panel(
-    double* __restrict__ A, long lda, int m, int j0, int pw, double* __restrict__ Tout) {
-  qr_panel_dev<NT, RPT, PW>(A, lda, m, j0, pw, Tout);
+    double* __restrict__ A, long lda, int m, int j0, int pw, double* __restrict__ Tout, double* __restrict__ tau) {
+  extern __shared__ double stage[];  // NT x (PW + 1)
+  qr_panel_dev<NT, RPT, PW>(A, lda, m, j0, pw, Tout, stage, tau);
+}
+
+// ------------------------------------------------------------ outer blocks
+constexpr int OB = 64;    // outer block width: reflectors aggregated per (V, T)
+constexpr int KC = 256;   // row chunk of the split-K products
+constexpr int MAX_CHUNKS = 16;  // m <= 4096
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Element (k, i) of the unit lower trapezoidal V of an outer block whose
+// origin is A[j0][j0]: 1 on the diagonal, the stored vector below, 0 above
+// and outside [0, mp) x [0, nb).
+__device__ __forceinline__ double vel(const double* __restrict__ Ab, long lda, int mp, int nb, int k, int i) {
+  if (k >= mp || i >= nb || k < i) return 0.0;
+  return k == i ? 1.0 : Ab[(long)k * lda + i];
+}
+
+// P[c][i][col] = sum over rows k of chunk c of V[k][i] * Yv[k][col],
+// i < nb, col < ncols; Yv = V for col < s_cols, else Y[k][col].
+// 256 threads; wave w owns output columns [16w, 16w + 16) of the 64-column
+// tile and all four 16-row blocks of i.  MFMA f64 16x16x4 operand layout:
+// A[i][k] in lane (i + 16 k), B[k][col] in lane (col + 16 k); result
+// C[i][col] with i = lane / 16 + 4 v, col = lane % 16.  Rows go in groups
+// of 8 k-steps whose operands are fetched one group ahead.
+constexpr int VG = 8;  // k-steps (of 4 rows) per operand group
+
+__device__ __forceinline__ void vty_fetch(const double* __restrict__ Ab, long lda, int mp, int nb,
+                                          const double* __restrict__ Yc, long ldy, bool colok, bool colv, int col,
+                                          int kend, int k0, int lane, double (&a)[VG][4], double (&b)[VG]) {
+  const int kq = lane >> 4, il = lane & 15;
+#pragma unroll
+  for (int t = 0; t < VG; ++t) {
+    const int k = k0 + 4 * t + kq;
+    const bool kok = k < kend;
+    b[t] = (colok && kok) ? (colv ? vel(Ab, lda, mp, nb, k, col) : Yc[(long)k * ldy]) : 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[t][s] = kok ? vel(Ab, lda, mp, nb, k, s * 16 + il) : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_vty(const double* __restrict__ A, long lda, int j0, int mp, int nb,
+                                             const double* __restrict__ Y, long ldy, int yr0, int yc0, int ncols,
+                                             int s_cols, int ntiles, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
+  const int col = tile * 64 + w * 16 + (lane & 15);
+  const int kq = lane >> 4;
+  const int kbeg = chunk * KC, kend = min(mp, kbeg + KC);
+  const double* Ab = A + (long)j0 * lda + j0;
+  const double* Yc = Y + (long)yr0 * ldy + yc0 + col;
+  const bool colok = col < ncols;
+  const bool colv = col < s_cols;
+  f64x4 acc[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double a[VG][4], b[VG], a2[VG][4], b2[VG];
+  vty_fetch(Ab, lda, mp, nb, Yc, ldy, colok, colv, col, kend, kbeg, lane, a, b);
+  for (int k0 = kbeg; k0 < kend; k0 += 4 * VG) {
+    const bool more = k0 + 4 * VG < kend;
+    if (more) vty_fetch(Ab, lda, mp, nb, Yc, ldy, colok, colv, col, kend, k0 + 4 * VG, lane, a2, b2);
+#pragma unroll
+    for (int t = 0; t < VG; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = mfma16x16x4(a[t][s], b[t], acc[s]);
+    if (more) {
+#pragma unroll
+      for (int t = 0; t < VG; ++t) {
+        b[t] = b2[t];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[t][s] = a2[t][s];
+      }
+    }
+  }
+  if (!colok) return;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = s * 16 + kq + 4 * v;
+      if (i < nb) part[((long)chunk * OB + i) * ncols + col] = acc[s][v];
+    }
+}
+
+// Panel boundaries inside one outer block (offsets relative to the block).
+struct PanelList {
+  int np;
+  int off[OB / 8 + 1];  // panel q covers columns [off[q], off[q + 1])
+};
+
+// Compact-WY factor of an outer block from S = sum_c P_c[0:nb, 0:nb] = V^T V
+// and the panels' own factors T_q (its diagonal blocks): block column q is
+//     T[0:o, q] = -T[0:o, 0:o] S[0:o, q] T_q,   o = off[q],
+// which is the column recurrence T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j]
+// taken one panel at a time.  One workgroup.
+__global__ __launch_bounds__(256) void k_tbuild(const double* __restrict__ Sg, int sstride, int nb,
+                                                const double* __restrict__ tin, PanelList pl,
+                                                double* __restrict__ Tout) {
+  __shared__ double S[OB][OB + 1];
+  __shared__ double T[OB][OB + 1];
+  __shared__ double X[OB][17];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < OB * OB / 256; ++u) {
+    const int e = tid + 256 * u;
+    const int i = e / OB, j = e % OB;
+    S[i][j] = (i < nb && j < nb && i < j) ? Sg[(long)i * sstride + j] : 0.0;
+    T[i][j] = 0.0;
+  }
+  __syncthreads();
+  for (int q = 0; q < pl.np; ++q) {
+    const int o = pl.off[q], w = pl.off[q + 1] - o;
+    for (int e = tid; e < w * w; e += 256) T[o + e / w][o + e % w] = tin[(long)q * 256 + (e / w) * 16 + e % w];
+  }
+  __syncthreads();
+  for (int q = 1; q < pl.np; ++q) {
+    const int o = pl.off[q], w = pl.off[q + 1] - o;
+    // X = T[0:o, 0:o] S[0:o, o:o+w]   (T upper triangular)
+    for (int e = tid; e < o * w; e += 256) {
+      const int i = e / w, c = e % w;
+      double acc = 0.0;
+      for (int l = i; l < o; ++l) acc += T[i][l] * S[l][o + c];
+      X[i][c] = acc;
+    }
+    __syncthreads();
+    // T[0:o, o:o+w] = -X T_q
+    for (int e = tid; e < o * w; e += 256) {
+      const int i = e / w, c = e % w;
+      double acc = 0.0;
+      for (int l = 0; l <= c; ++l) acc += X[i][l] * T[o + l][o + c];
+      T[i][o + c] = -acc;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < OB * OB; e += 256) Tout[e] = T[e / OB][e % OB];
+}
+
+// W[i][col] = sum_c P_c[i][col] for i < nb, col < ncols (fixed summation
+// order: deterministic).  One thread per entry, all chunk loads in flight.
+__global__ __launch_bounds__(256) void k_red(const double* __restrict__ part, int nchunks, int ncols, int nb,
+                                             double* __restrict__ W) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)nb * ncols) return;
+  const int i = (int)(e / ncols), col = (int)(e % ncols);
+  double v[MAX_CHUNKS];
+#pragma unroll
+  for (int c = 0; c < MAX_CHUNKS; ++c) v[c] = (c < nchunks) ? part[((long)c * OB + i) * ncols + col] : 0.0;
+  double sum = 0.0;
+#pragma unroll
+  for (int c = 0; c < MAX_CHUNKS; ++c) sum += v[c];
+  W[(long)i * ncols + col] = sum;
+}
+
+// Y[k][col] += sum_i V[k][i] W[i][col] for the rows of one chunk and one
+// 64-column tile.  Wave w owns columns [16w, 16w + 16); W's column slice is
+// held as 16 B operands; rows go in blocks of 16 (A = V rows, C = Y rows in
+// the f64 MFMA result layout), the next block's operands fetched ahead.
+__device__ __forceinline__ void upd_fetch(const double* __restrict__ Ab, long lda, int mp, int nb,
+                                          const double* __restrict__ Yc, long ldy, bool colok, int kend, int r0,
+                                          int nk, int lane, double (&a)[OB / 4], double (&c)[4]) {
+  const int kq = lane >> 4;
+  const int ka = r0 + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int k = r0 + kq + 4 * v;
+    c[v] = (colok && k < kend) ? Yc[(long)k * ldy] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < OB / 4; ++q) a[q] = (q < nk && ka < kend) ? vel(Ab, lda, mp, nb, ka, 4 * q + kq) : 0.0;
+}
+
+// The workgroup first forms its slice of W' = -op(T) W (64 x 16 per wave,
+// f64 MFMA); result element [16 s + kq + 4 v][col] is exactly the B operand
+// of k-step q = 4 s + v, so no data movement is needed between the two.
+__global__ __launch_bounds__(256) void k_vupd(const double* __restrict__ A, long lda, int j0, int mp, int nb,
+                                              const double* __restrict__ T, int trans, const double* __restrict__ W,
+                                              long ldw, int wc0, double* __restrict__ Y, long ldy, int yr0, int yc0,
+                                              int ncols, int ntiles) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
+  const int col = tile * 64 + w * 16 + (lane & 15);
+  const int kq = lane >> 4, il = lane & 15;
+  const bool colok = col < ncols;
+  const int kbeg = chunk * KC, kend = min(mp, kbeg + KC);
+  const double* Ab = A + (long)j0 * lda + j0;
+  double* Yc = Y + (long)yr0 * ldy + yc0 + col;
+  const int nk = (nb + 3) / 4;
+  double bw[OB / 4];
+  {
+    double wb[OB / 4];
+#pragma unroll
+    for (int q = 0; q < OB / 4; ++q) {
+      const int i = 4 * q + kq;
+      wb[q] = (i < nb && colok) ? W[(long)i * ldw + wc0 + col] : 0.0;
+    }
+    f64x4 acc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < OB / 4; ++q) {
+      const int k = 4 * q + kq;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int i = 16 * s + il;
+        const double t = trans ? T[k * OB + i] : T[i * OB + k];
+        acc[s] = mfma16x16x4(t, wb[q], acc[s]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bw[4 * s + v] = -acc[s][v];
+  }
+  double a[OB / 4], c[4], a2[OB / 4], c2[4];
+  upd_fetch(Ab, lda, mp, nb, Yc, ldy, colok, kend, kbeg, nk, lane, a, c);
+  for (int r0 = kbeg; r0 < kend; r0 += 16) {
+    const bool more = r0 + 16 < kend;
+    if (more) upd_fetch(Ab, lda, mp, nb, Yc, ldy, colok, kend, r0 + 16, nk, lane, a2, c2);
+    f64x4 acc = f64x4{c[0], c[1], c[2], c[3]};
+#pragma unroll
+    for (int q = 0; q < OB / 4; ++q)
+      if (q < nk) acc = mfma16x16x4(a[q], bw[q], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = r0 + kq + 4 * v;
+      if (colok && k < kend) Yc[(long)k * ldy] = acc[v];
+    }
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < OB / 4; ++q) a[q] = a2[q];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c[v] = c2[v];
+    }
+  }
 }
 
 inline void apply_cost(int mp, int pw, int ncols, double& bytes, double& flops);
@@ -191,88 +437,163 @@ struct PanelCfg {
   int nt, rpt, pw;
 };
 
+// One workgroup of 256 threads (one wave per SIMD, up to 512 registers per
+// lane) holds the panel: few waves keep the per-column reductions cheap.
 inline PanelCfg panel_cfg(int mp) {
   if (mp <= 256) return {256, 1, 16};
   if (mp <= 512) return {256, 2, 16};
   if (mp <= 1024) return {256, 4, 16};
-  if (mp <= 2048) return {1024, 2, 16};
-  return {1024, 4, 8};
+  if (mp <= 2048) return {256, 8, 16};
+  if (mp <= 3072) return {256, 12, 8};
+  return {256, 16, 8};
 }
 
-// Panel boundaries are a pure function of (m, kmax); both the factorisation
-// and every later application of Q walk the same sequence.
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Scratch layout (doubles) for ncols target columns: split-K partials
+// [MAX_CHUNKS][OB][ncols], W [OB][ncols], inner T blocks [OB/8][256], tau [OB].
+struct Scr {
+  double *part, *w, *tin, *tau;
+};
+inline Scr scr_of(double* scratch, long ncols) {
+  Scr r;
+  r.part = scratch;
+  r.w = r.part + (long)MAX_CHUNKS * OB * ncols;
+  r.tin = r.w + (long)OB * ncols;
+  r.tau = r.tin + (OB / 8) * 256;
+  return r;
+}
+
+hipError_t launch_panel(hipStream_t s, double* A, long lda, int m, int j0, int pw, PanelCfg c, double* T,
+                        double* tau) {
+  if (prof::active(prof::QR_PANEL)) {
+    const double mp = m - j0;
+    prof::begin(s, prof::QR_PANEL, 8.0 * 2.0 * mp * pw, 4.0 * mp * pw * pw);
+  }
+  const size_t sh = (size_t)c.nt * (c.pw + 1) * sizeof(double);
+  if (c.rpt == 1)
+    hipLaunchKernelGGL((k_qr_panel<256, 1, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
+  else if (c.rpt == 2)
+    hipLaunchKernelGGL((k_qr_panel<256, 2, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
+  else if (c.rpt == 4)
+    hipLaunchKernelGGL((k_qr_panel<256, 4, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
+  else if (c.rpt == 8)
+    hipLaunchKernelGGL((k_qr_panel<256, 8, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
+  else if (c.rpt == 12)
+    hipLaunchKernelGGL((k_qr_panel<256, 12, 8>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
+  else
+    hipLaunchKernelGGL((k_qr_panel<256, 16, 8>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
+  hipError_t e = hipGetLastError();
+  prof::end(s);
+  return e;
+}
+
+// P = V^T Yv over all row chunks of the block (mp rows).
+hipError_t launch_vty(hipStream_t s, const double* A, long lda, int j0, int mp, int nb, const double* Y, long ldy,
+                      int yr0, int yc0, int ncols, int s_cols, double* part) {
+  const int ntiles = ceil_div(ncols, 64), nch = ceil_div(mp, KC);
+  if (prof::active(prof::BLOCK_VTY))
+    prof::begin(s, prof::BLOCK_VTY, 8.0 * ((double)mp * nb + (double)mp * (ncols - s_cols) + (double)nch * nb * ncols),
+                2.0 * mp * (double)nb * ncols);
+  hipLaunchKernelGGL(k_vty, dim3(ntiles * nch), dim3(256), 0, s, A, lda, j0, mp, nb, Y, ldy, yr0, yc0, ncols, s_cols,
+                     ntiles, part);
+  hipError_t e = hipGetLastError();
+  prof::end(s);
+  return e;
+}
+
+hipError_t launch_vupd(hipStream_t s, const double* A, long lda, int j0, int mp, int nb, const double* T, int trans,
+                       const double* W, long ldw, int wc0, double* Y, long ldy, int yr0, int yc0, int ncols) {
+  const int ntiles = ceil_div(ncols, 64), nch = ceil_div(mp, KC);
+  if (prof::active(prof::BLOCK_UPD))
+    prof::begin(s, prof::BLOCK_UPD, 8.0 * (2.0 * mp * ncols + (double)mp * nb + (double)nb * ncols),
+                2.0 * mp * (double)nb * ncols);
+  hipLaunchKernelGGL(k_vupd, dim3(ntiles * nch), dim3(256), 0, s, A, lda, j0, mp, nb, T, trans, W, ldw, wc0, Y, ldy,
+                     yr0, yc0, ncols, ntiles);
+  hipError_t e = hipGetLastError();
+  prof::end(s);
+  return e;
+}
+
+// Outer blocks [jb, jb + nb) of width OB (the last one narrower); inside
+// each, inner panels of width panel_cfg(m - j).pw, clipped to the block.
+// A pure function of (m, kmax): the factorisation and every later
+// application of Q walk the same sequence.
 template <typename F>
-inline hipError_t for_each_panel(int m, int kmax, F f) {
-  int j0 = 0, p = 0;
-  while (j0 < kmax) {
-    const PanelCfg c = panel_cfg(m - j0);
-    const int pw = std::min(c.pw, kmax - j0);
-    hipError_t e = f(p, j0, pw, c);
+inline hipError_t for_each_outer(int kmax, F f) {
+  for (int b = 0, jb = 0; jb < kmax; ++b, jb += OB) {
+    hipError_t e = f(b, jb, std::min(OB, kmax - jb));
     if (e != hipSuccess) return e;
-    j0 += pw;
-    ++p;
   }
   return hipSuccess;
 }
 
 }  // namespace
 
-int qr_num_panels(int m, int n) {
-  const int kmax = std::min(m, n);
-  int cnt = 0;
-  (void)for_each_panel(m, kmax, [&](int, int, int, PanelCfg) {
-    ++cnt;
-    return hipSuccess;
-  });
-  return cnt;
-}
+int qr_num_panels(int m, int n) { return ceil_div(std::min(m, n), OB) * (OB * OB / 256); }
 
 hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf, double* scratch) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (m > 4096) return hipErrorInvalidValue;
+  if (m > KC * MAX_CHUNKS) return hipErrorInvalidValue;
   const int kmax = std::min(m, n);
-  return for_each_panel(m, kmax, [&](int p, int j0, int pw, PanelCfg c) -> hipError_t {
-    double* T = Tbuf + (long)p * 256;
-    if (prof::active(prof::QR_PANEL)) {
-      const double mp = m - j0;
-      prof::begin(s, prof::QR_PANEL, 8.0 * 2.0 * mp * pw, 4.0 * mp * pw * pw);
+  const Scr sc = scr_of(scratch, n);
+  return for_each_outer(kmax, [&](int b, int jb, int nb) -> hipError_t {
+    hipError_t e;
+    // inner panels
+    int q = 0;
+    PanelList pl;
+    pl.np = 0;
+    for (int j = jb; j < jb + nb; ++q) {
+      const PanelCfg c = panel_cfg(m - j);
+      const int pw = std::min(c.pw, jb + nb - j);
+      pl.off[q] = j - jb;
+      pl.off[q + 1] = j - jb + pw;
+      pl.np = q + 1;
+      double* Tq = sc.tin + (long)q * 256;
+      e = launch_panel(s, A, lda, m, j, pw, c, Tq, sc.tau + (j - jb));
+      if (e != hipSuccess) return e;
+      const int c0 = j + pw, nc = jb + nb - c0;
+      if (nc > 0) {
+        e = apply_block(s, A, lda, j, m - j, j, pw, Tq, A, lda, j, c0, nc, 1, sc.part);
+        if (e != hipSuccess) return e;
+      }
+      j += pw;
     }
-    if (c.nt == 256 && c.rpt == 1)
-      hipLaunchKernelGGL((k_qr_panel<256, 1, 16>), dim3(1), dim3(256), 0, s, A, lda, m, j0, pw, T);
-    else if (c.nt == 256 && c.rpt == 2)
-      hipLaunchKernelGGL((k_qr_panel<256, 2, 16>), dim3(1), dim3(256), 0, s, A, lda, m, j0, pw, T);
-    else if (c.nt == 256)
-      hipLaunchKernelGGL((k_qr_panel<256, 4, 16>), dim3(1), dim3(256), 0, s, A, lda, m, j0, pw, T);
-    else if (c.rpt == 2)
-      hipLaunchKernelGGL((k_qr_panel<1024, 2, 16>), dim3(1), dim3(1024), 0, s, A, lda, m, j0, pw, T);
-    else
-      hipLaunchKernelGGL((k_qr_panel<1024, 4, 8>), dim3(1), dim3(1024), 0, s, A, lda, m, j0, pw, T);
-    hipError_t e = hipGetLastError();
-    prof::end(s);
+    // aggregated (V, T) of the block, then the trailing update with Q_b^T
+    const int mp = m - jb, ntrail = n - (jb + nb), nch = ceil_div(mp, KC);
+    const int ncw = nb + ntrail;
+    e = launch_vty(s, A, lda, jb, mp, nb, A, lda, jb, jb, ncw, nb, sc.part);
     if (e != hipSuccess) return e;
-    const int c0 = j0 + pw;
-    const int nc = n - c0;
-    if (nc > 0) e = apply_block(s, A, lda, j0, m - j0, j0, pw, T, A, lda, j0, c0, nc, 1, scratch);
-    return e;
+    hipLaunchKernelGGL(k_red, dim3(ceil_div((long)nb * ncw, 256)), dim3(256), 0, s, (const double*)sc.part, nch, ncw,
+                       nb, sc.w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double* T = Tbuf + (long)b * OB * OB;
+    hipLaunchKernelGGL(k_tbuild, dim3(1), dim3(256), 0, s, (const double*)sc.w, ncw, nb, (const double*)sc.tin, pl, T);
+    e = hipGetLastError();
+    if (e != hipSuccess || ntrail <= 0) return e;
+    return launch_vupd(s, A, lda, jb, mp, nb, T, 1, sc.w, ncw, nb, A, lda, jb, jb + nb, ntrail);
   });
 }
 
 hipError_t apply_q(hipStream_t s, const double* A, int m, int kref, long lda, const double* Tbuf, double* Y,
                    int ncols, long ldy, bool trans, double* scratch) {
   if (m <= 0 || ncols <= 0 || kref <= 0) return hipSuccess;
-  struct P {
-    int p, j0, pw;
-  };
-  P list[4096 / 8 + 8];
-  int np = 0;
-  (void)for_each_panel(m, kref, [&](int p, int j0, int pw, PanelCfg) {
-    list[np++] = {p, j0, pw};
-    return hipSuccess;
-  });
-  for (int t = 0; t < np; ++t) {
-    const P& q = trans ? list[t] : list[np - 1 - t];
-    hipError_t e = apply_block(s, A, lda, q.j0, m - q.j0, q.j0, q.pw, Tbuf + (long)q.p * 256, Y, ldy, q.j0, 0, ncols,
-                               trans ? 1 : 0, scratch);
+  if (m > KC * MAX_CHUNKS) return hipErrorInvalidValue;
+  const Scr sc = scr_of(scratch, ncols);
+  const int nblk = ceil_div(kref, OB);
+  for (int t = 0; t < nblk; ++t) {
+    const int b = trans ? t : nblk - 1 - t;
+    const int jb = b * OB, nb = std::min(OB, kref - jb);
+    const int mp = m - jb, nch = ceil_div(mp, KC);
+    hipError_t e = launch_vty(s, A, lda, jb, mp, nb, Y, ldy, jb, 0, ncols, 0, sc.part);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_red, dim3(ceil_div((long)nb * ncols, 256)), dim3(256), 0, s, (const double*)sc.part, nch,
+                       ncols, nb, sc.w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_vupd(s, A, lda, jb, mp, nb, Tbuf + (long)b * OB * OB, trans ? 1 : 0, sc.w, ncols, 0, Y, ldy, jb, 0,
+                    ncols);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

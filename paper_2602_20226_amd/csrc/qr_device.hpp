@@ -16,9 +16,15 @@
 
 namespace qtt {
 
+// stage (optional, NT * (PW + 1) doubles of LDS): when given, the panel is
+// moved between global memory and registers through LDS in row-contiguous,
+// coalesced order (a thread's own row segment read directly would touch one
+// cache line per lane and instruction).  tau_out (optional) receives the pw
+// reflector coefficients.
 template <int NT, int RPT, int PW>
 __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, int m, int j0, int pw,
-                                             double* __restrict__ Tout) {
+                                             double* __restrict__ Tout, double* __restrict__ stage = nullptr,
+                                             double* __restrict__ tau_out = nullptr) {
   constexpr int NW = NT / 64;
   __shared__ double red[NT];
   __shared__ double bc[16];
@@ -27,12 +33,39 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
   __shared__ double alphaS;
   const int tid = threadIdx.x;
   const int mp = m - j0;
+  constexpr int SW = PW + 1;  // LDS row stride (odd: conflict-free row reads)
   double a[RPT][PW];
+  if (stage) {
+    // all global loads first, in coalesced order: a[r][q] = element
+    // e = tid + NT q of row block r (row e / PW, column e % PW) ...
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int lr = tid + r * NT;
+    for (int r = 0; r < RPT; ++r)
 #pragma unroll
-    for (int c = 0; c < PW; ++c) a[r][c] = (lr < mp && c < pw) ? A[(long)(j0 + lr) * lda + j0 + c] : 0.0;
+      for (int q = 0; q < PW; ++q) {
+        const int e = tid + NT * q;
+        const int gr = r * NT + e / PW, c = e % PW;
+        a[r][q] = (gr < mp && c < pw) ? A[(long)(j0 + gr) * lda + j0 + c] : 0.0;
+      }
+    // ... then one LDS transpose per row block into a[r][c] = row tid + r NT
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int e = tid + NT * q;
+        stage[(e / PW) * SW + e % PW] = a[r][q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < PW; ++c) a[r][c] = stage[tid * SW + c];
+      __syncthreads();
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int lr = tid + r * NT;
+#pragma unroll
+      for (int c = 0; c < PW; ++c) a[r][c] = (lr < mp && c < pw) ? A[(long)(j0 + lr) * lda + j0 + c] : 0.0;
+    }
   }
   for (int t = tid; t < 16 * 17; t += NT) (&Ts[0][0])[t] = 0.0;
 
@@ -105,16 +138,41 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
       __syncthreads();
     }
   }
+  if (stage) {
+    // LDS transposes back to coalesced order, then all global stores
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int lr = tid + r * NT;
-    if (lr < mp) {
+    for (int r = 0; r < RPT; ++r) {
 #pragma unroll
-      for (int c = 0; c < PW; ++c)
-        if (c < pw) A[(long)(j0 + lr) * lda + j0 + c] = a[r][c];
+      for (int c = 0; c < PW; ++c) stage[tid * SW + c] = a[r][c];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int e = tid + NT * q;
+        a[r][q] = stage[(e / PW) * SW + e % PW];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int e = tid + NT * q;
+        const int gr = r * NT + e / PW, c = e % PW;
+        if (gr < mp && c < pw) A[(long)(j0 + gr) * lda + j0 + c] = a[r][q];
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int lr = tid + r * NT;
+      if (lr < mp) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c)
+          if (c < pw) A[(long)(j0 + lr) * lda + j0 + c] = a[r][c];
+      }
     }
   }
   for (int t = tid; t < 256; t += NT) Tout[t] = Ts[t >> 4][t & 15];
+  if (tau_out && tid < pw) tau_out[tid] = Ts[tid][tid];
 }
 
 

@@ -48,17 +48,22 @@ hipError_t contract_backward_w(hipStream_t s, bool mpo, const T* X, int rx0, int
                                const T* dC, int rw0, int di, int rw1, T* dW);
 
 // ---------------------------------------------------------------- QR
-constexpr int QR_PB = 16;  // panel width (reflectors per T block)
+constexpr int QR_PB = 16;  // inner panel width of the batched workgroup QR
 // Blocked Householder QR of the m x n row-major matrix A (in place).  Reflector
-// vectors below the diagonal, R on and above; T blocks (QR_PB x QR_PB each,
-// one per panel) in Tbuf.  Supports m <= 4096.  scratch: qr_scratch_doubles(n).
+// vectors below the diagonal, R on and above; one 64 x 64 compact-WY factor
+// T per 64-column block of reflectors in Tbuf (qr_num_panels(m, n) * 256
+// doubles).  Supports m <= 4096.  scratch: qr_scratch_doubles(n).
 hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf, double* scratch);
-// Y <- Q Y (trans=false, panels in reverse order) or Q^T Y (trans=true,
+// Y <- Q Y (trans=false, blocks in reverse order) or Q^T Y (trans=true,
 // forward order); Y has m rows.  scratch: qr_scratch_doubles(ncols).
 hipError_t apply_q(hipStream_t s, const double* A, int m, int kref, long lda, const double* Tbuf,
                    double* Y, int ncols, long ldy, bool trans, double* scratch);
-// Partial-product scratch of one block-reflector application on ncols columns.
-inline long qr_scratch_doubles(long ncols) { return 16L * 16L * (ncols < 1 ? 1 : ncols); }
+// Scratch of one QR or Q application on ncols columns: split-K partials
+// (16 chunks x 64 x ncols), the 64 x ncols product, inner T blocks and tau.
+inline long qr_scratch_doubles(long ncols) {
+  const long nc = ncols < 1 ? 1 : ncols;
+  return 16L * 64L * nc + 64L * nc + 8L * 256L + 64L;
+}
 // R = upper trapezoid of A[0:kr, 0:n] (zeros below the diagonal) into Rout (ld n).
 hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, double* Rout);
 
@@ -105,7 +110,7 @@ int qr_num_panels(int m, int n);
 
 // ---------------------------------------------------------------- launch profiling
 namespace prof {
-enum Class { APPLY_PANEL = 0, JACOBI = 1, QR_PANEL = 2 };
+enum Class { APPLY_PANEL = 0, JACOBI = 1, QR_PANEL = 2, BLOCK_VTY = 3, BLOCK_UPD = 4 };
 bool active(int cls);
 void begin(hipStream_t st, int cls, double bytes, double flops);
 void end(hipStream_t st);
