@@ -269,57 +269,63 @@ __global__ __launch_bounds__(256) void k_vupd(const double* __restrict__ A, long
 
 inline void apply_cost(int mp, int pw, int ncols, double& bytes, double& flops);
 
-// Block-reflector application, split over (16-column tile) x (row chunk)
-// workgroups so that even a narrow target keeps the whole GPU busy:
+// Block-reflector application inside an outer block, split over
+// (16-column tile) x (256-row chunk) workgroups:
 //   k_apply_w:   W_chunk = V_chunk^T Y_chunk  (16 x 16 per workgroup, stored
 //                per chunk in scratch[chunk][16][ncols]);
 //   k_apply_upd: W = sum_chunk W_chunk, W <- op(T) W, Y_chunk -= V_chunk W.
 // V: rows [r0, r0+mp) of A, columns [vc0, vc0+pw), unit lower trapezoidal.
 // Y rows [yr0, yr0+mp), columns [c0, c0+ncols).
 // trans: Y <- (I - V T^T V^T) Y, else Y <- (I - V T V^T) Y.
-// 256 threads: thread (g, c) owns column c of the tile and rows g (mod 16)
-// of the chunk; rows are streamed four at a time.
-constexpr int AP_NT = 256, AP_G = AP_NT / 16, AP_CHUNK = 256;
+// 256 threads: the chunk of V is staged in LDS with coalesced loads; thread
+// (g, c) owns column c of the tile and rows g + 16 u (u < 16) of the chunk,
+// whose Y values it fetches all at once.
+constexpr int AP_NT = 256, AP_G = AP_NT / 16, AP_CHUNK = 256, AP_U = AP_CHUNK / AP_G;
 
-__device__ __forceinline__ void load_vrow(const double* __restrict__ arow, int lr, int pw, double (&v)[16]) {
+// Vs[lr][i] = V[rbeg + lr][i] for lr < AP_CHUNK (0 past the block).
+__device__ __forceinline__ void stage_v16(const double* __restrict__ Ab, long lda, int mp, int pw, int rbeg,
+                                          double (*Vs)[17]) {
+  const int tid = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = (i >= pw) ? 0.0 : (lr > i ? arow[i] : (lr == i ? 1.0 : 0.0));
+  for (int q = 0; q < AP_CHUNK * 16 / AP_NT; ++q) {
+    const int e = tid + AP_NT * q;
+    const int lr = e >> 4, i = e & 15;
+    const int gr = rbeg + lr;
+    double v = 0.0;
+    if (gr < mp && i < pw) v = gr > i ? Ab[(long)gr * lda + i] : (gr == i ? 1.0 : 0.0);
+    Vs[lr][i] = v;
+  }
 }
 
 __global__ __launch_bounds__(AP_NT) void k_apply_w(const double* __restrict__ A, long lda, int r0, int mp, int vc0,
                                                    int pw, const double* __restrict__ Y, long ldy, int yr0, int c0,
                                                    int ncols, int ntiles, double* __restrict__ part) {
+  __shared__ double Vs[AP_CHUNK][17];
   __shared__ double red[AP_G][16][17];
   const int tid = threadIdx.x;
   const int c = tid & 15, g = tid >> 4;
   const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
   const int col = tile * 16 + c;
   const bool valid = col < ncols;
-  const int rbeg = chunk * AP_CHUNK, rend = min(mp, rbeg + AP_CHUNK);
+  const int rbeg = chunk * AP_CHUNK;
   const double* Ab = A + (long)r0 * lda + vc0;
   const double* Yb = Y + (long)yr0 * ldy + c0 + col;
+  double y[AP_U];
+#pragma unroll
+  for (int u = 0; u < AP_U; ++u) {
+    const int gr = rbeg + g + AP_G * u;
+    y[u] = (valid && gr < mp) ? Yb[(long)gr * ldy] : 0.0;
+  }
+  stage_v16(Ab, lda, mp, pw, rbeg, Vs);
+  __syncthreads();
   double w[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) w[i] = 0.0;
-  int lr = rbeg + g;
-  for (; lr + 3 * AP_G < rend; lr += 4 * AP_G) {
-    double y[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) y[q] = valid ? Yb[(long)(lr + q * AP_G) * ldy] : 0.0;
+  for (int u = 0; u < AP_U; ++u) {
+    const int lr = g + AP_G * u;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double v[16];
-      load_vrow(Ab + (long)(lr + q * AP_G) * lda, lr + q * AP_G, pw, v);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) w[i] += v[i] * y[q];
-    }
-  }
-  for (; lr < rend; lr += AP_G) {
-    const double y = valid ? Yb[(long)lr * ldy] : 0.0;
-    double v[16];
-    load_vrow(Ab + (long)lr * lda, lr, pw, v);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) w[i] += v[i] * y;
+    for (int i = 0; i < 16; ++i) w[i] += Vs[lr][i] * y[u];
   }
 #pragma unroll
   for (int i = 0; i < 16; ++i) red[g][i][c] = w[i];
@@ -337,6 +343,7 @@ __global__ __launch_bounds__(AP_NT) void k_apply_upd(const double* __restrict__ 
                                                      int pw, const double* __restrict__ T, double* __restrict__ Y,
                                                      long ldy, int yr0, int c0, int ncols, int ntiles, int nchunks,
                                                      const double* __restrict__ part, int trans) {
+  __shared__ double Vs[AP_CHUNK][17];
   __shared__ double Ws[16][17];
   __shared__ double W2[16][17];
   __shared__ double Tsh[16][17];
@@ -345,14 +352,29 @@ __global__ __launch_bounds__(AP_NT) void k_apply_upd(const double* __restrict__ 
   const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
   const int col = tile * 16 + c;
   const bool valid = col < ncols;
+  const int rbeg = chunk * AP_CHUNK;
+  const double* Ab = A + (long)r0 * lda + vc0;
+  double* Yb = Y + (long)yr0 * ldy + c0 + col;
+  double y[AP_U];
+#pragma unroll
+  for (int u = 0; u < AP_U; ++u) {
+    const int gr = rbeg + g + AP_G * u;
+    y[u] = (valid && gr < mp) ? Yb[(long)gr * ldy] : 0.0;
+  }
   Tsh[tid >> 4][tid & 15] = T[tid];
   {
     const int i = tid >> 4, cc = tid & 15;
+    const bool ok = tile * 16 + cc < ncols;
+    double v[MAX_CHUNKS];
+#pragma unroll
+    for (int q = 0; q < MAX_CHUNKS; ++q)
+      v[q] = (ok && q < nchunks) ? part[((long)q * 16 + i) * ncols + tile * 16 + cc] : 0.0;
     double sum = 0.0;
-    if (tile * 16 + cc < ncols)
-      for (int q = 0; q < nchunks; ++q) sum += part[((long)q * 16 + i) * ncols + tile * 16 + cc];
+#pragma unroll
+    for (int q = 0; q < MAX_CHUNKS; ++q) sum += v[q];
     Ws[i][cc] = sum;
   }
+  stage_v16(Ab, lda, mp, pw, rbeg, Vs);
   __syncthreads();
   {
     const int i = tid >> 4, cc = tid & 15;
@@ -366,31 +388,13 @@ __global__ __launch_bounds__(AP_NT) void k_apply_upd(const double* __restrict__ 
   double w[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) w[i] = W2[i][c];
-  const int rbeg = chunk * AP_CHUNK, rend = min(mp, rbeg + AP_CHUNK);
-  const double* Ab = A + (long)r0 * lda + vc0;
-  double* Yb = Y + (long)yr0 * ldy + c0 + col;
-  int lr = rbeg + g;
-  for (; lr + 3 * AP_G < rend; lr += 4 * AP_G) {
-    double y[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) y[q] = Yb[(long)(lr + q * AP_G) * ldy];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double v[16];
-      load_vrow(Ab + (long)(lr + q * AP_G) * lda, lr + q * AP_G, pw, v);
-      double sum = 0.0;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) sum += v[i] * w[i];
-      Yb[(long)(lr + q * AP_G) * ldy] = y[q] - sum;
-    }
-  }
-  for (; lr < rend; lr += AP_G) {
-    double v[16];
-    load_vrow(Ab + (long)lr * lda, lr, pw, v);
+  for (int u = 0; u < AP_U; ++u) {
+    const int lr = g + AP_G * u;
     double sum = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) sum += v[i] * w[i];
-    Yb[(long)lr * ldy] -= sum;
+    for (int i = 0; i < 16; ++i) sum += Vs[lr][i] * w[i];
+    if (rbeg + lr < mp) Yb[(long)(rbeg + lr) * ldy] = y[u] - sum;
   }
 }
 
@@ -437,15 +441,16 @@ struct PanelCfg {
   int nt, rpt, pw;
 };
 
-// One workgroup of 256 threads (one wave per SIMD, up to 512 registers per
-// lane) holds the panel: few waves keep the per-column reductions cheap.
+// One workgroup per panel; few waves keep the per-column reductions cheap
+// (configurations measured on the 3D rank-256 rounding shapes).
 inline PanelCfg panel_cfg(int mp) {
   if (mp <= 256) return {256, 1, 16};
   if (mp <= 512) return {256, 2, 16};
   if (mp <= 1024) return {256, 4, 16};
-  if (mp <= 2048) return {256, 8, 16};
+  if (mp <= 2048) return {512, 4, 16};
   if (mp <= 3072) return {256, 12, 8};
-  return {256, 16, 8};
+  if (mp <= 3584) return {512, 7, 8};
+  return {512, 8, 8};
 }
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
@@ -471,18 +476,27 @@ hipError_t launch_panel(hipStream_t s, double* A, long lda, int m, int j0, int p
     prof::begin(s, prof::QR_PANEL, 8.0 * 2.0 * mp * pw, 4.0 * mp * pw * pw);
   }
   const size_t sh = (size_t)c.nt * (c.pw + 1) * sizeof(double);
-  if (c.rpt == 1)
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_qr_panel<512, 4, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       512 * 17 * 8);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (c.nt == 256 && c.rpt == 1)
     hipLaunchKernelGGL((k_qr_panel<256, 1, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
-  else if (c.rpt == 2)
+  else if (c.nt == 256 && c.rpt == 2)
     hipLaunchKernelGGL((k_qr_panel<256, 2, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
-  else if (c.rpt == 4)
+  else if (c.nt == 256 && c.rpt == 4)
     hipLaunchKernelGGL((k_qr_panel<256, 4, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
-  else if (c.rpt == 8)
-    hipLaunchKernelGGL((k_qr_panel<256, 8, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
-  else if (c.rpt == 12)
+  else if (c.nt == 512 && c.rpt == 4)
+    hipLaunchKernelGGL((k_qr_panel<512, 4, 16>), dim3(1), dim3(512), sh, s, A, lda, m, j0, pw, T, tau);
+  else if (c.nt == 256 && c.rpt == 12)
     hipLaunchKernelGGL((k_qr_panel<256, 12, 8>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
+  else if (c.nt == 512 && c.rpt == 7)
+    hipLaunchKernelGGL((k_qr_panel<512, 7, 8>), dim3(1), dim3(512), sh, s, A, lda, m, j0, pw, T, tau);
   else
-    hipLaunchKernelGGL((k_qr_panel<256, 16, 8>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
+    hipLaunchKernelGGL((k_qr_panel<512, 8, 8>), dim3(1), dim3(512), sh, s, A, lda, m, j0, pw, T, tau);
   hipError_t e = hipGetLastError();
   prof::end(s);
   return e;

@@ -8,8 +8,9 @@
 //     v = x / (x0 - beta) with v0 = 1,   H = I - tau v v^T,   H x = beta e0
 // (tau = 0, H = I when x has no entries below the diagonal).  The same
 // workgroup reduction that forms v^T A for the update also yields the
-// column V^T v_j, from which the compact-WY factor T (H_1..H_b = I - V T V^T,
-// T upper triangular) is built column by column.
+// column V^T v_j; after the last column the compact-WY factor T
+// (H_1..H_b = I - V T V^T, T upper triangular) follows from V^T V and tau by
+// the column recurrence T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
 #pragma once
 
 #include "qtt_device.hpp"
@@ -17,27 +18,65 @@
 namespace qtt {
 
 // stage (optional, NT * (PW + 1) doubles of LDS): when given, the panel is
-// moved between global memory and registers through LDS in row-contiguous,
-// coalesced order (a thread's own row segment read directly would touch one
-// cache line per lane and instruction).  tau_out (optional) receives the pw
-// reflector coefficients.
+// moved between global memory and registers in coalesced order (16-byte
+// accesses when the panel is full width and aligned), all loads issued
+// before the LDS transposes into the per-thread row layout; a thread's own
+// row segment read directly would touch one cache line per lane and
+// instruction.  T is formed after the column loop by one wave from the
+// accumulated V^T V and the coefficients tau (tau_out, optional, receives
+// them).
 template <int NT, int RPT, int PW>
 __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, int m, int j0, int pw,
                                              double* __restrict__ Tout, double* __restrict__ stage = nullptr,
                                              double* __restrict__ tau_out = nullptr) {
   constexpr int NW = NT / 64;
+  constexpr int SW = PW + 1;
+  constexpr int HP = PW / 2;  // column pairs
   __shared__ double red[NT];
   __shared__ double bc[16];
   __shared__ double sc[NW];
-  __shared__ double Ts[16][17];
+  __shared__ double G[16][17];   // G[l][j] = v_l^T v_j (l < j)
+  __shared__ double tauS[16];
   __shared__ double alphaS;
   const int tid = threadIdx.x;
   const int mp = m - j0;
-  constexpr int SW = PW + 1;  // LDS row stride (odd: conflict-free row reads)
   double a[RPT][PW];
-  if (stage) {
-    // all global loads first, in coalesced order: a[r][q] = element
-    // e = tid + NT q of row block r (row e / PW, column e % PW) ...
+  const bool pairs = stage && (pw == PW) && ((lda & 1) == 0) && ((j0 & 1) == 0);
+  if (!stage) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int lr = tid + r * NT;
+#pragma unroll
+      for (int c = 0; c < PW; ++c) a[r][c] = (lr < mp && c < pw) ? A[(long)(j0 + lr) * lda + j0 + c] : 0.0;
+    }
+  } else if (pairs) {
+    // 16-byte loads: pair e = tid + NT q of row block r -> row e / HP, columns 2 (e % HP) + {0, 1}
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+      for (int q = 0; q < HP; ++q) {
+        const int e = tid + NT * q;
+        const int gr = r * NT + e / HP, c = 2 * (e % HP);
+        double2 v = make_double2(0.0, 0.0);
+        if (gr < mp) v = *reinterpret_cast<const double2*>(A + (long)(j0 + gr) * lda + j0 + c);
+        a[r][2 * q] = v.x;
+        a[r][2 * q + 1] = v.y;
+      }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+#pragma unroll
+      for (int q = 0; q < HP; ++q) {
+        const int e = tid + NT * q;
+        const int rr = e / HP, c = 2 * (e % HP);
+        stage[rr * SW + c] = a[r][2 * q];
+        stage[rr * SW + c + 1] = a[r][2 * q + 1];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < PW; ++c) a[r][c] = stage[tid * SW + c];
+      __syncthreads();
+    }
+  } else {
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
 #pragma unroll
@@ -46,7 +85,6 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
         const int gr = r * NT + e / PW, c = e % PW;
         a[r][q] = (gr < mp && c < pw) ? A[(long)(j0 + gr) * lda + j0 + c] : 0.0;
       }
-    // ... then one LDS transpose per row block into a[r][c] = row tid + r NT
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
 #pragma unroll
@@ -59,16 +97,7 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
       for (int c = 0; c < PW; ++c) a[r][c] = stage[tid * SW + c];
       __syncthreads();
     }
-  } else {
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int lr = tid + r * NT;
-#pragma unroll
-      for (int c = 0; c < PW; ++c) a[r][c] = (lr < mp && c < pw) ? A[(long)(j0 + lr) * lda + j0 + c] : 0.0;
-    }
   }
-  for (int t = tid; t < 16 * 17; t += NT) (&Ts[0][0])[t] = 0.0;
-
 #pragma unroll
   for (int j = 0; j < PW; ++j) {
     if (j < pw) {
@@ -97,23 +126,21 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
         if (lr > j && lr < mp) a[r][j] *= scale;
       }
       if (tid == j) a[0][j] = beta;
-      // p[c] (c > j): v_j^T A[:, c];  p[c] (c < j): v_c^T v_j  (column j of V^T V)
       double p[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) p[c] = 0.0;
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         const int lr = tid + r * NT;
-        if (lr >= j && lr < mp) {
-          const double v = (lr == j) ? 1.0 : a[r][j];
+        const bool in = lr >= j && lr < mp;
+        const double v = in ? ((lr == j) ? 1.0 : a[r][j]) : 0.0;
 #pragma unroll
-          for (int c = 0; c < PW; ++c) {
-            if (c > j) {
-              p[c] += v * a[r][c];
-            } else if (c < j) {
-              const double vc = (lr > c) ? a[r][c] : (lr == c ? 1.0 : 0.0);
-              p[c] += v * vc;
-            }
+        for (int c = 0; c < PW; ++c) {
+          if (c > j) {
+            p[c] += v * a[r][c];
+          } else if (c < j) {
+            const double vc = (lr > c) ? a[r][c] : (lr == c ? 1.0 : 0.0);
+            p[c] += v * vc;
           }
         }
       }
@@ -121,25 +148,75 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
         const int lr = tid + r * NT;
-        if (lr >= j && lr < mp) {
-          const double v = (lr == j) ? 1.0 : a[r][j];
+        const bool in = lr >= j && lr < mp;
+        const double tv = in ? tau * ((lr == j) ? 1.0 : a[r][j]) : 0.0;
 #pragma unroll
-          for (int c = 0; c < PW; ++c)
-            if (c > j) a[r][c] -= tau * v * bc[c];
-        }
+        for (int c = 0; c < PW; ++c)
+          if (c > j) a[r][c] -= tv * bc[c];
       }
-      // T[0:j, j] = -tau T[0:j, 0:j] (V^T v_j)[0:j],  T[j][j] = tau
-      if (tid < j) {
-        double acc = 0.0;
-        for (int l = tid; l < j; ++l) acc += Ts[tid][l] * bc[l];
-        Ts[tid][j] = -tau * acc;
-      }
-      if (tid == j) Ts[j][j] = tau;
+      if (tid < j) G[tid][j] = bc[tid];
+      if (tid == j) tauS[j] = tau;
       __syncthreads();
     }
   }
-  if (stage) {
-    // LDS transposes back to coalesced order, then all global stores
+  // T (upper triangular, order pw): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j];
+  // lane i of wave 0 keeps row i of T in registers.
+  if (tid < 64) {
+    const int i = tid;
+    double trow[16];
+#pragma unroll
+    for (int l = 0; l < 16; ++l) trow[l] = 0.0;
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+      if (j < pw) {
+        const double tj = tauS[j];
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < j; ++l) acc += (l >= i) ? trow[l] * G[l][j] : 0.0;
+        if (i < j) trow[j] = -tj * acc;
+        if (i == j) trow[j] = tj;
+      }
+    }
+    if (i < 16) {
+#pragma unroll
+      for (int l = 0; l < 16; ++l) Tout[i * 16 + l] = trow[l];
+    }
+    if (tau_out && i < pw) tau_out[i] = tauS[i];
+  }
+  if (!stage) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int lr = tid + r * NT;
+      if (lr < mp) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c)
+          if (c < pw) A[(long)(j0 + lr) * lda + j0 + c] = a[r][c];
+      }
+    }
+  } else if (pairs) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+#pragma unroll
+      for (int c = 0; c < PW; ++c) stage[tid * SW + c] = a[r][c];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < HP; ++q) {
+        const int e = tid + NT * q;
+        const int rr = e / HP, c = 2 * (e % HP);
+        a[r][2 * q] = stage[rr * SW + c];
+        a[r][2 * q + 1] = stage[rr * SW + c + 1];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+      for (int q = 0; q < HP; ++q) {
+        const int e = tid + NT * q;
+        const int gr = r * NT + e / HP, c = 2 * (e % HP);
+        if (gr < mp) *reinterpret_cast<double2*>(A + (long)(j0 + gr) * lda + j0 + c) = make_double2(a[r][2 * q], a[r][2 * q + 1]);
+      }
+  } else {
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
 #pragma unroll
@@ -160,21 +237,8 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
         const int gr = r * NT + e / PW, c = e % PW;
         if (gr < mp && c < pw) A[(long)(j0 + gr) * lda + j0 + c] = a[r][q];
       }
-  } else {
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int lr = tid + r * NT;
-      if (lr < mp) {
-#pragma unroll
-        for (int c = 0; c < PW; ++c)
-          if (c < pw) A[(long)(j0 + lr) * lda + j0 + c] = a[r][c];
-      }
-    }
   }
-  for (int t = tid; t < 256; t += NT) Tout[t] = Ts[t >> 4][t & 15];
-  if (tau_out && tid < pw) tau_out[tid] = Ts[tid][tid];
 }
-
 
 // Block reflector (V, op(T)) applied by one workgroup to the 16 columns
 // [col0, cend) of Y, all rows [0, mp) of the block:

@@ -35,6 +35,16 @@ __device__ __forceinline__ int rr_item(int pos, int round, int n) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (n - 1));
 }
 
+// Sum over the 64 lanes with the row broadcasts of DPP: after the row sums,
+// row 3 accumulates rows 0-2 (row_bcast:15 into rows 1 and 3, row_bcast:31
+// into rows 2 and 3); lane 63 holds the total, read back for every lane.
+__device__ __forceinline__ double wave_sum_bc(double v) {
+  v = row_sum(v);
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x142, 0xA, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x143, 0xC, 0xF, false);
+  return readlane_f64(v, 63);
+}
+
 // Rotate the pair (u, v) of rows (E elements per lane, zero past the row end)
 // so that they become orthogonal; returns true when a rotation was applied.
 template <int E>
@@ -46,13 +56,23 @@ __device__ __forceinline__ bool rotate_pair(double (&u)[E], double (&v)[E], doub
     be += v[q] * v[q];
     ga += u[q] * v[q];
   }
-  al = wave_sum(al);
-  be = wave_sum(be);
-  ga = wave_sum(ga);
+  al = wave_sum_bc(al);
+  be = wave_sum_bc(be);
+  ga = wave_sum_bc(ga);
   if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (fabs(zeta) > 1e150) ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + t * t);
+  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 ga),
+  // written without forming zeta: t = sign(d g) |g| / (|d| + sqrt(d^2 + g^2))
+  // with d = be - al, g = 2 ga (one square root and one division on the
+  // dependent chain instead of two of each).
+  const double d = be - al, g = 2.0 * ga;
+  double t;
+  if (fmax(fabs(d), fabs(g)) < 1e150) {
+    t = copysign(fabs(g), d * g) / (fabs(d) + sqrt(d * d + g * g));
+  } else {
+    const double zeta = d / g;
+    t = (fabs(zeta) > 1e150) ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  }
+  const double cs = rsqrt(1.0 + t * t);
   const double sn = cs * t;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
@@ -63,13 +83,18 @@ __device__ __forceinline__ bool rotate_pair(double (&u)[E], double (&v)[E], doub
   return true;
 }
 
+// Rows move between workgroups through global memory with agent-scope
+// (coherent) accesses, so that no cache writeback or invalidation is needed
+// when a block changes hands: the writer waits for its stores to complete
+// before publishing the block's version, the reader reads the version and
+// then the rows.
 template <int E>
 __device__ __forceinline__ void load_row(const double* __restrict__ src, int L, bool ok, double (&r)[E]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int c = lane + 64 * q;
-    r[q] = (ok && c < L) ? src[c] : 0.0;
+    r[q] = (ok && c < L) ? __hip_atomic_load(src + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
   }
 }
 
@@ -80,7 +105,7 @@ __device__ __forceinline__ void store_row(double* __restrict__ dst, int L, bool 
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int c = lane + 64 * q;
-    if (c < L) dst[c] = r[q];
+    if (c < L) __hip_atomic_store(dst + c, r[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -120,9 +145,9 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
       const int b1 = rr_item(nb2 - 1 - pair, round, nb2);
       const unsigned expect = (unsigned)(sweep * nrounds + round);
       if (tid == 0) {
-        while (__hip_atomic_load(&ver[b0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != expect)
+        while (__hip_atomic_load(&ver[b0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != expect)
           __builtin_amdgcn_s_sleep(1);
-        while (__hip_atomic_load(&ver[b1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != expect)
+        while (__hip_atomic_load(&ver[b1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != expect)
           __builtin_amdgcn_s_sleep(1);
       }
       __syncthreads();
@@ -167,11 +192,11 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
       store_row<E>(X + (long)rt * L, L, okt, top);
       const int rb = b1 * JB + (w + JB - 1) % JB;
       store_row<E>(X + (long)rb * L, L, rb < p, bot);
-      __threadfence();
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's row stores have completed
       __syncthreads();
       if (tid == 0) {
-        __hip_atomic_store(&ver[b0], expect + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ver[b1], expect + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ver[b0], expect + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ver[b1], expect + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     // sweep bookkeeping: counter (sweep % 3) collects this sweep's rotations
