@@ -85,6 +85,10 @@ def main():
     ap.add_argument("--prec", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-breakdown", action="store_true",
+                    help="skip the per-class profiled steps (and the roofline object)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the measurement, run one plain device copy of this many MiB")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the single-chain rounding "
@@ -161,28 +165,78 @@ def main():
         out["fp64_ms_per_step"] = sec64 * 1e3
         out["speedup_vs_fp64_path"] = sec64 / sec
 
-    # Roofline of the dominant kernel (the Householder block-reflector
-    # application): one extra step with that kernel class bracketed by HIP
-    # events on its launch stream inside libqtt.
-    Q.profile_start("apply_panel", 200000)
-    step(args.prec)
-    launches, kms, kbytes, kflops = Q.profile_stop()
-    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
-    out["roofline"] = {
-        "bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
-        "traffic": None, "kernel": "k_apply_w+k_apply_upd", "launches": launches,
-        "avg_us": 1e3 * kms / max(launches, 1), "share_of_step": kms / (sec * 1e3),
-        "alg_bytes_per_launch": kbytes / max(launches, 1), "alg_flop_per_launch": kflops / max(launches, 1),
+    # Per-class kernel time: one extra step per class with every launch of
+    # that class bracketed by HIP events on its launch stream inside libqtt.
+    # The roofline is reported for the class that takes the most time.
+    classes = {
+        # class: (bound, peak, unit, kernels, source file of the kernel)
+        "jacobi": ("alu", 78600.0, "GFLOP/s", "k_jacobi", "svd.hip"),
+        "qr_panel": ("alu", 78600.0, "GFLOP/s", "k_qr_panel", "qr.hip"),
+        "apply_panel": ("hbm", 8000.0, "GB/s", "k_apply_w+k_apply_upd", "qr.hip"),
+        "block_vty": ("mfma", 78600.0, "GFLOP/s", "k_vty", "qr.hip"),
+        "block_upd": ("mfma", 78600.0, "GFLOP/s", "k_vupd", "qr.hip"),
     }
-    Q.profile_start("jacobi", 1000)
-    step(args.prec)
-    jl, jms, _, _ = Q.profile_stop()
-    out["jacobi_ms_per_step"] = jms
-    out["jacobi_launches"] = jl
+    kernels = {}
+    for cls, (bound, peak, unit, kname, src) in ({} if args.no_kernel_breakdown else classes).items():
+        Q.profile_start(cls, 20000)
+        step(args.prec)
+        launches, kms, kbytes, kflops = Q.profile_stop()
+        work = kbytes if bound == "hbm" else kflops
+        achieved = work / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+        kernels[cls] = {
+            "kernel": kname, "bound": bound, "launches": launches, "ms_per_step": kms,
+            "avg_us": 1e3 * kms / max(launches, 1), "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "alg_bytes_per_launch": kbytes / max(launches, 1),
+            "alg_flop_per_launch": kflops / max(launches, 1), "source": src,
+        }
+    if kernels:
+        add_roofline(out, kernels, sec)
+    if args.calib_copy_mb > 0:
+        # one plain elementwise pass of known size (read n doubles, write n
+        # doubles), for scaling the hardware byte counters taken on this run
+        n = int(args.calib_copy_mb) * (1 << 20) // 8
+        src_t = torch.empty(n, dtype=torch.float64, device=dev).uniform_()
+        dst_t = torch.mul(src_t, 1.5)
+        torch.cuda.synchronize()
+        del src_t, dst_t
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, ra, rb, d, dj)
     print(json.dumps(out), flush=True)
+
+
+def add_roofline(out, kernels, sec):
+    top = max(kernels, key=lambda c: kernels[c]["ms_per_step"])
+    k = kernels[top]
+    scale = 1e-3 if k["unit"] == "GFLOP/s" else 1.0  # report TFLOP/s or GB/s
+    out["roofline"] = {
+        "bound": k["bound"], "achieved": k["achieved"] * scale, "peak": k["peak"] * scale,
+        "unit": "TFLOP/s" if k["unit"] == "GFLOP/s" else "GB/s", "frac": k["frac"],
+        "traffic": measured_traffic(k["kernel"], k["source"]),
+        "kernel": k["kernel"], "launches": k["launches"], "avg_us": k["avg_us"],
+        "share_of_step": k["ms_per_step"] / (sec * 1e3),
+        "alg_bytes_per_launch": k["alg_bytes_per_launch"], "alg_flop_per_launch": k["alg_flop_per_launch"],
+    }
+    out["kernels"] = {c: {key: v[key] for key in ("kernel", "bound", "launches", "ms_per_step", "avg_us", "achieved",
+                                                   "unit", "frac")} for c, v in kernels.items()}
+
+
+def measured_traffic(kernel, source):
+    """HBM bytes per launch from the committed hardware-counter summary of this
+    kernel, if it was taken on the current source of the kernel; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel.split('+')[0]}.json")
+    src = os.path.join(ROOT, "paper_2602_20226_amd", "csrc", source)
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(w, ra, rb, d, dj):

@@ -399,6 +399,11 @@ int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_in
     const TruncOut t = *w.h->pin_trunc;
     const int swp = *w.h->pin_int;
     if (swp >= kMaxSweeps) return QTT_ERR_NOCONV;
+    {
+      double jb = 0.0, jf = 0.0;
+      jacobi_sweep_cost(p, L, &jb, &jf);
+      prof::amend(prof::JACOBI, swp * jb, swp * jf);
+    }
     maxsw = std::max(maxsw, swp);
     const int r = t.rank;
     if (info) {

@@ -49,37 +49,48 @@ __device__ __forceinline__ double vel(const double* __restrict__ Ab, long lda, i
   return k == i ? 1.0 : Ab[(long)k * lda + i];
 }
 
+// V of an outer block is staged in LDS in slabs of SL rows (double
+// buffered: the next slab's global loads are in flight while the current
+// one feeds the MFMAs), so that the four waves of a workgroup share it.
+constexpr int SL = 64;      // rows per staged slab
+constexpr int VT_LD = 80;   // LDS row stride for V^T operands: conflict-free
+constexpr int VU_LD = 66;   // LDS row stride for V operands: conflict-free
+
+// st[q] = V[r0 + e / 64][e % 64], e = tid + 256 q  (0 past kend)
+__device__ __forceinline__ void fetch_vslab(const double* __restrict__ Ab, long lda, int mp, int nb, int r0, int kend,
+                                            double (&st)[SL * OB / 256]) {
+#pragma unroll
+  for (int q = 0; q < SL * OB / 256; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int k = r0 + e / OB;
+    st[q] = (k < kend) ? vel(Ab, lda, mp, nb, k, e % OB) : 0.0;
+  }
+}
+template <int LD>
+__device__ __forceinline__ void put_vslab(double* __restrict__ Vs, const double (&st)[SL * OB / 256]) {
+#pragma unroll
+  for (int q = 0; q < SL * OB / 256; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    Vs[(e / OB) * LD + e % OB] = st[q];
+  }
+}
+
 // P[c][i][col] = sum over rows k of chunk c of V[k][i] * Yv[k][col],
 // i < nb, col < ncols; Yv = V for col < s_cols, else Y[k][col].
 // 256 threads; wave w owns output columns [16w, 16w + 16) of the 64-column
 // tile and all four 16-row blocks of i.  MFMA f64 16x16x4 operand layout:
 // A[i][k] in lane (i + 16 k), B[k][col] in lane (col + 16 k); result
-// C[i][col] with i = lane / 16 + 4 v, col = lane % 16.  Rows go in groups
-// of 8 k-steps whose operands are fetched one group ahead.
-constexpr int VG = 8;  // k-steps (of 4 rows) per operand group
-
-__device__ __forceinline__ void vty_fetch(const double* __restrict__ Ab, long lda, int mp, int nb,
-                                          const double* __restrict__ Yc, long ldy, bool colok, bool colv, int col,
-                                          int kend, int k0, int lane, double (&a)[VG][4], double (&b)[VG]) {
-  const int kq = lane >> 4, il = lane & 15;
-#pragma unroll
-  for (int t = 0; t < VG; ++t) {
-    const int k = k0 + 4 * t + kq;
-    const bool kok = k < kend;
-    b[t] = (colok && kok) ? (colv ? vel(Ab, lda, mp, nb, k, col) : Yc[(long)k * ldy]) : 0.0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) a[t][s] = kok ? vel(Ab, lda, mp, nb, k, s * 16 + il) : 0.0;
-  }
-}
-
+// C[i][col] with i = lane / 16 + 4 v, col = lane % 16.
 __global__ __launch_bounds__(256) void k_vty(const double* __restrict__ A, long lda, int j0, int mp, int nb,
                                              const double* __restrict__ Y, long ldy, int yr0, int yc0, int ncols,
                                              int s_cols, int ntiles, double* __restrict__ part) {
+  __shared__ double Vs[2][SL * VT_LD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
   const int col = tile * 64 + w * 16 + (lane & 15);
-  const int kq = lane >> 4;
+  const int kq = lane >> 4, il = lane & 15;
   const int kbeg = chunk * KC, kend = min(mp, kbeg + KC);
+  const int nslab = (kend - kbeg + SL - 1) / SL;
   const double* Ab = A + (long)j0 * lda + j0;
   const double* Yc = Y + (long)yr0 * ldy + yc0 + col;
   const bool colok = col < ncols;
@@ -87,23 +98,36 @@ __global__ __launch_bounds__(256) void k_vty(const double* __restrict__ A, long 
   f64x4 acc[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-  double a[VG][4], b[VG], a2[VG][4], b2[VG];
-  vty_fetch(Ab, lda, mp, nb, Yc, ldy, colok, colv, col, kend, kbeg, lane, a, b);
-  for (int k0 = kbeg; k0 < kend; k0 += 4 * VG) {
-    const bool more = k0 + 4 * VG < kend;
-    if (more) vty_fetch(Ab, lda, mp, nb, Yc, ldy, colok, colv, col, kend, k0 + 4 * VG, lane, a2, b2);
+  double st[SL * OB / 256], b[SL / 4], b2[SL / 4];
+  auto fetch_b = [&](int r0, double (&bb)[SL / 4]) {
 #pragma unroll
-    for (int t = 0; t < VG; ++t)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc[s] = mfma16x16x4(a[t][s], b[t], acc[s]);
-    if (more) {
-#pragma unroll
-      for (int t = 0; t < VG; ++t) {
-        b[t] = b2[t];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) a[t][s] = a2[t][s];
-      }
+    for (int t = 0; t < SL / 4; ++t) {
+      const int k = r0 + 4 * t + kq;
+      bb[t] = (colok && k < kend) ? (colv ? vel(Ab, lda, mp, nb, k, col) : Yc[(long)k * ldy]) : 0.0;
     }
+  };
+  fetch_vslab(Ab, lda, mp, nb, kbeg, kend, st);
+  fetch_b(kbeg, b);
+  put_vslab<VT_LD>(Vs[0], st);
+  __syncthreads();
+  for (int sl = 0; sl < nslab; ++sl) {
+    const int r0 = kbeg + sl * SL;
+    const bool more = sl + 1 < nslab;
+    if (more) {
+      fetch_vslab(Ab, lda, mp, nb, r0 + SL, kend, st);
+      fetch_b(r0 + SL, b2);
+    }
+    const double* V = Vs[sl & 1];
+#pragma unroll
+    for (int t = 0; t < SL / 4; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = mfma16x16x4(V[(4 * t + kq) * VT_LD + 16 * s + il], b[t], acc[s]);
+    if (more) {
+      put_vslab<VT_LD>(Vs[(sl + 1) & 1], st);
+#pragma unroll
+      for (int t = 0; t < SL / 4; ++t) b[t] = b2[t];
+    }
+    __syncthreads();
   }
   if (!colok) return;
 #pragma unroll
@@ -184,40 +208,41 @@ __global__ __launch_bounds__(256) void k_red(const double* __restrict__ part, in
   W[(long)i * ncols + col] = sum;
 }
 
-// Y[k][col] += sum_i V[k][i] W[i][col] for the rows of one chunk and one
-// 64-column tile.  Wave w owns columns [16w, 16w + 16); W's column slice is
-// held as 16 B operands; rows go in blocks of 16 (A = V rows, C = Y rows in
-// the f64 MFMA result layout), the next block's operands fetched ahead.
-__device__ __forceinline__ void upd_fetch(const double* __restrict__ Ab, long lda, int mp, int nb,
-                                          const double* __restrict__ Yc, long ldy, bool colok, int kend, int r0,
-                                          int nk, int lane, double (&a)[OB / 4], double (&c)[4]) {
-  const int kq = lane >> 4;
-  const int ka = r0 + (lane & 15);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int k = r0 + kq + 4 * v;
-    c[v] = (colok && k < kend) ? Yc[(long)k * ldy] : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < OB / 4; ++q) a[q] = (q < nk && ka < kend) ? vel(Ab, lda, mp, nb, ka, 4 * q + kq) : 0.0;
-}
-
-// The workgroup first forms its slice of W' = -op(T) W (64 x 16 per wave,
-// f64 MFMA); result element [16 s + kq + 4 v][col] is exactly the B operand
-// of k-step q = 4 s + v, so no data movement is needed between the two.
+// Y[k][col] += sum_i V[k][i] W'[i][col] for the rows of one chunk and one
+// 64-column tile, W' = -op(T) W.  The workgroup first forms its slice of W'
+// (64 x 16 per wave, f64 MFMA); result element [16 s + kq + 4 v][col] is
+// exactly the B operand of k-step q = 4 s + v, so no data movement is needed
+// between the two.  Wave w owns columns [16w, 16w + 16); rows go in blocks
+// of 16 (A = V rows from the staged slab, C = Y rows in the f64 MFMA result
+// layout, fetched one slab ahead).
 __global__ __launch_bounds__(256) void k_vupd(const double* __restrict__ A, long lda, int j0, int mp, int nb,
                                               const double* __restrict__ T, int trans, const double* __restrict__ W,
                                               long ldw, int wc0, double* __restrict__ Y, long ldy, int yr0, int yc0,
                                               int ncols, int ntiles) {
+  __shared__ double Vs[2][SL * VU_LD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
   const int col = tile * 64 + w * 16 + (lane & 15);
   const int kq = lane >> 4, il = lane & 15;
   const bool colok = col < ncols;
   const int kbeg = chunk * KC, kend = min(mp, kbeg + KC);
+  const int nslab = (kend - kbeg + SL - 1) / SL;
   const double* Ab = A + (long)j0 * lda + j0;
   double* Yc = Y + (long)yr0 * ldy + yc0 + col;
   const int nk = (nb + 3) / 4;
+  double st[SL * OB / 256];
+  fetch_vslab(Ab, lda, mp, nb, kbeg, kend, st);
+  double c[SL / 16][4], c2[SL / 16][4];
+  auto fetch_c = [&](int r0, double (&cc)[SL / 16][4]) {
+#pragma unroll
+    for (int rb = 0; rb < SL / 16; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = r0 + 16 * rb + kq + 4 * v;
+        cc[rb][v] = (colok && k < kend) ? Yc[(long)k * ldy] : 0.0;
+      }
+  };
+  fetch_c(kbeg, c);
   double bw[OB / 4];
   {
     double wb[OB / 4];
@@ -244,26 +269,36 @@ __global__ __launch_bounds__(256) void k_vupd(const double* __restrict__ A, long
 #pragma unroll
       for (int v = 0; v < 4; ++v) bw[4 * s + v] = -acc[s][v];
   }
-  double a[OB / 4], c[4], a2[OB / 4], c2[4];
-  upd_fetch(Ab, lda, mp, nb, Yc, ldy, colok, kend, kbeg, nk, lane, a, c);
-  for (int r0 = kbeg; r0 < kend; r0 += 16) {
-    const bool more = r0 + 16 < kend;
-    if (more) upd_fetch(Ab, lda, mp, nb, Yc, ldy, colok, kend, r0 + 16, nk, lane, a2, c2);
-    f64x4 acc = f64x4{c[0], c[1], c[2], c[3]};
+  put_vslab<VU_LD>(Vs[0], st);
+  __syncthreads();
+  for (int sl = 0; sl < nslab; ++sl) {
+    const int r0 = kbeg + sl * SL;
+    const bool more = sl + 1 < nslab;
+    if (more) {
+      fetch_vslab(Ab, lda, mp, nb, r0 + SL, kend, st);
+      fetch_c(r0 + SL, c2);
+    }
+    const double* V = Vs[sl & 1];
 #pragma unroll
-    for (int q = 0; q < OB / 4; ++q)
-      if (q < nk) acc = mfma16x16x4(a[q], bw[q], acc);
+    for (int rb = 0; rb < SL / 16; ++rb) {
+      f64x4 acc = f64x4{c[rb][0], c[rb][1], c[rb][2], c[rb][3]};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int k = r0 + kq + 4 * v;
-      if (colok && k < kend) Yc[(long)k * ldy] = acc[v];
+      for (int q = 0; q < OB / 4; ++q)
+        if (q < nk) acc = mfma16x16x4(V[(16 * rb + il) * VU_LD + 4 * q + kq], bw[q], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = r0 + 16 * rb + kq + 4 * v;
+        if (colok && k < kend) Yc[(long)k * ldy] = acc[v];
+      }
     }
     if (more) {
+      put_vslab<VU_LD>(Vs[(sl + 1) & 1], st);
 #pragma unroll
-      for (int q = 0; q < OB / 4; ++q) a[q] = a2[q];
+      for (int rb = 0; rb < SL / 16; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) c[v] = c2[v];
+        for (int v = 0; v < 4; ++v) c[rb][v] = c2[rb][v];
     }
+    __syncthreads();
   }
 }
 

@@ -70,8 +70,10 @@ hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, do
 // ---------------------------------------------------------------- SVD
 // One-sided Jacobi on the rows of X (p x L, row-major, ld L): on return the
 // rows are mutually orthogonal (X <- Z^T X, Z orthogonal, not formed).
-// counter: 8 unsigned of device scratch (cleared by the routine).  Sweeps
+// counter: 8 + ceil(p / 8) unsigned of device scratch (cleared by the routine).  Sweeps
 // used go to *sweeps_dev.
+// Algorithmic bytes and FLOP of one Jacobi sweep on p rows of length L.
+void jacobi_sweep_cost(int p, int L, double* bytes, double* flops);
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
                        int* sweeps_dev);
 // dst[j] = src[perm[j]] (row gather).
@@ -114,6 +116,9 @@ enum Class { APPLY_PANEL = 0, JACOBI = 1, QR_PANEL = 2, BLOCK_VTY = 3, BLOCK_UPD
 bool active(int cls);
 void begin(hipStream_t st, int cls, double bytes, double flops);
 void end(hipStream_t st);
+// Adds work to the last launch recorded for class cls (work known only after
+// the launch, e.g. an iteration count read back later).
+void amend(int cls, double bytes, double flops);
 hipError_t start(int cls, int max_launches);
 hipError_t stop(long* launches, double* total_ms, double* bytes, double* flops);
 }  // namespace prof

@@ -347,14 +347,22 @@ hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter
       attr_set = true;
     }
   }
-  if (prof::active(prof::JACOBI)) {
-    // one nominal sweep over all row pairs: 3 dots + one rotation of length L each
-    const double pairs = 0.5 * (double)p * (p - 1);
-    prof::begin(s, prof::JACOBI, 8.0 * 2.0 * p * (double)L, pairs * 12.0 * L);
-  }
+  // Work is recorded per sweep by the caller once the sweep count is known
+  // (jacobi_sweep_cost); the launch itself is only timed here.
+  if (prof::active(prof::JACOBI)) prof::begin(s, prof::JACOBI, 0.0, 0.0);
   e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(JNT), args, shmem, s);
   prof::end(s);
   return e;
+}
+
+void jacobi_sweep_cost(int p, int L, double* bytes, double* flops) {
+  // every round moves both blocks of every pair in and out of the workgroups:
+  // 2 (nb2 - 1) passes over the padded p x L matrix; every row pair costs
+  // three dot products and one rotation of length L
+  const int nblk = (p + JB - 1) / JB;
+  const int nb2 = nblk + (nblk & 1);
+  *bytes = 2.0 * (nb2 - 1) * (double)nb2 * JB * L * 8.0;
+  *flops = 0.5 * (double)p * (p - 1) * 12.0 * L;
 }
 
 hipError_t row_norms_sorted(hipStream_t s, const double* X, int p, int L, double* sig_sorted, int* perm) {
