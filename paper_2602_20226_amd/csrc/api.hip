@@ -96,7 +96,9 @@ struct Plan {
 
 long round_up(long x, long a) { return (x + a - 1) / a * a; }
 
-int make_plan(const Shape& s, long max_rank, Plan& P) {
+// svd = false plans the QR sweep only (orthogonalisation): no SVD-sweep
+// buffers and none of their size limits.
+int make_plan(const Shape& s, long max_rank, Plan& P, bool svd = true) {
   const int n = s.n;
   P.m.assign(n, 0);
   P.rho.assign(n + 1, 1);
@@ -145,7 +147,7 @@ int make_plan(const Shape& s, long max_rank, Plan& P) {
     }
   }
   long maxZ = 1, maxX = 1, maxYn = 1, maxTB = 1, maxP = 1;
-  for (int k = n - 1; k >= 1; --k) {
+  for (int k = n - 1; svd && k >= 1; --k) {
     const long D = s.d[k] * rr[k + 1];
     const long rows = P.rho[k];  // rho_{k-1} in 1-based terms = rows of B
     // Q_k [Y; 0] lives in Z: m_k x r''_{k+1}  (for k = n-1 the centre is used)
@@ -162,7 +164,7 @@ int make_plan(const Shape& s, long max_rank, Plan& P) {
     if (D > 1024) return QTT_ERR_UNSUPPORTED;  // Jacobi keeps 16 row slices of length D per lane group
     maxYn = std::max(maxYn, rows * rr[k]);
   }
-  if (n >= 2) maxZ = std::max(maxZ, P.m[0] * rr[1]);
+  if (svd && n >= 2) maxZ = std::max(maxZ, P.m[0] * rr[1]);
   maxZ = std::max(maxZ, maxQ);
   P.offZ = take(maxZ);
   P.offX = take(maxX);
@@ -179,7 +181,7 @@ int make_plan(const Shape& s, long max_rank, Plan& P) {
   {
     long maxc = 1;
     for (int k = 0; k <= n; ++k) maxc = std::max(maxc, s.rc[k]);
-    for (int k = 0; k < n; ++k) maxc = std::max(maxc, (long)s.d[k] * std::max(rr[k], rr[k + 1]));
+    for (int k = 0; svd && k < n; ++k) maxc = std::max(maxc, (long)s.d[k] * std::max(rr[k], rr[k + 1]));
     P.offScr = take(qr_scratch_doubles(maxc));
   }
   P.total = off;
@@ -819,7 +821,7 @@ int qtt_workspace_size(qtt_handle h, int op, const char* spec, const qtt_tt* a, 
       Shape s;
       shape_from_tt(a, s);
       Plan P;
-      if ((st = make_plan(s, op == QTT_OP_ROUND ? max_rank : 0, P))) return st;
+      if ((st = make_plan(s, op == QTT_OP_ROUND ? max_rank : 0, P, op == QTT_OP_ROUND))) return st;
       *bytes = ws_bytes_of(P);
       return QTT_OK;
     }
@@ -894,7 +896,7 @@ int qtt_orthogonalize(qtt_handle h, qtt_tt* t, double* norm_host, void* ws, size
   Shape s;
   shape_from_tt(t, s);
   Plan P;
-  if ((st = make_plan(s, 0, P))) return st;
+  if ((st = make_plan(s, 0, P, false))) return st;
   if (!ws || ws_bytes < ws_bytes_of(P)) return QTT_ERR_WORKSPACE;
   Scoped sc(h->device);
   Sweep w{h, (hipStream_t)stream, align_ws(ws), &s, &P, QTT_GEMM_FP64};

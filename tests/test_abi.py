@@ -120,3 +120,17 @@ def test_rank_bounds_match_profile():
     assert b == [1, 2, 4, 8, 4, 2, 1]
     b = rank_bounds([1, 4, 16, 64, 16, 4, 1], [2] * 6, 3)
     assert b == [1, 2, 3, 3, 3, 2, 1]
+
+
+def test_orthogonalisation_plans_the_largest_unfolding():
+    """Ranks 2048 make 4096 x 2048 unfoldings: the QR supports them, the Jacobi
+    of the rounding sweep (rows of length <= 1024) does not."""
+    n = 24
+    ranks = [min(2 ** k, 2048, 2 ** (n - k)) for k in range(n + 1)]
+    a = _fake_tt(ranks, [2] * n)
+    st, nb = ws(Q.OP_ORTHOGONALIZE, a)
+    assert st == 0 and nb > 0
+    assert ws(Q.OP_ROUND, a)[0] == -10  # QTT_ERR_UNSUPPORTED
+    n2 = 26
+    too_tall = _fake_tt([min(2 ** k, 4096, 2 ** (n2 - k)) for k in range(n2 + 1)], [2] * n2)  # 8192-row unfolding
+    assert ws(Q.OP_ORTHOGONALIZE, too_tall)[0] == -10

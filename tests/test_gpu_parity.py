@@ -127,6 +127,38 @@ def test_orthogonalize(ranks):
     assert O.ranks_of(Yh) == expect
 
 
+def _rank1_probe(cores, z):
+    """<T, Z> for a rank-1 TT Z given by its vectors z[k] (length d_k)."""
+    v = np.ones(1)
+    for c, zk in zip(cores, z):
+        v = np.einsum("a,aib,i->b", v, c, zk)
+    return float(v[0])
+
+
+@pytest.mark.timeout(600)
+def test_orthogonalize_largest_unfolding():
+    """Ranks up to 2048, so the middle unfolding is 4096 x 2048: the tallest
+    panel shape the QR supports.  Checks orthogonality of every core, the
+    norm against the oracle, and the tensor through random rank-1 probes."""
+    n = 24
+    ranks = [min(2 ** k, 2048, 2 ** (n - k)) for k in range(n + 1)]
+    log(f"orthogonalize largest unfolding, max rank {max(ranks)}")
+    rng = np.random.default_rng(107)
+    X = [rng.standard_normal((ranks[k], 2, ranks[k + 1])) / np.sqrt(2 * ranks[k + 1]) for k in range(n)]
+    Y, nrm = Q.orthogonalize(dev(X))
+    Yh = host(Y)
+    assert max(c.shape[0] * c.shape[1] for c in Yh) == 4096
+    for c in Yh[:-1]:
+        M = c.reshape(-1, c.shape[-1])
+        assert np.abs(M.T @ M - np.eye(M.shape[1])).max() <= 1e-13
+    _, ref_norm = O.orthogonalize(X)
+    assert abs(nrm - ref_norm) <= 1e-13 * ref_norm
+    for _ in range(4):
+        z = [rng.standard_normal(2) for _ in range(n)]
+        zn = np.prod([np.linalg.norm(v) for v in z])
+        assert abs(_rank1_probe(Yh, z) - _rank1_probe(X, z)) <= 1e-12 * ref_norm * zn
+
+
 # ------------------------------------------------------------------ rounding (a3 + a4)
 def check_round(got, ref_cores, ref_info, tol=1e-12, sig_tol=1e-12, ranks_exact=True):
     gh = host(got.cores)
