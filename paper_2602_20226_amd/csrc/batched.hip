@@ -146,12 +146,41 @@ __device__ __forceinline__ int rr_item(int pos, int round, int n) {
 }
 
 // One-sided Jacobi on the rows of X (p x L) by this workgroup; blocks of JB
-// rows, block pairs visited sequentially, each pair staged in LDS.  Returns
-// the sweep count (max_sweeps when not converged).
+// rows, block pairs visited sequentially in the round-robin order, each pair
+// staged in LDS.  A visit rotates the JB x JB cross pairs (JB steps of JB
+// disjoint pairs, waves taking pairs in turn); the pairs inside each block
+// are rotated once per sweep, in the first round.  Returns the sweep count
+// (max_sweeps when not converged).
+__device__ __forceinline__ int wg_rotate(double* __restrict__ xa, double* __restrict__ xc, int L, double tol) {
+  const int lane = threadIdx.x & 63;
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int c = lane; c < L; c += 64) {
+    const double u = xa[c], w = xc[c];
+    al += u * u;
+    be += w * w;
+    ga += u * w;
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  if (!(ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be))) return 0;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (fabs(zeta) > 1e150) ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / sqrt(1.0 + t * t);
+  const double sn = cs * t;
+  for (int c = lane; c < L; c += 64) {
+    const double u = xa[c], w = xc[c];
+    xa[c] = cs * u - sn * w;
+    xc[c] = sn * u + cs * w;
+  }
+  return 1;
+}
+
 template <int JB>
 __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restrict__ sh, int max_sweeps, double tol,
                          Smem& sm) {
   constexpr int JR = 2 * JB;
+  constexpr int NW = BNT / 64;
   const int nblk = (p + JB - 1) / JB;
   const int nb2 = nblk + (nblk & 1);
   const int npairs = nb2 / 2;
@@ -171,36 +200,20 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
         }
         wg_sync();
         int rot = 0;
-        for (int ir = 0; ir < JR - 1; ++ir) {
-          for (int q = wave; q < JB; q += BNT / 64) {
-            const int ra = rr_item(q, ir, JR);
-            const int rc = rr_item(JR - 1 - q, ir, JR);
-            double* xa = sh + ra * L;
-            double* xc = sh + rc * L;
-            double al = 0.0, be = 0.0, ga = 0.0;
-            for (int c = lane; c < L; c += 64) {
-              const double u = xa[c], w = xc[c];
-              al += u * u;
-              be += w * w;
-              ga += u * w;
+        if (round == 0) {
+          // pairs inside each block: JB - 1 steps of JB / 2 disjoint pairs per block
+          for (int st = 0; st < JB - 1; ++st) {
+            for (int q = wave; q < JB; q += NW) {
+              const int blk = q / (JB / 2), i = q % (JB / 2);
+              rot += wg_rotate(sh + (blk * JB + rr_item(i, st, JB)) * L,
+                               sh + (blk * JB + rr_item(JB - 1 - i, st, JB)) * L, L, tol);
             }
-            al = wave_sum(al);
-            be = wave_sum(be);
-            ga = wave_sum(ga);
-            if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-              const double zeta = (be - al) / (2.0 * ga);
-              const double t = (fabs(zeta) > 1e150) ? 0.5 / zeta
-                                                    : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-              const double cs = 1.0 / sqrt(1.0 + t * t);
-              const double sn = cs * t;
-              for (int c = lane; c < L; c += 64) {
-                const double u = xa[c], w = xc[c];
-                xa[c] = cs * u - sn * w;
-                xc[c] = sn * u + cs * w;
-              }
-              ++rot;
-            }
+            wg_sync();
           }
+        }
+        // cross pairs: at step s top row q meets bottom row (q + s) % JB
+        for (int s = 0; s < JB; ++s) {
+          for (int q = wave; q < JB; q += NW) rot += wg_rotate(sh + q * L, sh + (JB + (q + s) % JB) * L, L, tol);
           wg_sync();
         }
         if (lane == 0 && rot) atomicAdd(&sm.iscal[0], rot);
