@@ -160,14 +160,11 @@ __device__ __forceinline__ int wg_rotate(double* __restrict__ xa, double* __rest
     be += w * w;
     ga += u * w;
   }
-  al = wave_sum(al);
-  be = wave_sum(be);
-  ga = wave_sum(ga);
-  if (!(ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be))) return 0;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (fabs(zeta) > 1e150) ? 0.5 / zeta : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cs = 1.0 / sqrt(1.0 + t * t);
-  const double sn = cs * t;
+  al = wave_sum_bc(al);
+  be = wave_sum_bc(be);
+  ga = wave_sum_bc(ga);
+  double cs, sn;
+  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return 0;
   for (int c = lane; c < L; c += 64) {
     const double u = xa[c], w = xc[c];
     xa[c] = cs * u - sn * w;

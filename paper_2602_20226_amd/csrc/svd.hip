@@ -35,16 +35,6 @@ __device__ __forceinline__ int rr_item(int pos, int round, int n) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (n - 1));
 }
 
-// Sum over the 64 lanes with the row broadcasts of DPP: after the row sums,
-// row 3 accumulates rows 0-2 (row_bcast:15 into rows 1 and 3, row_bcast:31
-// into rows 2 and 3); lane 63 holds the total, read back for every lane.
-__device__ __forceinline__ double wave_sum_bc(double v) {
-  v = row_sum(v);
-  v += __builtin_amdgcn_update_dpp(0.0, v, 0x142, 0xA, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0.0, v, 0x143, 0xC, 0xF, false);
-  return readlane_f64(v, 63);
-}
-
 // Rotate the pair (u, v) of rows (E elements per lane, zero past the row end)
 // so that they become orthogonal; returns true when a rotation was applied.
 template <int E>
@@ -59,36 +49,8 @@ __device__ __forceinline__ bool rotate_pair(double (&u)[E], double (&v)[E], doub
   al = wave_sum_bc(al);
   be = wave_sum_bc(be);
   ga = wave_sum_bc(ga);
-  if (ga == 0.0) return false;
-  // skip when |a.c| <= tol ||a|| ||c|| (squared form inside the safe range)
-  const bool safe = fmin(al, be) > 1e-140 && fmax(al, be) < 1e140;
-  if (safe ? !(ga * ga > (tol * tol) * (al * be)) : !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
-  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 ga),
-  // i.e. t = sign(d g) |g| / (|d| + sqrt(d^2 + g^2)) with d = be - al,
-  // g = 2 ga, evaluated on d, g scaled by a power of two so that the larger
-  // magnitude lies in [0.5, 1) (the ratio does not change); c = (1 + t^2)^(-1/2), s = c t.  Square roots and
-  // reciprocals start from the single-precision hardware estimates and take
-  // two Newton steps each (relative error ~2^-23 -> ~2^-92, i.e. rounding).
-  double d = be - al, g = 2.0 * ga;
-  const int ke = __builtin_amdgcn_frexp_exp(fmax(fabs(d), fabs(g)));
-  d = __builtin_amdgcn_ldexp(d, -ke);
-  g = __builtin_amdgcn_ldexp(g, -ke);
-  const double x = d * d + g * g;  // in [0.25, 2)
-  double r = (double)__builtin_amdgcn_rsqf((float)x);
-  const double hx = 0.5 * x;
-  r = r * fma(-hx, r * r, 1.5);
-  r = r * fma(-hx, r * r, 1.5);
-  const double den = fabs(d) + x * r;  // |d| + sqrt(d^2 + g^2), in [0.5, 3)
-  double rq = (double)__builtin_amdgcn_rcpf((float)den);
-  rq = fma(rq, fma(-den, rq, 1.0), rq);
-  rq = fma(rq, fma(-den, rq, 1.0), rq);
-  const double t = copysign(fabs(g) * rq, d * g);  // |t| <= 1
-  const double y = fma(t, t, 1.0);                // in [1, 2]
-  double cs = (double)__builtin_amdgcn_rsqf((float)y);
-  const double hy = 0.5 * y;
-  cs = cs * fma(-hy, cs * cs, 1.5);
-  cs = cs * fma(-hy, cs * cs, 1.5);
-  const double sn = cs * t;
+  double cs, sn;
+  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const double a = u[q], c = v[q];
