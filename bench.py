@@ -212,7 +212,7 @@ def add_roofline(out, kernels, sec):
     out["roofline"] = {
         "bound": k["bound"], "achieved": k["achieved"] * scale, "peak": k["peak"] * scale,
         "unit": "TFLOP/s" if k["unit"] == "GFLOP/s" else "GB/s", "frac": k["frac"],
-        "traffic": measured_traffic(k["kernel"], k["source"]),
+        "traffic": measured_traffic(k["kernel"], k["alg_bytes_per_launch"]),
         "kernel": k["kernel"], "launches": k["launches"], "avg_us": k["avg_us"],
         "share_of_step": k["ms_per_step"] / (sec * 1e3),
         "alg_bytes_per_launch": k["alg_bytes_per_launch"], "alg_flop_per_launch": k["alg_flop_per_launch"],
@@ -221,22 +221,27 @@ def add_roofline(out, kernels, sec):
                                                    "unit", "frac")} for c, v in kernels.items()}
 
 
-def measured_traffic(kernel, source):
+def measured_traffic(kernel, alg_bytes_per_launch):
     """HBM bytes per launch from the committed hardware-counter summary of this
-    kernel, if it was taken on the current source of the kernel; else None."""
+    kernel (FETCH_SIZE + WRITE_SIZE of one launch, each scaled by the counter's
+    reading for a plain copy of known size), applied as the measured/algorithmic
+    ratio to this run's algorithmic bytes per launch; None unless the summary was
+    taken on the current source of the kernel."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel.split('+')[0]}.json")
-    src = os.path.join(ROOT, "paper_2602_20226_amd", "csrc", source)
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-    except OSError:
+        h = hashlib.sha256()
+        for name in rec.get("sources", []):
+            with open(os.path.join(ROOT, name), "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
+    except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != sha:
+    if rec.get("source_sha256") != sha or not rec.get("ratio"):
         return None
-    return rec.get("bytes_per_launch")
+    return rec["ratio"] * alg_bytes_per_launch
 
 
 def cpu_baseline(w, ra, rb, d, dj):
