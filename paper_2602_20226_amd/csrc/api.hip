@@ -118,7 +118,7 @@ int make_plan(const Shape& s, long max_rank, Plan& P, bool svd = true) {
     P.m[k] = m;
     P.rho[k + 1] = std::min(m, cols);
     P.offM[k] = take(m * cols);
-    P.offT[k] = take((long)qr_num_panels((int)m, (int)cols) * 256);
+    P.offT[k] = take(qr_t_doubles((int)m, (int)cols));
     maxR = std::max(maxR, P.rho[k + 1] * cols);
     maxQ = std::max(maxQ, m * P.rho[k + 1]);  // explicit Q_k for qtt_orthogonalize
     if (s.kind != K_TT) {
@@ -155,7 +155,7 @@ int make_plan(const Shape& s, long max_rank, Plan& P, bool svd = true) {
     maxZ = std::max(maxZ, rows * D);
     if (rows >= D) {
       maxX = std::max(maxX, D * D);
-      maxTB = std::max(maxTB, (long)qr_num_panels((int)rows, (int)D) * 256);
+      maxTB = std::max(maxTB, qr_t_doubles((int)rows, (int)D));
       maxP = std::max(maxP, D);
     } else {
       maxX = std::max(maxX, rows * D);

@@ -579,7 +579,7 @@ inline hipError_t for_each_outer(int kmax, F f) {
 
 }  // namespace
 
-int qr_num_panels(int m, int n) { return ceil_div(std::min(m, n), OB) * (OB * OB / 256); }
+long qr_t_doubles(int m, int n) { return (long)ceil_div(std::min(m, n), OB) * OB * OB; }
 
 hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf, double* scratch) {
   if (m <= 0 || n <= 0) return hipSuccess;

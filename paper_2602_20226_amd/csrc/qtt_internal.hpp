@@ -48,11 +48,11 @@ hipError_t contract_backward_w(hipStream_t s, bool mpo, const T* X, int rx0, int
                                const T* dC, int rw0, int di, int rw1, T* dW);
 
 // ---------------------------------------------------------------- QR
-constexpr int QR_PB = 16;  // inner panel width of the batched workgroup QR
 // Blocked Householder QR of the m x n row-major matrix A (in place).  Reflector
 // vectors below the diagonal, R on and above; one 64 x 64 compact-WY factor
-// T per 64-column block of reflectors in Tbuf (qr_num_panels(m, n) * 256
-// doubles).  Supports m <= 4096.  scratch: qr_scratch_doubles(n).
+// T per 64-column block of reflectors in Tbuf (qr_t_doubles(m, n) doubles;
+// also enough for the 16 x 16 blocks of the batched workgroup QR).
+// Supports m <= 4096.  scratch: qr_scratch_doubles(n).
 hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf, double* scratch);
 // Y <- Q Y (trans=false, blocks in reverse order) or Q^T Y (trans=true,
 // forward order); Y has m rows.  scratch: qr_scratch_doubles(ncols).
@@ -108,7 +108,7 @@ hipError_t truncate_decide(hipStream_t s, const double* sig, int cnt, const doub
 // rmax_host bounds the launch.
 hipError_t gather_rows_normalized(hipStream_t s, const double* X, int L, const int* perm, const double* sig,
                                   const TruncOut* t, double* out, long ldo, int rmax_host);
-int qr_num_panels(int m, int n);
+long qr_t_doubles(int m, int n);
 
 // ---------------------------------------------------------------- launch profiling
 namespace prof {
