@@ -149,7 +149,7 @@ __device__ __forceinline__ double wave_sum_bc(double v) {
 // orthogonal to the tolerance (|a.c| <= tol ||a|| ||c||), else (cs, sn) with
 // [a; c] <- [cs a - sn c; sn a + cs c] making the pair orthogonal.
 __device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double tol, double& cs_out,
-                                                double& sn_out) {
+                                                double& sn_out, double& t_out) {
   if (ga == 0.0) return false;
   // squared form of the test inside the safe range
   const bool safe = fmin(al, be) > 1e-140 && fmax(al, be) < 1e140;
@@ -183,7 +183,14 @@ __device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga,
   const double sn = cs * t;
   cs_out = cs;
   sn_out = sn;
+  t_out = t;  // the new squared norms are al - t ga and be + t ga
   return true;
+}
+
+__device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double tol, double& cs_out,
+                                                double& sn_out) {
+  double t;
+  return jacobi_rotation(al, be, ga, tol, cs_out, sn_out, t);
 }
 
 // Grid-wide barrier for co-resident persistent workgroups (cooperative launch).

@@ -106,6 +106,7 @@ template <int E>
 __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, int L, unsigned* __restrict__ ctr,
                                                 int max_sweeps, int* sweeps_out, double tol) {
   extern __shared__ double sh[];  // 16 row slots of 64 E doubles
+  __shared__ double bes[2][JB];   // squared norms travelling with the bottom rows
   __shared__ unsigned s_tot;
   constexpr int RS = 64 * E;
   const int nblk = (p + JB - 1) / JB;
@@ -156,14 +157,43 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
         lds_get<E>(sh + (JB + w) * RS, bot);
         __syncthreads();
       }
-      // cross pairs: at step s wave w rotates top row w with bottom row (w + s) % 8
+      // cross pairs: at step s wave w rotates top row w with bottom row (w + s) % 8.
+      // The squared row norms are formed once per round and then carried
+      // through the rotations (||a'||^2 = ||a||^2 - t a.c, ||c'||^2 =
+      // ||c||^2 + t a.c) and with the bottom rows through LDS, so a step
+      // needs one dot product and one reduction.
+      double al = 0.0, be = 0.0;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        al += top[q] * top[q];
+        be += bot[q] * bot[q];
+      }
+      al = wave_sum_bc(al);
+      be = wave_sum_bc(be);
       for (int s = 0; s < JB; ++s) {
-        if (rotate_pair<E>(top, bot, tol) && lane == 0) ++local_rot;
+        double ga = 0.0;
+#pragma unroll
+        for (int q = 0; q < E; ++q) ga += top[q] * bot[q];
+        ga = wave_sum_bc(ga);
+        double cs, sn, t;
+        if (jacobi_rotation(al, be, ga, tol, cs, sn, t)) {
+#pragma unroll
+          for (int q = 0; q < E; ++q) {
+            const double a = top[q], c = bot[q];
+            top[q] = cs * a - sn * c;
+            bot[q] = sn * a + cs * c;
+          }
+          al -= t * ga;
+          be += t * ga;
+          if (lane == 0) ++local_rot;
+        }
         if (s + 1 < JB) {
           double* buf = sh + (s & 1) * JB * RS;
           lds_put<E>(buf + ((w + s) % JB) * RS, bot);
+          if (lane == 0) bes[s & 1][(w + s) % JB] = be;
           __syncthreads();
           lds_get<E>(buf + ((w + s + 1) % JB) * RS, bot);
+          be = bes[s & 1][(w + s + 1) % JB];
         }
       }
       store_row<E>(X + (long)rt * L, L, okt, top);
