@@ -172,7 +172,7 @@ def main():
         # class: (bound, peak, unit, kernels, source file of the kernel)
         "jacobi": ("alu", 78600.0, "GFLOP/s", "k_jacobi", "svd.hip"),
         "qr_panel": ("alu", 78600.0, "GFLOP/s", "k_qr_panel", "qr.hip"),
-        "apply_panel": ("hbm", 8000.0, "GB/s", "k_apply_w+k_apply_upd", "qr.hip"),
+        "apply_panel": ("hbm", 8000.0, "GB/s", "k_apply1", "qr.hip"),
         "block_vty": ("mfma", 78600.0, "GFLOP/s", "k_vty", "qr.hip"),
         "block_upd": ("mfma", 78600.0, "GFLOP/s", "k_vupd", "qr.hip"),
     }

@@ -2,8 +2,7 @@
 //
 // Two levels.  Inner panels of up to 16 columns are factored by one
 // workgroup each (qr_panel_dev in qr_device.hpp) and applied to the rest of
-// their 64-column outer block by apply_block (a pair of kernels split over
-// 16-column tiles and 256-row chunks).  The reflectors of an outer block are
+// their 64-column outer block by apply_block (one workgroup per column).  The reflectors of an outer block are
 // then aggregated into one compact-WY pair (V, T) with T of order <= 64,
 // built from S = V^T V and the reflector coefficients, and the trailing
 // matrix -- and every later application of Q or Q^T -- is updated once per
@@ -304,153 +303,127 @@ __global__ __launch_bounds__(256) void k_vupd(const double* __restrict__ A, long
 
 inline void apply_cost(int mp, int pw, int ncols, double& bytes, double& flops);
 
-// Block-reflector application inside an outer block, split over
-// (16-column tile) x (256-row chunk) workgroups:
-//   k_apply_w:   W_chunk = V_chunk^T Y_chunk  (16 x 16 per workgroup, stored
-//                per chunk in scratch[chunk][16][ncols]);
-//   k_apply_upd: W = sum_chunk W_chunk, W <- op(T) W, Y_chunk -= V_chunk W.
-// V: rows [r0, r0+mp) of A, columns [vc0, vc0+pw), unit lower trapezoidal.
-// Y rows [yr0, yr0+mp), columns [c0, c0+ncols).
+// Block-reflector application inside an outer block, one launch:
+// workgroup t owns column c0 + t of Y over all mp rows, so no workgroup
+// reads what another one writes:
+//     w = V^T y  (one workgroup sum of PWV values),  w <- op(T) w,
+//     y <- y - V w.
+// V: rows [r0, r0+mp) of A, columns [vc0, vc0+pw) (pw <= PWV), unit lower
+// trapezoidal; y: rows [yr0, yr0+mp) of column c0 + t of Y.
 // trans: Y <- (I - V T^T V^T) Y, else Y <- (I - V T V^T) Y.
-// 256 threads: the chunk of V is staged in LDS with coalesced loads; thread
-// (g, c) owns column c of the tile and rows g + 16 u (u < 16) of the chunk,
-// whose Y values it fetches all at once.
-constexpr int AP_NT = 256, AP_G = AP_NT / 16, AP_CHUNK = 256, AP_U = AP_CHUNK / AP_G;
-
-// Vs[lr][i] = V[rbeg + lr][i] for lr < AP_CHUNK (0 past the block).
-__device__ __forceinline__ void stage_v16(const double* __restrict__ Ab, long lda, int mp, int pw, int rbeg,
-                                          double (*Vs)[17]) {
-  const int tid = threadIdx.x;
+// The NT lanes form quads; the quad (tid >> 2) holds rows NT/4 k + (tid >> 2),
+// lane q of it V columns [q VPQ, (q+1) VPQ) of those rows, and all four
+// lanes the y values.  V and y stay in registers between the two passes
+// (KMAX = ceil(4 mp / NT) chunks); a quad's partial products are summed by
+// two DPP exchanges, which leave the same bits in its four lanes.
+// PAIRS: pw == PWV and lda even -- V is read 16 bytes at a time.
+template <int NT, int PWV, int KMAX, bool PAIRS>
+__global__ __launch_bounds__(NT) void k_apply1(const double* __restrict__ A, long lda, int r0, int mp, int vc0, int pw,
+                                               const double* __restrict__ T, double* __restrict__ Y, long ldy,
+                                               int yr0, int c0, int trans) {
+  constexpr int VPQ = PWV / 4, RS = NT / 4;
+  __shared__ double slots[2 * (NT / 64) * PWV];
+  __shared__ double Ts[16 * 16];
+  const int tid = threadIdx.x, q = tid & 3, sr = tid >> 2;
+  for (int t = tid; t < 256; t += NT) Ts[t] = T[t];  // visible after the barrier of the sum below
+  const double* __restrict__ Ab = A + (long)(r0 + sr) * lda + vc0 + q * VPQ;
+  double* __restrict__ yb = Y + (long)(yr0 + sr) * ldy + c0 + blockIdx.x;
+  const long astep = (long)RS * lda, ystep = (long)RS * ldy;
+  double v[KMAX][VPQ], y[KMAX];
 #pragma unroll
-  for (int q = 0; q < AP_CHUNK * 16 / AP_NT; ++q) {
-    const int e = tid + AP_NT * q;
-    const int lr = e >> 4, i = e & 15;
-    const int gr = rbeg + lr;
-    double v = 0.0;
-    if (gr < mp && i < pw) v = gr > i ? Ab[(long)gr * lda + i] : (gr == i ? 1.0 : 0.0);
-    Vs[lr][i] = v;
+  for (int k = 0; k < KMAX; ++k) {
+    const int lr = RS * k + sr;
+    const bool in = lr < mp;
+    y[k] = in ? yb[k * ystep] : 0.0;
+    if (PAIRS) {
+#pragma unroll
+      for (int e = 0; e < VPQ; e += 2) {
+        double2 t2 = make_double2(0.0, 0.0);
+        if (in) t2 = *reinterpret_cast<const double2*>(Ab + k * astep + e);
+        v[k][e] = t2.x;
+        v[k][e + 1] = t2.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < VPQ; ++e) v[k][e] = (in && q * VPQ + e < pw) ? Ab[k * astep + e] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < VPQ; ++e) {  // unit diagonal, zeros above it
+      const int i = q * VPQ + e;
+      if (lr <= i) v[k][e] = (lr == i && in && i < pw) ? 1.0 : 0.0;
+    }
+  }
+  double acc[VPQ];
+#pragma unroll
+  for (int e = 0; e < VPQ; ++e) acc[e] = 0.0;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+    for (int e = 0; e < VPQ; ++e) acc[e] += v[k][e] * y[k];
+  double x[PWV], w[PWV];
+#pragma unroll
+  for (int i = 0; i < PWV; ++i) x[i] = (i / VPQ == q) ? acc[i % VPQ] : 0.0;
+  wg_sum_vals<NT, PWV>(x, slots, 0, w);
+  double w2[VPQ];
+#pragma unroll
+  for (int e = 0; e < VPQ; ++e) {
+    const int i = q * VPQ + e;
+    double t = 0.0;
+#pragma unroll
+    for (int l = 0; l < PWV; ++l) t += (trans ? Ts[l * 16 + i] : Ts[i * 16 + l]) * w[l];
+    w2[e] = t;
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    double pk = 0.0;
+#pragma unroll
+    for (int e = 0; e < VPQ; ++e) pk += v[k][e] * w2[e];
+    pk += dpp<DPP_XOR1>(pk);
+    pk += dpp<DPP_XOR2>(pk);
+    if (q == 0 && RS * k + sr < mp) yb[k * ystep] = y[k] - pk;
   }
 }
 
-__global__ __launch_bounds__(AP_NT) void k_apply_w(const double* __restrict__ A, long lda, int r0, int mp, int vc0,
-                                                   int pw, const double* __restrict__ Y, long ldy, int yr0, int c0,
-                                                   int ncols, int ntiles, double* __restrict__ part) {
-  __shared__ double Vs[AP_CHUNK][17];
-  __shared__ double red[AP_G][16][17];
-  const int tid = threadIdx.x;
-  const int c = tid & 15, g = tid >> 4;
-  const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
-  const int col = tile * 16 + c;
-  const bool valid = col < ncols;
-  const int rbeg = chunk * AP_CHUNK;
-  const double* Ab = A + (long)r0 * lda + vc0;
-  const double* Yb = Y + (long)yr0 * ldy + c0 + col;
-  double y[AP_U];
-#pragma unroll
-  for (int u = 0; u < AP_U; ++u) {
-    const int gr = rbeg + g + AP_G * u;
-    y[u] = (valid && gr < mp) ? Yb[(long)gr * ldy] : 0.0;
-  }
-  stage_v16(Ab, lda, mp, pw, rbeg, Vs);
-  __syncthreads();
-  double w[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) w[i] = 0.0;
-#pragma unroll
-  for (int u = 0; u < AP_U; ++u) {
-    const int lr = g + AP_G * u;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) w[i] += Vs[lr][i] * y[u];
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) red[g][i][c] = w[i];
-  __syncthreads();
-  {
-    const int i = tid >> 4, cc = tid & 15;
-    double sum = 0.0;
-#pragma unroll
-    for (int q = 0; q < AP_G; ++q) sum += red[q][i][cc];
-    if (tile * 16 + cc < ncols) part[((long)chunk * 16 + i) * ncols + tile * 16 + cc] = sum;
-  }
+template <int NT, int PWV, int KMAX>
+inline void launch_apply1(hipStream_t s, bool pairs, const double* A, long lda, int r0, int mp, int vc0, int pw,
+                          const double* T, double* Y, long ldy, int yr0, int c0, int ncols, int trans) {
+  static_assert(KMAX * NT / 4 >= 64, "");
+  if (pairs)
+    hipLaunchKernelGGL((k_apply1<NT, PWV, KMAX, true>), dim3(ncols), dim3(NT), 0, s, A, lda, r0, mp, vc0, pw, T, Y,
+                       ldy, yr0, c0, trans);
+  else
+    hipLaunchKernelGGL((k_apply1<NT, PWV, KMAX, false>), dim3(ncols), dim3(NT), 0, s, A, lda, r0, mp, vc0, pw, T, Y,
+                       ldy, yr0, c0, trans);
 }
 
-__global__ __launch_bounds__(AP_NT) void k_apply_upd(const double* __restrict__ A, long lda, int r0, int mp, int vc0,
-                                                     int pw, const double* __restrict__ T, double* __restrict__ Y,
-                                                     long ldy, int yr0, int c0, int ncols, int ntiles, int nchunks,
-                                                     const double* __restrict__ part, int trans) {
-  __shared__ double Vs[AP_CHUNK][17];
-  __shared__ double Ws[16][17];
-  __shared__ double W2[16][17];
-  __shared__ double Tsh[16][17];
-  const int tid = threadIdx.x;
-  const int c = tid & 15, g = tid >> 4;
-  const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
-  const int col = tile * 16 + c;
-  const bool valid = col < ncols;
-  const int rbeg = chunk * AP_CHUNK;
-  const double* Ab = A + (long)r0 * lda + vc0;
-  double* Yb = Y + (long)yr0 * ldy + c0 + col;
-  double y[AP_U];
-#pragma unroll
-  for (int u = 0; u < AP_U; ++u) {
-    const int gr = rbeg + g + AP_G * u;
-    y[u] = (valid && gr < mp) ? Yb[(long)gr * ldy] : 0.0;
-  }
-  Tsh[tid >> 4][tid & 15] = T[tid];
-  {
-    const int i = tid >> 4, cc = tid & 15;
-    const bool ok = tile * 16 + cc < ncols;
-    double v[MAX_CHUNKS];
-#pragma unroll
-    for (int q = 0; q < MAX_CHUNKS; ++q)
-      v[q] = (ok && q < nchunks) ? part[((long)q * 16 + i) * ncols + tile * 16 + cc] : 0.0;
-    double sum = 0.0;
-#pragma unroll
-    for (int q = 0; q < MAX_CHUNKS; ++q) sum += v[q];
-    Ws[i][cc] = sum;
-  }
-  stage_v16(Ab, lda, mp, pw, rbeg, Vs);
-  __syncthreads();
-  {
-    const int i = tid >> 4, cc = tid & 15;
-    double sum = 0.0;
-#pragma unroll
-    for (int l = 0; l < 16; ++l) sum += (trans ? Tsh[l][i] : Tsh[i][l]) * Ws[l][cc];
-    W2[i][cc] = sum;
-  }
-  __syncthreads();
-  if (!valid) return;
-  double w[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) w[i] = W2[i][c];
-#pragma unroll
-  for (int u = 0; u < AP_U; ++u) {
-    const int lr = g + AP_G * u;
-    double sum = 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) sum += Vs[lr][i] * w[i];
-    if (rbeg + lr < mp) Yb[(long)(rbeg + lr) * ldy] = y[u] - sum;
-  }
-}
-
-// One block-reflector application (two launches).
+// One block-reflector application inside an outer block (mp <= 4096 rows,
+// pw <= 16; pw <= 8 when mp > 2048).
 hipError_t apply_block(hipStream_t s, const double* A, long lda, int r0, int mp, int vc0, int pw, const double* T,
-                       double* Y, long ldy, int yr0, int c0, int ncols, int trans, double* scratch) {
-  const int ntiles = (ncols + 15) / 16;
-  const int nchunks = (mp + AP_CHUNK - 1) / AP_CHUNK;
+                       double* Y, long ldy, int yr0, int c0, int ncols, int trans) {
+  if (mp <= 0 || ncols <= 0) return hipSuccess;
+  if (mp > 4096 || pw > 16 || (mp > 2048 && pw > 8)) return hipErrorInvalidValue;
   if (prof::active(prof::APPLY_PANEL)) {
     double b, f;
     apply_cost(mp, pw, ncols, b, f);
     prof::begin(s, prof::APPLY_PANEL, b, f);
   }
-  hipLaunchKernelGGL(k_apply_w, dim3(ntiles * nchunks), dim3(AP_NT), 0, s, A, lda, r0, mp, vc0, pw, (const double*)Y,
-                     ldy, yr0, c0, ncols, ntiles, scratch);
+  const int pwv = mp > 2048 ? 8 : 16;
+  const bool pairs = pw == pwv && (lda & 1) == 0 && (vc0 & 1) == 0 && ((uintptr_t)A & 15) == 0;
+  if (mp <= 256)
+    launch_apply1<256, 16, 4>(s, pairs, A, lda, r0, mp, vc0, pw, T, Y, ldy, yr0, c0, ncols, trans);
+  else if (mp <= 512)
+    launch_apply1<256, 16, 8>(s, pairs, A, lda, r0, mp, vc0, pw, T, Y, ldy, yr0, c0, ncols, trans);
+  else if (mp <= 1024)
+    launch_apply1<512, 16, 8>(s, pairs, A, lda, r0, mp, vc0, pw, T, Y, ldy, yr0, c0, ncols, trans);
+  else if (mp <= 2048)
+    launch_apply1<512, 16, 16>(s, pairs, A, lda, r0, mp, vc0, pw, T, Y, ldy, yr0, c0, ncols, trans);
+  else if (mp <= 3072)
+    launch_apply1<512, 8, 24>(s, pairs, A, lda, r0, mp, vc0, pw, T, Y, ldy, yr0, c0, ncols, trans);
+  else if (mp <= 3584)
+    launch_apply1<512, 8, 28>(s, pairs, A, lda, r0, mp, vc0, pw, T, Y, ldy, yr0, c0, ncols, trans);
+  else
+    launch_apply1<512, 8, 32>(s, pairs, A, lda, r0, mp, vc0, pw, T, Y, ldy, yr0, c0, ncols, trans);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_apply_upd, dim3(ntiles * nchunks), dim3(AP_NT), 0, s, A, lda, r0, mp, vc0, pw, T, Y, ldy,
-                       yr0, c0, ncols, ntiles, nchunks, (const double*)scratch, trans);
-    e = hipGetLastError();
-  }
   prof::end(s);
   return e;
 }
@@ -482,6 +455,7 @@ inline PanelCfg panel_cfg(int mp) {
   if (mp <= 256) return {256, 1, 16};
   if (mp <= 512) return {256, 2, 16};
   if (mp <= 1024) return {256, 4, 16};
+  if (mp <= 1792) return {256, 7, 16};
   if (mp <= 2048) return {512, 4, 16};
   if (mp <= 3072) return {256, 12, 8};
   if (mp <= 3584) return {512, 7, 8};
@@ -512,7 +486,7 @@ hipError_t launch_panel(hipStream_t s, double* A, long lda, int m, int j0, int p
   }
   const size_t sh = (size_t)c.nt * (c.pw + 1) * sizeof(double);
   static bool attr_set = false;
-  if (!attr_set) {
+  if (!attr_set) {  // 512 x 17 doubles of staging exceed the default 64 KiB
     hipError_t e = hipFuncSetAttribute((const void*)k_qr_panel<512, 4, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        512 * 17 * 8);
     if (e != hipSuccess) return e;
@@ -524,6 +498,8 @@ hipError_t launch_panel(hipStream_t s, double* A, long lda, int m, int j0, int p
     hipLaunchKernelGGL((k_qr_panel<256, 2, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
   else if (c.nt == 256 && c.rpt == 4)
     hipLaunchKernelGGL((k_qr_panel<256, 4, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
+  else if (c.nt == 256 && c.rpt == 7)
+    hipLaunchKernelGGL((k_qr_panel<256, 7, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
   else if (c.nt == 512 && c.rpt == 4)
     hipLaunchKernelGGL((k_qr_panel<512, 4, 16>), dim3(1), dim3(512), sh, s, A, lda, m, j0, pw, T, tau);
   else if (c.nt == 256 && c.rpt == 12)
@@ -603,7 +579,7 @@ hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, doub
       if (e != hipSuccess) return e;
       const int c0 = j + pw, nc = jb + nb - c0;
       if (nc > 0) {
-        e = apply_block(s, A, lda, j, m - j, j, pw, Tq, A, lda, j, c0, nc, 1, sc.part);
+        e = apply_block(s, A, lda, j, m - j, j, pw, Tq, A, lda, j, c0, nc, 1);
         if (e != hipSuccess) return e;
       }
       j += pw;

@@ -8,9 +8,15 @@
 //     v = x / (x0 - beta) with v0 = 1,   H = I - tau v v^T,   H x = beta e0
 // (tau = 0, H = I when x has no entries below the diagonal).  The same
 // workgroup reduction that forms v^T A for the update also yields the
-// column V^T v_j; after the last column the compact-WY factor T
-// (H_1..H_b = I - V T V^T, T upper triangular) follows from V^T V and tau by
-// the column recurrence T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
+// column V^T v_j of the earlier reflectors, from which the compact-WY factor
+// T (H_1..H_b = I - V T V^T, T upper triangular) grows one column per step:
+// T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
+//
+// Each column costs one single-barrier workgroup sum for the norm and one
+// for the PW dot products (8 values by a 3-step row transpose, 16 by a
+// 4-step one); the panel is bound by its vector-ALU work, so the
+// reductions are kept short and the column loop is unrolled (every register
+// index a constant).
 #pragma once
 
 #include "qtt_device.hpp"
@@ -22,9 +28,8 @@ namespace qtt {
 // accesses when the panel is full width and aligned), all loads issued
 // before the LDS transposes into the per-thread row layout; a thread's own
 // row segment read directly would touch one cache line per lane and
-// instruction.  T is formed after the column loop by one wave from the
-// accumulated V^T V and the coefficients tau (tau_out, optional, receives
-// them).
+// instruction.  T (16 x 16, row-major, zero outside pw x pw) goes to Tout
+// and the coefficients tau to tau_out (optional).
 template <int NT, int RPT, int PW>
 __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, int m, int j0, int pw,
                                              double* __restrict__ Tout, double* __restrict__ stage = nullptr,
@@ -32,12 +37,11 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
   constexpr int NW = NT / 64;
   constexpr int SW = PW + 1;
   constexpr int HP = PW / 2;  // column pairs
-  __shared__ double red[NT];
-  __shared__ double bc[16];
-  __shared__ double sc[NW];
-  __shared__ double G[16][17];   // G[l][j] = v_l^T v_j (l < j)
-  __shared__ double tauS[16];
-  __shared__ double alphaS;
+  static_assert(PW == 8 || PW == 16, "panel width 8 or 16");
+  __shared__ double red[2 * NW * PW];
+  __shared__ double sc[2 * NW];
+  __shared__ double alphaS[2];
+  __shared__ double Ts[16][17];  // T, built one column per step
   const int tid = threadIdx.x;
   const int mp = m - j0;
   double a[RPT][PW];
@@ -98,18 +102,20 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
       __syncthreads();
     }
   }
+  for (int t = tid; t < 16 * 17; t += NT) (&Ts[0][0])[t] = 0.0;
+  // Rows outside the panel are zero and stay zero; only rows of r = 0 can
+  // lie at or above the diagonal (j < 16 <= NT).
 #pragma unroll
   for (int j = 0; j < PW; ++j) {
     if (j < pw) {
+      const int par = j & 1;
       double s = 0.0;
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int lr = tid + r * NT;
-        if (lr > j && lr < mp) s += a[r][j] * a[r][j];
-      }
-      if (tid == j) alphaS = a[0][j];
-      s = block_sum<NT>(s, sc);
-      const double alpha = alphaS;
+      for (int r = 0; r < RPT; ++r)
+        if (r > 0 || tid > j) s += a[r][j] * a[r][j];
+      if (tid == j) alphaS[par] = a[0][j];
+      s = wg_sum1<NT>(s, sc, par);
+      const double alpha = alphaS[par];
       double tau, beta, scale;
       if (s == 0.0) {
         tau = 0.0;
@@ -120,69 +126,47 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
+      double v[RPT];
 #pragma unroll
       for (int r = 0; r < RPT; ++r) {
-        const int lr = tid + r * NT;
-        if (lr > j && lr < mp) a[r][j] *= scale;
+        if (r > 0 || tid > j) a[r][j] *= scale;
+        v[r] = (r > 0 || tid > j) ? a[r][j] : (tid == j ? 1.0 : 0.0);
       }
       if (tid == j) a[0][j] = beta;
-      double p[16];
+      // columns still to come get v^T a (the update), columns already
+      // factored give v_l^T v_j (rows >= j lie below their diagonal)
+      double p[PW], d[PW];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) p[c] = 0.0;
+      for (int c = 0; c < PW; ++c) p[c] = 0.0;
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int lr = tid + r * NT;
-        const bool in = lr >= j && lr < mp;
-        const double v = in ? ((lr == j) ? 1.0 : a[r][j]) : 0.0;
-#pragma unroll
-        for (int c = 0; c < PW; ++c) {
-          if (c > j) {
-            p[c] += v * a[r][c];
-          } else if (c < j) {
-            const double vc = (lr > c) ? a[r][c] : (lr == c ? 1.0 : 0.0);
-            p[c] += v * vc;
-          }
-        }
-      }
-      block_sum16<NT>(p, red, bc);
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int lr = tid + r * NT;
-        const bool in = lr >= j && lr < mp;
-        const double tv = in ? tau * ((lr == j) ? 1.0 : a[r][j]) : 0.0;
+      for (int r = 0; r < RPT; ++r)
 #pragma unroll
         for (int c = 0; c < PW; ++c)
-          if (c > j) a[r][c] -= tv * bc[c];
+          if (c != j) p[c] += v[r] * a[r][c];
+      wg_sum_vals<NT, PW>(p, red, par, d);
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) v[r] *= tau;
+#pragma unroll
+      for (int c = j + 1; c < PW; ++c) {
+        if (c < pw) {
+#pragma unroll
+          for (int r = 0; r < RPT; ++r) a[r][c] -= v[r] * d[c];
+        }
       }
-      if (tid < j) G[tid][j] = bc[tid];
-      if (tid == j) tauS[j] = tau;
-      __syncthreads();
-    }
-  }
-  // T (upper triangular, order pw): T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j];
-  // lane i of wave 0 keeps row i of T in registers.
-  if (tid < 64) {
-    const int i = tid;
-    double trow[16];
-#pragma unroll
-    for (int l = 0; l < 16; ++l) trow[l] = 0.0;
-#pragma unroll
-    for (int j = 0; j < PW; ++j) {
-      if (j < pw) {
-        const double tj = tauS[j];
+      // column j of T
+      if (tid < j) {
         double acc = 0.0;
 #pragma unroll
-        for (int l = 0; l < j; ++l) acc += (l >= i) ? trow[l] * G[l][j] : 0.0;
-        if (i < j) trow[j] = -tj * acc;
-        if (i == j) trow[j] = tj;
+        for (int l = 0; l < j; ++l)
+          if (l >= tid) acc += Ts[tid][l] * d[l];
+        Ts[tid][j] = -tau * acc;
       }
+      if (tid == j) Ts[j][j] = tau;
     }
-    if (i < 16) {
-#pragma unroll
-      for (int l = 0; l < 16; ++l) Tout[i * 16 + l] = trow[l];
-    }
-    if (tau_out && i < pw) tau_out[i] = tauS[i];
   }
+  __syncthreads();
+  for (int t = tid; t < 256; t += NT) Tout[t] = Ts[t >> 4][t & 15];
+  if (tau_out && tid < pw) tau_out[tid] = Ts[tid][tid];
   if (!stage) {
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {

@@ -20,6 +20,7 @@ constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1,0,3,2]
 constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2,3,0,1]
 constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8
 constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15 - i within 16
+constexpr int DPP_ROW_ROR8 = 0x128;     // lane i <- lane (i + 8) % 16 within 16
 
 // Sum over the 16 lanes of each row; all 16 lanes get the same bits.
 __device__ __forceinline__ double row_sum(double v) {
@@ -132,6 +133,91 @@ __device__ __forceinline__ void block_sum16(const double (&x)[16], double* red, 
     out[threadIdx.x] = s;
   }
   __syncthreads();
+}
+
+// Row-level transpose reduction of 8 values per lane: afterwards lane L
+// holds the sum over its row (16 lanes) of value index L % 8.  Three
+// splitting steps inside each half row (partners by half mirror, xor 2,
+// xor 1: 4 + 2 + 1 DPP exchanges), then the two half rows are added by a
+// rotation of the row by 8 lanes.
+__device__ __forceinline__ double row_sum8(const double (&x)[8]) {
+  const int l = threadIdx.x & 15;
+  double y[4];
+  const bool b2 = (l & 4) != 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double send = b2 ? x[i] : x[i + 4];
+    const double keep = b2 ? x[i + 4] : x[i];
+    y[i] = keep + dpp<DPP_HALF_MIRROR>(send);
+  }
+  double z[2];
+  const bool b1 = (l & 2) != 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double send = b1 ? y[i] : y[i + 2];
+    const double keep = b1 ? y[i + 2] : y[i];
+    z[i] = keep + dpp<DPP_XOR2>(send);
+  }
+  const bool b0 = (l & 1) != 0;
+  const double send = b0 ? z[0] : z[1];
+  const double keep = b0 ? z[1] : z[0];
+  const double u = keep + dpp<DPP_XOR1>(send);
+  return u + dpp<DPP_ROW_ROR8>(u);
+}
+
+// Adds the four rows of 16 lanes lane by lane (row swaps of gfx950): every
+// lane L gets the sum over lanes L % 16 + 16 q, q = 0..3.
+__device__ __forceinline__ double rows_add(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  v = __longlong_as_double((long long)(((unsigned long long)b[0] << 32) | a[0])) +
+      __longlong_as_double((long long)(((unsigned long long)b[1] << 32) | a[1]));
+  const unsigned long long w = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo2 = (unsigned)w, hi2 = (unsigned)(w >> 32);
+  const auto c = __builtin_amdgcn_permlane32_swap(lo2, lo2, false, false);
+  const auto d = __builtin_amdgcn_permlane32_swap(hi2, hi2, false, false);
+  return __longlong_as_double((long long)(((unsigned long long)d[0] << 32) | c[0])) +
+         __longlong_as_double((long long)(((unsigned long long)d[1] << 32) | c[1]));
+}
+
+// Workgroup sum of one value with a single barrier: slots holds 2 sets of
+// NT/64 doubles used alternately (par), so that consecutive calls need no
+// barrier to protect the slots.  Every thread gets the same bits.
+template <int NT>
+__device__ __forceinline__ double wg_sum1(double v, double* slots, int par) {
+  constexpr int NW = NT / WAVE;
+  v = rows_add(row_sum(v));
+  if ((threadIdx.x & (WAVE - 1)) == 0) slots[par * NW + threadIdx.x / WAVE] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += slots[par * NW + w];
+  return s;
+}
+
+// Workgroup sums of NV (8 or 16) values per thread with a single barrier;
+// slots holds 2 sets of (NT/64) * NV doubles used alternately.  out[c] is
+// the total of value c, the same bits in every thread (read back from one
+// lane, so it is uniform across the wave).
+template <int NT, int NV>
+__device__ __forceinline__ void wg_sum_vals(const double (&x)[NV], double* slots, int par, double (&out)[NV]) {
+  static_assert(NV == 8 || NV == 16, "8 or 16 values");
+  constexpr int NW = NT / WAVE;
+  double r;
+  if constexpr (NV == 8) r = row_sum8(x);
+  else r = row_sum16(x);
+  r = rows_add(r);
+  const int lane = threadIdx.x & (WAVE - 1);
+  double* base = slots + par * NW * NV;
+  if (lane < NV) base[(threadIdx.x / WAVE) * NV + lane] = r;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += base[w * NV + (lane & (NV - 1))];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) out[c] = readlane_f64(t, c);
 }
 
 // Sum over the 64 lanes with the row broadcasts of DPP: after the row sums,
