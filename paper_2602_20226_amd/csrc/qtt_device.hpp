@@ -230,47 +230,52 @@ __device__ __forceinline__ double wave_sum_bc(double v) {
   return readlane_f64(v, 63);
 }
 
+// 1/sqrt(x) and 1/x for x in [2^-3, 2^3]: single-precision hardware
+// estimate (relative error e ~ 2^-22), then one correction step of third
+// order, r (1 + e/2 + 3 e^2 / 8) and r (1 + e + e^2), which leaves a
+// truncation error ~e^3 (below double rounding) in fewer dependent steps
+// than two Newton iterations.
+__device__ __forceinline__ double rsq_f64(double x) {
+  const double r = (double)__builtin_amdgcn_rsqf((float)x);
+  const double e = fma(-x * r, r, 1.0);
+  return fma(r * e, fma(0.375, e, 0.5), r);
+}
+__device__ __forceinline__ double rcp_f64(double x) {
+  const double r = (double)__builtin_amdgcn_rcpf((float)x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
+}
+
 // Plane rotation of the one-sided Jacobi method for rows a, c with
 // al = ||a||^2, be = ||c||^2, ga = a.c: returns false when the pair is
 // orthogonal to the tolerance (|a.c| <= tol ||a|| ||c||), else (cs, sn) with
 // [a; c] <- [cs a - sn c; sn a + cs c] making the pair orthogonal.
 __device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double tol, double& cs_out,
                                                 double& sn_out, double& t_out) {
-  if (ga == 0.0) return false;
   // squared form of the test inside the safe range
   const bool safe = fmin(al, be) > 1e-140 && fmax(al, be) < 1e140;
-  if (safe ? !(ga * ga > (tol * tol) * (al * be)) : !(fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
-  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 ga),
-  // i.e. t = sign(d g) |g| / (|d| + sqrt(d^2 + g^2)) with d = be - al,
-  // g = 2 ga, evaluated on d, g scaled by a power of two so that the larger
-  // magnitude lies in [0.5, 1) (the ratio does not change);
-  // c = (1 + t^2)^(-1/2), s = c t.  Square roots and reciprocals start from
-  // the single-precision hardware estimates and take two Newton steps each
-  // (relative error ~2^-23 -> ~2^-92, i.e. below double rounding).
+  const bool rot = ga != 0.0 && (safe ? (ga * ga > (tol * tol) * (al * be)) : (fabs(ga) > tol * sqrt(al) * sqrt(be)));
+  // With d = be - al, g = 2 ga (scaled by a power of two so that the larger
+  // magnitude lies in [0.5, 1); the ratios below do not change):
+  //   h = sqrt(d^2 + g^2), u = h + |d|, w = 1/sqrt(2 h u),
+  //   cs = u w, sn = sign(d g) |g| w, t = sn/cs = sign(d g) |g| / u,
+  // i.e. t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) with zeta = d / g and
+  // cs = (1 + t^2)^(-1/2), sn = cs t; 1/sqrt(2 h u) and 1/u are independent.
+  // Evaluated whether or not the pair rotates, so that it overlaps the test.
   double d = be - al, g = 2.0 * ga;
   const int ke = __builtin_amdgcn_frexp_exp(fmax(fabs(d), fabs(g)));
   d = __builtin_amdgcn_ldexp(d, -ke);
   g = __builtin_amdgcn_ldexp(g, -ke);
-  const double x = d * d + g * g;  // in [0.25, 2)
-  double r = (double)__builtin_amdgcn_rsqf((float)x);
-  const double hx = 0.5 * x;
-  r = r * fma(-hx, r * r, 1.5);
-  r = r * fma(-hx, r * r, 1.5);
-  const double den = fabs(d) + x * r;  // |d| + sqrt(d^2 + g^2), in [0.5, 3)
-  double rq = (double)__builtin_amdgcn_rcpf((float)den);
-  rq = fma(rq, fma(-den, rq, 1.0), rq);
-  rq = fma(rq, fma(-den, rq, 1.0), rq);
-  const double t = copysign(fabs(g) * rq, d * g);  // |t| <= 1
-  const double y = fma(t, t, 1.0);                // in [1, 2]
-  double cs = (double)__builtin_amdgcn_rsqf((float)y);
-  const double hy = 0.5 * y;
-  cs = cs * fma(-hy, cs * cs, 1.5);
-  cs = cs * fma(-hy, cs * cs, 1.5);
-  const double sn = cs * t;
-  cs_out = cs;
-  sn_out = sn;
-  t_out = t;  // the new squared norms are al - t ga and be + t ga
-  return true;
+  const double x = fma(d, d, g * g);  // in [0.25, 2)
+  const double h = x * rsq_f64(x);
+  const double u = h + fabs(d);       // in [0.5, 2.5)
+  const double w = rsq_f64(2.0 * h * u);
+  const double ru = rcp_f64(u);
+  const double ag = copysign(fabs(g), d * g);
+  cs_out = u * w;
+  sn_out = ag * w;
+  t_out = ag * ru;  // the new squared norms are al - t ga and be + t ga
+  return rot;
 }
 
 __device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double tol, double& cs_out,
