@@ -31,8 +31,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 
 // ------------------------------------------------------------ outer blocks
 constexpr int OB = 64;    // outer block width: reflectors aggregated per (V, T)
-constexpr int KC = 256;   // row chunk of the split-K products
-constexpr int MAX_CHUNKS = 16;  // m <= 4096
+constexpr int KC = 256;   // largest row chunk of the split-K products
+constexpr int KC_MIN = 64;      // smallest (one staged slab)
+constexpr int MAX_CHUNKS = 64;  // m <= 4096 at the smallest chunk
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -82,13 +83,13 @@ __device__ __forceinline__ void put_vslab(double* __restrict__ Vs, const double 
 // C[i][col] with i = lane / 16 + 4 v, col = lane % 16.
 __global__ __launch_bounds__(256) void k_vty(const double* __restrict__ A, long lda, int j0, int mp, int nb,
                                              const double* __restrict__ Y, long ldy, int yr0, int yc0, int ncols,
-                                             int s_cols, int ntiles, double* __restrict__ part) {
+                                             int s_cols, int ntiles, int kc, double* __restrict__ part) {
   __shared__ double Vs[2][SL * VT_LD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
   const int col = tile * 64 + w * 16 + (lane & 15);
   const int kq = lane >> 4, il = lane & 15;
-  const int kbeg = chunk * KC, kend = min(mp, kbeg + KC);
+  const int kbeg = chunk * kc, kend = min(mp, kbeg + kc);
   const int nslab = (kend - kbeg + SL - 1) / SL;
   const double* Ab = A + (long)j0 * lda + j0;
   const double* Yc = Y + (long)yr0 * ldy + yc0 + col;
@@ -192,18 +193,20 @@ __global__ __launch_bounds__(256) void k_tbuild(const double* __restrict__ Sg, i
 }
 
 // W[i][col] = sum_c P_c[i][col] for i < nb, col < ncols (fixed summation
-// order: deterministic).  One thread per entry, all chunk loads in flight.
+// order: deterministic).  One thread per entry, loads in flight 16 at a time.
 __global__ __launch_bounds__(256) void k_red(const double* __restrict__ part, int nchunks, int ncols, int nb,
                                              double* __restrict__ W) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= (long)nb * ncols) return;
   const int i = (int)(e / ncols), col = (int)(e % ncols);
-  double v[MAX_CHUNKS];
-#pragma unroll
-  for (int c = 0; c < MAX_CHUNKS; ++c) v[c] = (c < nchunks) ? part[((long)c * OB + i) * ncols + col] : 0.0;
   double sum = 0.0;
+  for (int c0 = 0; c0 < nchunks; c0 += 16) {
+    double v[16];
 #pragma unroll
-  for (int c = 0; c < MAX_CHUNKS; ++c) sum += v[c];
+    for (int c = 0; c < 16; ++c) v[c] = (c0 + c < nchunks) ? part[((long)(c0 + c) * OB + i) * ncols + col] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) sum += v[c];
+  }
   W[(long)i * ncols + col] = sum;
 }
 
@@ -217,14 +220,14 @@ __global__ __launch_bounds__(256) void k_red(const double* __restrict__ part, in
 __global__ __launch_bounds__(256) void k_vupd(const double* __restrict__ A, long lda, int j0, int mp, int nb,
                                               const double* __restrict__ T, int trans, const double* __restrict__ W,
                                               long ldw, int wc0, double* __restrict__ Y, long ldy, int yr0, int yc0,
-                                              int ncols, int ntiles) {
+                                              int ncols, int ntiles, int kc) {
   __shared__ double Vs[2][SL * VU_LD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int tile = blockIdx.x % ntiles, chunk = blockIdx.x / ntiles;
   const int col = tile * 64 + w * 16 + (lane & 15);
   const int kq = lane >> 4, il = lane & 15;
   const bool colok = col < ncols;
-  const int kbeg = chunk * KC, kend = min(mp, kbeg + KC);
+  const int kbeg = chunk * kc, kend = min(mp, kbeg + kc);
   const int nslab = (kend - kbeg + SL - 1) / SL;
   const double* Ab = A + (long)j0 * lda + j0;
   double* Yc = Y + (long)yr0 * ldy + yc0 + col;
@@ -513,28 +516,41 @@ hipError_t launch_panel(hipStream_t s, double* A, long lda, int m, int j0, int p
   return e;
 }
 
-// P = V^T Yv over all row chunks of the block (mp rows).
-hipError_t launch_vty(hipStream_t s, const double* A, long lda, int j0, int mp, int nb, const double* Y, long ldy,
-                      int yr0, int yc0, int ncols, int s_cols, double* part) {
-  const int ntiles = ceil_div(ncols, 64), nch = ceil_div(mp, KC);
+// Row chunk of the split-K kernels: 256 rows, halved (down to one 64-row
+// slab) while the grid has fewer than 160 workgroups, so that small
+// trailing blocks still spread over the chip.
+inline int pick_kc(int ncols, int mp) {
+  const int ntiles = ceil_div(ncols, 64);
+  int kc = KC;
+  while (kc > KC_MIN && (long)ntiles * ceil_div(mp, kc) < 160) kc /= 2;
+  return kc;
+}
+
+// P = V^T Yv over all row chunks of the block (mp rows); returns the number
+// of chunks written (nch > 0), 0 on a launch error.
+int launch_vty(hipStream_t s, const double* A, long lda, int j0, int mp, int nb, const double* Y, long ldy, int yr0,
+               int yc0, int ncols, int s_cols, double* part) {
+  const int kc = pick_kc(ncols, mp);
+  const int ntiles = ceil_div(ncols, 64), nch = ceil_div(mp, kc);
   if (prof::active(prof::BLOCK_VTY))
     prof::begin(s, prof::BLOCK_VTY, 8.0 * ((double)mp * nb + (double)mp * (ncols - s_cols) + (double)nch * nb * ncols),
                 2.0 * mp * (double)nb * ncols);
   hipLaunchKernelGGL(k_vty, dim3(ntiles * nch), dim3(256), 0, s, A, lda, j0, mp, nb, Y, ldy, yr0, yc0, ncols, s_cols,
-                     ntiles, part);
+                     ntiles, kc, part);
   hipError_t e = hipGetLastError();
   prof::end(s);
-  return e;
+  return e == hipSuccess ? nch : 0;
 }
 
 hipError_t launch_vupd(hipStream_t s, const double* A, long lda, int j0, int mp, int nb, const double* T, int trans,
                        const double* W, long ldw, int wc0, double* Y, long ldy, int yr0, int yc0, int ncols) {
-  const int ntiles = ceil_div(ncols, 64), nch = ceil_div(mp, KC);
+  const int kc = pick_kc(ncols, mp);
+  const int ntiles = ceil_div(ncols, 64), nch = ceil_div(mp, kc);
   if (prof::active(prof::BLOCK_UPD))
     prof::begin(s, prof::BLOCK_UPD, 8.0 * (2.0 * mp * ncols + (double)mp * nb + (double)nb * ncols),
                 2.0 * mp * (double)nb * ncols);
   hipLaunchKernelGGL(k_vupd, dim3(ntiles * nch), dim3(256), 0, s, A, lda, j0, mp, nb, T, trans, W, ldw, wc0, Y, ldy,
-                     yr0, yc0, ncols, ntiles);
+                     yr0, yc0, ncols, ntiles, kc);
   hipError_t e = hipGetLastError();
   prof::end(s);
   return e;
@@ -559,7 +575,7 @@ long qr_t_doubles(int m, int n) { return (long)ceil_div(std::min(m, n), OB) * OB
 
 hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, double* Tbuf, double* scratch) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (m > KC * MAX_CHUNKS) return hipErrorInvalidValue;
+  if (m > KC_MIN * MAX_CHUNKS) return hipErrorInvalidValue;
   const int kmax = std::min(m, n);
   const Scr sc = scr_of(scratch, n);
   return for_each_outer(kmax, [&](int b, int jb, int nb) -> hipError_t {
@@ -585,10 +601,10 @@ hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, doub
       j += pw;
     }
     // aggregated (V, T) of the block, then the trailing update with Q_b^T
-    const int mp = m - jb, ntrail = n - (jb + nb), nch = ceil_div(mp, KC);
+    const int mp = m - jb, ntrail = n - (jb + nb);
     const int ncw = nb + ntrail;
-    e = launch_vty(s, A, lda, jb, mp, nb, A, lda, jb, jb, ncw, nb, sc.part);
-    if (e != hipSuccess) return e;
+    const int nch = launch_vty(s, A, lda, jb, mp, nb, A, lda, jb, jb, ncw, nb, sc.part);
+    if (nch == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_red, dim3(ceil_div((long)nb * ncw, 256)), dim3(256), 0, s, (const double*)sc.part, nch, ncw,
                        nb, sc.w);
     e = hipGetLastError();
@@ -604,15 +620,16 @@ hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, doub
 hipError_t apply_q(hipStream_t s, const double* A, int m, int kref, long lda, const double* Tbuf, double* Y,
                    int ncols, long ldy, bool trans, double* scratch) {
   if (m <= 0 || ncols <= 0 || kref <= 0) return hipSuccess;
-  if (m > KC * MAX_CHUNKS) return hipErrorInvalidValue;
+  if (m > KC_MIN * MAX_CHUNKS) return hipErrorInvalidValue;
   const Scr sc = scr_of(scratch, ncols);
   const int nblk = ceil_div(kref, OB);
   for (int t = 0; t < nblk; ++t) {
     const int b = trans ? t : nblk - 1 - t;
     const int jb = b * OB, nb = std::min(OB, kref - jb);
-    const int mp = m - jb, nch = ceil_div(mp, KC);
-    hipError_t e = launch_vty(s, A, lda, jb, mp, nb, Y, ldy, jb, 0, ncols, 0, sc.part);
-    if (e != hipSuccess) return e;
+    const int mp = m - jb;
+    const int nch = launch_vty(s, A, lda, jb, mp, nb, Y, ldy, jb, 0, ncols, 0, sc.part);
+    if (nch == 0) return hipGetLastError();
+    hipError_t e;
     hipLaunchKernelGGL(k_red, dim3(ceil_div((long)nb * ncols, 256)), dim3(256), 0, s, (const double*)sc.part, nch,
                        ncols, nb, sc.w);
     e = hipGetLastError();

@@ -59,10 +59,10 @@ hipError_t householder_qr(hipStream_t s, double* A, int m, int n, long lda, doub
 hipError_t apply_q(hipStream_t s, const double* A, int m, int kref, long lda, const double* Tbuf,
                    double* Y, int ncols, long ldy, bool trans, double* scratch);
 // Scratch of one QR or Q application on ncols columns: split-K partials
-// (16 chunks x 64 x ncols), the 64 x ncols product, inner T blocks and tau.
+// (up to 64 chunks x 64 x ncols), the 64 x ncols product, inner T blocks and tau.
 inline long qr_scratch_doubles(long ncols) {
   const long nc = ncols < 1 ? 1 : ncols;
-  return 16L * 64L * nc + 64L * nc + 8L * 256L + 64L;
+  return 64L * 64L * nc + 64L * nc + 8L * 256L + 64L;
 }
 // R = upper trapezoid of A[0:kr, 0:n] (zeros below the diagonal) into Rout (ld n).
 hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, double* Rout);
