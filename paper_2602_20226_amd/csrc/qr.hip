@@ -522,7 +522,7 @@ hipError_t launch_panel(hipStream_t s, double* A, long lda, int m, int j0, int p
 inline int pick_kc(int ncols, int mp) {
   const int ntiles = ceil_div(ncols, 64);
   int kc = KC;
-  while (kc > KC_MIN && (long)ntiles * ceil_div(mp, kc) < 160) kc /= 2;
+  while (kc > KC_MIN && (long)ntiles * ceil_div(mp, kc) < 320) kc /= 2;
   return kc;
 }
 
