@@ -175,9 +175,14 @@ __global__ __launch_bounds__(256) void k_tbuild(const double* __restrict__ Sg, i
     // X = T[0:o, 0:o] S[0:o, o:o+w]   (T upper triangular)
     for (int e = tid; e < o * w; e += 256) {
       const int i = e / w, c = e % w;
-      double acc = 0.0;
-      for (int l = i; l < o; ++l) acc += T[i][l] * S[l][o + c];
-      X[i][c] = acc;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums: a quarter of the dependent chain
+      int l = i;
+      for (; l + 3 < o; l += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += T[i][l + u] * S[l + u][o + c];
+      }
+      for (; l < o; ++l) acc[0] += T[i][l] * S[l][o + c];
+      X[i][c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
     __syncthreads();
     // T[0:o, o:o+w] = -X T_q
