@@ -159,6 +159,32 @@ def test_orthogonalize_largest_unfolding():
         assert abs(_rank1_probe(Yh, z) - _rank1_probe(X, z)) <= 1e-12 * ref_norm * zn
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("r1,r2", [(129, 131), (513, 64), (897, 131), (1025, 64), (1537, 131), (1793, 131)])
+def test_orthogonalize_panel_configurations(r1, r2):
+    """Unfoldings of 2 r1 rows on both sides of every row-count boundary at
+    which the QR changes its panel shape, inner-application tile or split-K
+    chunking (258 ... 3586 rows), with odd and even column counts (row
+    strides that forbid and allow 16-byte accesses).  Left ranks double up to
+    1024 so that every unfolding has full row rank."""
+    ranks = [2 ** k for k in range(11)] + [r1, r2, 2, 1]
+    log(f"orthogonalize panel configurations r1={r1} r2={r2}")
+    rng = np.random.default_rng(109 + r1)
+    X = [rng.standard_normal((ranks[k], 2, ranks[k + 1])) / np.sqrt(2 * ranks[k + 1]) for k in range(len(ranks) - 1)]
+    Y, nrm = Q.orthogonalize(dev(X))
+    Yh = host(Y)
+    assert Yh[11].shape == (r1, 2, r2)
+    for c in Yh[:-1]:
+        M = c.reshape(-1, c.shape[-1])
+        assert np.abs(M.T @ M - np.eye(M.shape[1])).max() <= 1e-13
+    _, ref_norm = O.orthogonalize(X)
+    assert abs(nrm - ref_norm) <= 1e-13 * ref_norm
+    for _ in range(4):
+        z = [rng.standard_normal(2) for _ in range(len(X))]
+        zn = np.prod([np.linalg.norm(v) for v in z])
+        assert abs(_rank1_probe(Yh, z) - _rank1_probe(X, z)) <= 1e-12 * ref_norm * zn
+
+
 # ------------------------------------------------------------------ rounding (a3 + a4)
 def check_round(got, ref_cores, ref_info, tol=1e-12, sig_tol=1e-12, ranks_exact=True):
     gh = host(got.cores)
