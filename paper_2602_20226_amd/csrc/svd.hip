@@ -229,14 +229,21 @@ __global__ __launch_bounds__(1024) void k_norms_sort(const double* __restrict__ 
                                                      double* __restrict__ sig_sorted, int* __restrict__ perm) {
   extern __shared__ double sg[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < p; i += 16) {
-    double s = 0.0;
+  // four rows per wave at a time, all their loads in flight together
+  for (int i0 = 4 * wave; i0 < p; i0 += 64) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = lane; c < L; c += 64) {
-      const double v = X[(long)i * L + c];
-      s += v * v;
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = (i0 + u < p) ? X[(long)(i0 + u) * L + c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u] += v[u] * v[u];
     }
-    s = wave_sum(s);
-    if (lane == 0) sg[i] = sqrt(s);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double t = wave_sum(s[u]);
+      if (lane == 0 && i0 + u < p) sg[i0 + u] = sqrt(t);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < p; i += 1024) {
