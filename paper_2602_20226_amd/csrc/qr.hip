@@ -2,12 +2,13 @@
 //
 // Two levels.  Inner panels of up to 16 columns are factored by one
 // workgroup each (qr_panel_dev in qr_device.hpp) and applied to the rest of
-// their 64-column outer block by apply_block (one workgroup per column).  The reflectors of an outer block are
-// then aggregated into one compact-WY pair (V, T) with T of order <= 64,
-// built from S = V^T V and the reflector coefficients, and the trailing
-// matrix -- and every later application of Q or Q^T -- is updated once per
-// outer block by three kernels on FP64 MFMA tiles:
-//     P_c = V_c^T Y_c          (split over 256-row chunks c),
+// their 64-column outer block by apply_block (one workgroup per column).
+// The reflectors of an outer block are then aggregated into one compact-WY
+// pair (V, T) with T of order <= 64, built from S = V^T V and the panels'
+// own T blocks, and the trailing matrix -- and every later application of
+// Q or Q^T -- is updated once per outer block by three kernels on FP64
+// MFMA tiles:
+//     P_c = V_c^T Y_c          (split over row chunks c of 64..256 rows),
 //     W   = -op(T) sum_c P_c,
 //     Y  += V W.
 // V is never copied: the kernels read it from the unit lower trapezoid of
