@@ -31,6 +31,7 @@ struct Smem {
   double w2sh[16][17];
   double tsh[16][17];
   double scal[16];
+  double jn[16];  // squared norms of the 16 rows of a Jacobi visit
   int iscal[8];
 };
 
@@ -147,28 +148,42 @@ __device__ __forceinline__ int rr_item(int pos, int round, int n) {
 
 // One-sided Jacobi on the rows of X (p x L) by this workgroup; blocks of JB
 // rows, block pairs visited sequentially in the round-robin order, each pair
-// staged in LDS.  A visit rotates the JB x JB cross pairs (JB steps of JB
+// staged in LDS with its squared row norms.  A visit rotates the JB x JB cross pairs (JB steps of JB
 // disjoint pairs, waves taking pairs in turn); the pairs inside each block
 // are rotated once per sweep, in the first round.  Returns the sweep count
 // (max_sweeps when not converged).
-__device__ __forceinline__ int wg_rotate(double* __restrict__ xa, double* __restrict__ xc, int L, double tol) {
+constexpr int JEMAX = 12;  // row elements per lane: L <= 768
+
+// Rotate rows xa, xc (LDS, length L) whose squared norms *na, *nc (LDS) are
+// carried through the visit: one dot product and one wave sum per pair, each
+// row read once; the new norms are ||a||^2 - t a.c and ||c||^2 + t a.c.
+__device__ __forceinline__ int wg_rotate(double* __restrict__ xa, double* __restrict__ xc, double* __restrict__ na,
+                                         double* __restrict__ nc, int L, double tol) {
   const int lane = threadIdx.x & 63;
-  double al = 0.0, be = 0.0, ga = 0.0;
-  for (int c = lane; c < L; c += 64) {
-    const double u = xa[c], w = xc[c];
-    al += u * u;
-    be += w * w;
-    ga += u * w;
+  double u[JEMAX], w[JEMAX];
+  double ga = 0.0;
+#pragma unroll
+  for (int q = 0; q < JEMAX; ++q) {
+    const int c = lane + 64 * q;
+    u[q] = c < L ? xa[c] : 0.0;
+    w[q] = c < L ? xc[c] : 0.0;
+    ga += u[q] * w[q];
   }
-  al = wave_sum_bc(al);
-  be = wave_sum_bc(be);
   ga = wave_sum_bc(ga);
-  double cs, sn;
-  if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return 0;
-  for (int c = lane; c < L; c += 64) {
-    const double u = xa[c], w = xc[c];
-    xa[c] = cs * u - sn * w;
-    xc[c] = sn * u + cs * w;
+  const double al = *na, be = *nc;
+  double cs, sn, t;
+  if (!jacobi_rotation(al, be, ga, tol, cs, sn, t)) return 0;
+#pragma unroll
+  for (int q = 0; q < JEMAX; ++q) {
+    const int c = lane + 64 * q;
+    if (c < L) {
+      xa[c] = cs * u[q] - sn * w[q];
+      xc[c] = sn * u[q] + cs * w[q];
+    }
+  }
+  if (lane == 0) {
+    *na = al - t * ga;
+    *nc = be + t * ga;
   }
   return 1;
 }
@@ -196,21 +211,31 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
           sh[t * L + c] = (gr < p) ? X[(long)gr * L + c] : 0.0;
         }
         wg_sync();
+        for (int t = wave; t < JR; t += NW) {  // squared row norms, carried through the visit
+          double s2 = 0.0;
+          for (int c = lane; c < L; c += 64) s2 += sh[t * L + c] * sh[t * L + c];
+          s2 = wave_sum_bc(s2);
+          if (lane == 0) sm.jn[t] = s2;
+        }
+        wg_sync();
         int rot = 0;
         if (round == 0) {
           // pairs inside each block: JB - 1 steps of JB / 2 disjoint pairs per block
           for (int st = 0; st < JB - 1; ++st) {
             for (int q = wave; q < JB; q += NW) {
               const int blk = q / (JB / 2), i = q % (JB / 2);
-              rot += wg_rotate(sh + (blk * JB + rr_item(i, st, JB)) * L,
-                               sh + (blk * JB + rr_item(JB - 1 - i, st, JB)) * L, L, tol);
+              const int ta = blk * JB + rr_item(i, st, JB), tc = blk * JB + rr_item(JB - 1 - i, st, JB);
+              rot += wg_rotate(sh + ta * L, sh + tc * L, &sm.jn[ta], &sm.jn[tc], L, tol);
             }
             wg_sync();
           }
         }
         // cross pairs: at step s top row q meets bottom row (q + s) % JB
         for (int s = 0; s < JB; ++s) {
-          for (int q = wave; q < JB; q += NW) rot += wg_rotate(sh + q * L, sh + (JB + (q + s) % JB) * L, L, tol);
+          for (int q = wave; q < JB; q += NW) {
+            const int tc = JB + (q + s) % JB;
+            rot += wg_rotate(sh + q * L, sh + tc * L, &sm.jn[q], &sm.jn[tc], L, tol);
+          }
           wg_sync();
         }
         if (lane == 0 && rot) atomicAdd(&sm.iscal[0], rot);
