@@ -30,6 +30,16 @@ namespace qtt {
 // row segment read directly would touch one cache line per lane and
 // instruction.  T (16 x 16, row-major, zero outside pw x pw) goes to Tout
 // and the coefficients tau to tau_out (optional).
+// 1/x over the whole normal range: double-precision hardware estimate
+// (relative error e ~2^-24) and one third-order correction r (1 + e + e^2),
+// within an ulp or two; the two reciprocals of a reflector need no IEEE
+// division.
+__device__ __forceinline__ double rcp_f64_full(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
+}
+
 template <int NT, int RPT, int PW>
 __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, int m, int j0, int pw,
                                              double* __restrict__ Tout, double* __restrict__ stage = nullptr,
@@ -109,12 +119,12 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
   for (int j = 0; j < PW; ++j) {
     if (j < pw) {
       const int par = j & 1;
-      double s = 0.0;
+      double sp[3] = {0.0, 0.0, 0.0};  // three partial sums: a third of the dependent chain
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
-        if (r > 0 || tid > j) s += a[r][j] * a[r][j];
+        if (r > 0 || tid > j) sp[r % 3] += a[r][j] * a[r][j];
       if (tid == j) alphaS[par] = a[0][j];
-      s = wg_sum1<NT>(s, sc, par);
+      double s = wg_sum1<NT>((sp[0] + sp[1]) + sp[2], sc, par);
       const double alpha = alphaS[par];
       double tau, beta, scale;
       if (s == 0.0) {
@@ -123,8 +133,8 @@ __device__ __forceinline__ void qr_panel_dev(double* __restrict__ A, long lda, i
         scale = 0.0;
       } else {
         beta = -copysign(sqrt(alpha * alpha + s), alpha);
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
+        tau = (beta - alpha) * rcp_f64_full(beta);
+        scale = rcp_f64_full(alpha - beta);
       }
       double v[RPT];
 #pragma unroll
