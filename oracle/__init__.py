@@ -17,7 +17,10 @@ numpy.linalg, written from the paper's definitions:
     SVD sweep -- the TT-rounding algorithm of Oseledets (2011), which the
     paper cites for tensor trains; the paper's "decomposition(max_rank,
     cutoff)" options are read as a relative Frobenius tolerance and a rank cap;
-  * inner product: the <C|C>-type contractions of Sec. 3.3.
+  * inner product: the <C|C>-type contractions of Sec. 3.3;
+  * decomposition ("zip-up") algorithm of Sec. 3.2: operands normalised to
+    the left end, then a super-core of N exact product cores split off one
+    truncated-SVD core at a time while the next product core is added.
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: dense reconstruction + numpy.einsum on tiny grids, the closed forms of
