@@ -10,7 +10,11 @@ inputs are resident in HBM before the timed region.
 Prints one JSON line: metric, value, roofline of the kernel class that
 takes the most time, and the oracle's CPU baseline on the same workload.
 `--workload hadamard_batch` measures the batched form instead (512 uneven 1D
-Hadamard products in one graph-replayed persistent launch).
+Hadamard products in one graph-replayed persistent launch), and
+`--workload laplacian3d_n42_r256_zipup` the same product computed by the
+decomposition ("zip-up") algorithm of Sec. 3.2 (`--ncores` product cores per
+super-core), whose FLOP are counted under the same conventions for the work
+that algorithm does.
 """
 from __future__ import annotations
 
@@ -79,6 +83,50 @@ def contract_round_flops(ra, rb, d, dj, ranks_out, mpo=True):
     return f
 
 
+def zipup_flops(ra, rb, d, dj, ranks_out, ncores, mpo=True):
+    """Algorithmic FLOP of the decomposition (zip-up) path under the same
+    conventions: right-to-left QR sweeps of both operands (Householder QR of
+    the transposed unfoldings, explicit Q, R^T into the left neighbour), the
+    factored bond products S C_k, and per split of an m x c super-core the
+    nominal SVD of m x c, U Sigma = F V and the Q application."""
+    n = len(d)
+    Pa = [d[k] * dj[k] for k in range(n)] if mpo else list(d)
+    Pb = list(dj) if mpo else list(d)
+    f = 0.0
+
+    def right(r, P):
+        nonlocal f
+        rho = [1] * (n + 1)
+        for k in range(n - 1, 0, -1):
+            m, c = P[k] * rho[k + 1], r[k]
+            q = min(m, c)
+            rho[k] = q
+            f += geqrf_flops(m, c) + ormqr_flops(m, q, q) + 2.0 * r[k - 1] * P[k - 1] * q * c
+        return rho
+
+    sa, sb = right(ra, Pa), right(rb, Pb)
+    N = min(ncores, n)
+    r, Pleg, legs, outc = 1, 1, 0, 0
+    for k in range(n):
+        rho0 = r * Pleg
+        f += 2.0 * (rho0 * sa[k]) * (dj[k] * sb[k + 1]) * sb[k]
+        f += 2.0 * (rho0 * d[k]) * (sa[k + 1] * sb[k + 1]) * (sa[k] * (dj[k] if mpo else 1))
+        Pleg *= d[k]
+        rcs = sa[k + 1] * sb[k + 1]
+        legs += 1
+        while (legs == N and k < n - 1) or (k == n - 1 and legs > 1):
+            db = d[outc]
+            m, c = r * db, (Pleg // db) * rcs
+            rn = ranks_out[outc + 1]
+            p = min(m, c)
+            f += svd_nominal_flops(m, c) + 2.0 * p * rn * m
+            if c >= m:
+                f += ormqr_flops(c, p, rn)
+            outc += 1
+            r, Pleg, legs = rn, Pleg // db, legs - 1
+    return f
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,8 +139,12 @@ def main():
                     help="skip the per-class profiled steps (and the roofline object)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the measurement, run one plain device copy of this many MiB")
-    ap.add_argument("--workload", default="laplacian3d_n42_r256", choices=["laplacian3d_n42_r256", "hadamard_batch"],
-                    help="hadamard_batch: the batched form (512 uneven 1D Hadamard products, one graph launch)")
+    ap.add_argument("--workload", default="laplacian3d_n42_r256",
+                    choices=["laplacian3d_n42_r256", "laplacian3d_n42_r256_zipup", "hadamard_batch"],
+                    help="hadamard_batch: the batched form (512 uneven 1D Hadamard products, one graph launch); "
+                         "laplacian3d_n42_r256_zipup: the same product by the decomposition (zip-up) algorithm")
+    ap.add_argument("--ncores", type=int, default=2, choices=[1, 2],
+                    help="zip-up super-core size (exact product cores per split)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the single-chain rounding "
@@ -109,6 +161,7 @@ def main():
     dev = "cuda:0"
     if args.workload == "hadamard_batch":
         return bench_batch(args, I, Q, torch, dev)
+    zipup = args.workload.endswith("_zipup")
     w = I.laplacian3d_r256()
     A = Q.to_device(w.a, dev)
     B = Q.to_device(w.b, dev)
@@ -116,23 +169,26 @@ def main():
     rb = [1] + [c.shape[-1] for c in w.b]
     d = [c.shape[1] for c in w.a]
     dj = [c.shape[2] for c in w.a]
-    bnd = Q.rank_bounds([x * y for x, y in zip(ra, rb)], d, w.max_rank)
-    outs = [torch.empty(bnd[k] * d[k] * bnd[k + 1], dtype=torch.float64, device=dev) for k in range(len(d))]
-    ws = None
-
-    def step(prec):
-        nonlocal ws
-        res = Q.contract_round(w.spec, A, B, w.rel_tol, w.max_rank, prec=prec, out_buffers=outs, workspace=ws)
-        return res
-
-    # workspace allocated once, outside the timed region
     L = Q.load_library()
     import ctypes as C
     va, vb = Q.TTView(A, 2), Q.TTView(B, 1)
-    nb = C.c_size_t()
-    Q._check(L.qtt_workspace_size(None, Q.OP_CONTRACT_ROUND, w.spec.encode(), C.byref(va.struct),
-                                  C.byref(vb.struct), w.max_rank, Q.PREC[args.prec], C.byref(nb)), "ws")
-    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    if zipup:
+        bnd, nbytes = Q.zipup_query(w.spec, va.struct, vb.struct, w.max_rank, args.ncores)
+    else:
+        bnd = Q.rank_bounds([x * y for x, y in zip(ra, rb)], d, w.max_rank)
+        nb = C.c_size_t()
+        Q._check(L.qtt_workspace_size(None, Q.OP_CONTRACT_ROUND, w.spec.encode(), C.byref(va.struct),
+                                      C.byref(vb.struct), w.max_rank, Q.PREC[args.prec], C.byref(nb)), "ws")
+        nbytes = nb.value
+    # output cores and workspace allocated once, outside the timed region
+    outs = [torch.empty(bnd[k] * d[k] * bnd[k + 1], dtype=torch.float64, device=dev) for k in range(len(d))]
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+    def step(prec):
+        if zipup:
+            return Q.contract_zipup(w.spec, A, B, w.rel_tol, w.max_rank, ncores=args.ncores, prec=prec,
+                                    out_buffers=outs, workspace=ws)
+        return Q.contract_round(w.spec, A, B, w.rel_tol, w.max_rank, prec=prec, out_buffers=outs, workspace=ws)
 
     def timed(prec, steps, warmup):
         res = None
@@ -146,9 +202,15 @@ def main():
         return (time.perf_counter() - t0) / steps, res
 
     sec, res = timed(args.prec, args.steps, args.warmup)
-    flops = contract_round_flops(ra, rb, d, dj, res.ranks)
+    if zipup:
+        flops = zipup_flops(ra, rb, d, dj, res.ranks, args.ncores)
+        metric = ("QTT contract+truncate by zip-up TFLOP/s (3D Laplacian MPO x rank-256 MPS, n=42, "
+                  "truncated to rank 256 at 1e-8)")
+    else:
+        flops = contract_round_flops(ra, rb, d, dj, res.ranks)
+        metric = "QTT contract+round TFLOP/s (3D Laplacian MPO x rank-256 MPS, n=42, round to rank 256 at 1e-8)"
     out = {
-        "metric": "QTT contract+round TFLOP/s (3D Laplacian MPO x rank-256 MPS, n=42, round to rank 256 at 1e-8)",
+        "metric": metric,
         "value": flops / sec / 1e12,
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -160,7 +222,7 @@ def main():
         "vs_baseline": None,
         "dtype": f"{args.prec}+f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "cores": len(d), "mps_rank": 256, "mpo_rank": 7, "max_rank": w.max_rank,
+        "config": {"workload": args.workload, "cores": len(d), "mps_rank": 256, "mpo_rank": 7, "max_rank": w.max_rank,
                    "rel_tol": w.rel_tol, "gemm": args.prec, "factorisations": "fp64"},
         "algorithmic_gflop_per_step": flops / 1e9,
         "ranks_out_max": max(res.ranks),
@@ -207,7 +269,7 @@ def main():
         del src_t, dst_t
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, ra, rb, d, dj)
+        out["cpu_baseline"] = cpu_baseline(w, ra, rb, d, dj, args.ncores if zipup else 0)
     print(json.dumps(out), flush=True)
 
 
@@ -312,8 +374,9 @@ def measured_traffic(kernel, alg_bytes_per_launch):
     return rec["ratio"] * alg_bytes_per_launch
 
 
-def cpu_baseline(w, ra, rb, d, dj):
-    """The FP64 oracle (NumPy + LAPACK) on this host's cores: one full contract+round."""
+def cpu_baseline(w, ra, rb, d, dj, zipup_ncores=0):
+    """The FP64 oracle (NumPy + LAPACK) on this host's cores: one full
+    contract+round (or zip-up with super-cores of zipup_ncores cores)."""
     import oracle as O
     try:
         from threadpoolctl import threadpool_info
@@ -321,12 +384,19 @@ def cpu_baseline(w, ra, rb, d, dj):
     except Exception:
         threads = os.cpu_count() or 1
     t0 = time.perf_counter()
-    C = O.contract(w.spec, w.a, w.b)
-    Y, info = O.round_tt(C, w.rel_tol, w.max_rank, return_info=True)
-    dt = time.perf_counter() - t0
-    flops = contract_round_flops(ra, rb, d, dj, info.ranks)
+    if zipup_ncores:
+        Y, info = O.zipup(w.spec, w.a, w.b, w.rel_tol, w.max_rank, ncores=zipup_ncores, return_info=True)
+        dt = time.perf_counter() - t0
+        flops = zipup_flops(ra, rb, d, dj, info.ranks, zipup_ncores)
+        what = f"one full zip-up (super-cores of {zipup_ncores})"
+    else:
+        C = O.contract(w.spec, w.a, w.b)
+        Y, info = O.round_tt(C, w.rel_tol, w.max_rank, return_info=True)
+        dt = time.perf_counter() - t0
+        flops = contract_round_flops(ra, rb, d, dj, info.ranks)
+        what = "one full contract+round"
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": "one full contract+round of the same 42-core workload (NumPy FP64, LAPACK QR/SVD)",
+            "sample": f"{what} of the same 42-core workload (NumPy FP64, LAPACK QR/SVD)",
             "seconds": dt}
 
 

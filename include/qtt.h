@@ -142,6 +142,36 @@ int qtt_contract_round(qtt_handle h, const char *spec, const qtt_tt *a, const qt
                        double rel_tol, int64_t max_rank, int prec, qtt_round_info *info,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* Decomposition ("zip-up") algorithm of Sec. 3.2 for the same products:
+ * copies of both operands are first normalised to the left end (a
+ * right-to-left QR sweep, cores 2..n right-orthonormal); a super-core of
+ * `ncores` (1 or 2) exact product cores then grows from the left by one
+ * bond product S C_k at a time, and whenever it holds ncores cores (and,
+ * after the last core, until one remains) its (r d) x (rest) unfolding is
+ * split by a truncated one-sided Jacobi SVD: U_r becomes the next result
+ * core (left-orthonormal) and Sig_r V_r^T the new super-core.  The kept rank
+ * follows qtt_round's rule with delta = rel_tol * ||S||_F / sqrt(n-1), S the
+ * super-core being split (the paper's reading of S as the whole result's
+ * norm holds only when the exact right part of the product is orthonormal);
+ * the contracted train is never formed and never QR-factored as a whole.
+ * The result is an approximation whose error is not bounded by
+ * info->err_bound in general; its ranks can exceed those of qtt_round.
+ * out: FP64 MPS with caller-allocated cores of at least the bounds that
+ * qtt_zipup_query returns; its ranks are written on return.  info->norm and
+ * info->delta refer to the first split; tail/margins/sigma per bond as for
+ * qtt_round.  FP64 operands; prec selects the bond-product arithmetic.
+ * Limits: (r d) <= 1024 at every split, operand unfoldings <= 4096 rows.
+ * Synchronous. */
+int qtt_contract_zipup(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qtt_tt *out,
+                       double rel_tol, int64_t max_rank, int32_t ncores, int prec,
+                       qtt_round_info *info, void *ws, size_t ws_bytes, void *stream);
+
+/* Shape query of qtt_contract_zipup: per-bond rank bounds of the result
+ * (n+1 entries, nullable) and the device workspace in bytes (nullable).
+ * Pure shape arithmetic; core pointers are not dereferenced. */
+int qtt_zipup_query(const char *spec, const qtt_tt *a, const qtt_tt *b, int64_t max_rank, int32_t ncores,
+                    int64_t *bounds, size_t *ws_bytes);
+
 /* <a, b> = E_n, E_0 = [[1]], E_k = sum_i a_k(i)^T E_{k-1} b_k(i) (the <C|C>
  * contractions of Sec. 3.3).  MPS operands of equal length and physical
  * sizes, FP64 or FP32 (accumulated in the storage type).  Synchronous. */

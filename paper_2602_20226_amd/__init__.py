@@ -10,6 +10,7 @@ from .qtt import (  # noqa: F401
     contract,
     contract_backward,
     contract_round,
+    contract_zipup,
     inner,
     inner_backward,
     load_library,

@@ -32,7 +32,11 @@ struct qtt_context {
 
 namespace {
 
-constexpr int kMaxSweeps = 40;
+// Jacobi sweep cap.  Full-rank inputs converge in 10-15 sweeps; inputs with
+// exactly null directions (structurally rank-deficient super-cores of the
+// decomposition algorithm) need up to about 40, since the rows that collapse
+// to rounding level are made orthogonal only after the others have settled.
+constexpr int kMaxSweeps = 80;
 constexpr int kMaxRows = 4096;
 
 #define QTT_HIP(call)                          \
@@ -753,6 +757,307 @@ hipError_t batch_run(qtt_batch* p, hipStream_t s, int variant) {
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------- decomposition (zip-up)
+// Sec. 3.2: both operands move their normalisation centre to the left end;
+// a super-core of N exact product cores then grows one product core at a
+// time and is split off one truncated-SVD core whenever it holds N cores.
+struct ZipPlan {
+  int N = 1;
+  std::vector<long> ra, rb;       // operand ranks after the right-to-left sweep
+  std::vector<long> Pa, Pb;       // physical size per core (all legs)
+  std::vector<long> offA, offB;   // operand copies
+  std::vector<long> bound;        // result rank bounds (n+1)
+  long offG = 0, offTq = 0, offQe = 0, offRr = 0, offTmp = 0;
+  long offS = 0, offT = 0, offY = 0, offBt = 0, offTB = 0, offX = 0, offXc = 0, offYn = 0, offV = 0;
+  long offSig = 0, offPerm = 0, offTrunc = 0, offCtr = 0, offSweeps = 0, offOne = 0, offNrm = 0, offScr = 0;
+  long total = 0;
+};
+
+int make_zip_plan(const Shape& s, const qtt_tt* a, const qtt_tt* b, long max_rank, int ncores, ZipPlan& Z) {
+  if (ncores < 1 || ncores > 2) return QTT_ERR_UNSUPPORTED;
+  const int n = s.n;
+  Z.N = std::min(ncores, n);
+  Z.Pa.assign(n, 1);
+  Z.Pb.assign(n, 1);
+  for (int k = 0; k < n; ++k) {
+    for (int l = 0; l < a->legs; ++l) Z.Pa[k] *= a->phys[k * a->legs + l];
+    Z.Pb[k] = b->phys[k];
+  }
+  long off = 0;
+  auto take = [&](long cnt) {
+    long o = off;
+    off += round_up(std::max(cnt, 1L), 32);
+    return o;
+  };
+  // right-to-left sweep ranks and its scratch
+  long maxG = 1, maxTq = 1, maxQe = 1, maxRr = 1, maxTmp = 1, maxScrCols = 1;
+  auto right_ranks = [&](const std::vector<long>& r, const std::vector<long>& P, std::vector<long>& rho) {
+    rho.assign(n + 1, 1);
+    for (int k = n - 1; k >= 1; --k) {
+      const long m = P[k] * rho[k + 1], c = r[k];
+      if (m > kMaxRows) return QTT_ERR_UNSUPPORTED;
+      rho[k] = std::min(m, c);
+      maxG = std::max(maxG, m * c);
+      maxTq = std::max(maxTq, qr_t_doubles((int)m, (int)c));
+      maxQe = std::max(maxQe, m * rho[k]);
+      maxRr = std::max(maxRr, rho[k] * c);
+      maxTmp = std::max(maxTmp, r[k - 1] * P[k - 1] * rho[k]);
+      maxScrCols = std::max(maxScrCols, c);
+    }
+    return QTT_OK;
+  };
+  int st;
+  if ((st = right_ranks(s.ra, Z.Pa, Z.ra))) return st;
+  if ((st = right_ranks(s.rb, Z.Pb, Z.rb))) return st;
+  Z.offA.assign(n, 0);
+  Z.offB.assign(n, 0);
+  for (int k = 0; k < n; ++k) {
+    Z.offA[k] = take(s.ra[k] * Z.Pa[k] * s.ra[k + 1]);
+    Z.offB[k] = take(s.rb[k] * Z.Pb[k] * s.rb[k + 1]);
+  }
+  // zip-up sizes, simulated with the rank bounds
+  Z.bound.assign(n + 1, 1);
+  long maxS = 1, maxY = 1, maxBt = 1, maxTB = 1, maxX = 1, maxYn = 1, maxV = 1, maxP = 1;
+  long r = 1, Pleg = 1, rcS = 1;
+  int legs = 0, outc = 0;
+  for (int k = 0; k < n; ++k) {
+    const long rho0 = r * Pleg;
+    const long dj = (s.kind == K_MPO) ? s.dj[k] : s.d[k];
+    const long rc1 = Z.ra[k + 1] * Z.rb[k + 1];
+    maxY = std::max(maxY, rho0 * Z.ra[k] * dj * Z.rb[k + 1]);
+    maxS = std::max(maxS, rho0 * s.d[k] * rc1);
+    Pleg *= s.d[k];
+    rcS = rc1;
+    ++legs;
+    while ((legs == Z.N && k < n - 1) || (k == n - 1 && legs > 1)) {
+      const long db = s.d[outc];
+      const long m = r * db, cols = (Pleg / db) * rcS;
+      if (m > 1024) return QTT_ERR_UNSUPPORTED;  // Jacobi row length
+      long p;
+      if (cols >= m) {
+        if (cols > kMaxRows) return QTT_ERR_UNSUPPORTED;
+        maxBt = std::max(maxBt, cols * m);
+        maxTB = std::max(maxTB, qr_t_doubles((int)cols, (int)m));
+        maxX = std::max(maxX, m * m);
+        p = m;
+      } else {
+        maxX = std::max(maxX, cols * m);
+        p = cols;
+      }
+      long rn = p;
+      if (max_rank > 0) rn = std::min(rn, max_rank);
+      maxYn = std::max(maxYn, cols * rn);
+      maxV = std::max(maxV, rn * m);
+      maxP = std::max(maxP, p);
+      maxScrCols = std::max(maxScrCols, m);
+      Z.bound[++outc] = rn;
+      r = rn;
+      Pleg /= db;
+      --legs;
+    }
+  }
+  Z.offG = take(maxG);
+  Z.offTq = take(maxTq);
+  Z.offQe = take(maxQe);
+  Z.offRr = take(maxRr);
+  Z.offTmp = take(maxTmp);
+  Z.offS = take(maxS);
+  Z.offT = take(maxS);
+  Z.offY = take(maxY);
+  Z.offBt = take(maxBt);
+  Z.offTB = take(maxTB);
+  Z.offX = take(maxX);
+  Z.offXc = take(maxX);
+  Z.offYn = take(maxYn);
+  Z.offV = take(maxV);
+  Z.offSig = take(maxP);
+  Z.offPerm = take(maxP / 2 + 1);
+  Z.offTrunc = take(8);
+  Z.offCtr = take(96);
+  Z.offSweeps = take(1);
+  Z.offOne = take(1);
+  Z.offNrm = take(1);
+  Z.offScr = take(qr_scratch_doubles(maxScrCols));
+  Z.total = off;
+  return QTT_OK;
+}
+
+// Right-to-left QR sweep on an operand copy held in the workspace: core k
+// (r_k x P_k r'_{k+1}) is replaced by Q^T from G^T = Q R and R^T moves into
+// core k-1.  r holds the original ranks, rho the ranks after the sweep.
+int right_sweep(hipStream_t st, double* ws, const ZipPlan& Z, const std::vector<long>& off,
+                const std::vector<long>& r, const std::vector<long>& P, const std::vector<long>& rho, int n) {
+  double* G = ws + Z.offG;
+  double* Tq = ws + Z.offTq;
+  double* Qe = ws + Z.offQe;
+  double* Rr = ws + Z.offRr;
+  double* Tmp = ws + Z.offTmp;
+  double* scr = ws + Z.offScr;
+  for (int k = n - 1; k >= 1; --k) {
+    const int m = (int)(P[k] * rho[k + 1]), c = (int)r[k], q = (int)rho[k];
+    double* core = ws + off[k];
+    QTT_HIP(transpose(st, core, c, m, m, G, c));  // G^T: m x c
+    QTT_HIP(householder_qr(st, G, m, c, c, Tq, scr));
+    QTT_HIP(extract_r(st, G, q, c, c, Rr));  // q x c
+    QTT_HIP(set_eye_rect(st, Qe, m, q));
+    QTT_HIP(apply_q(st, G, m, q, c, Tq, Qe, q, q, false, scr));
+    QTT_HIP(transpose(st, Qe, m, q, q, core, m));  // core k = Q^T: q x m
+    // core k-1 <- core k-1 R^T: (r_{k-1} P_{k-1}) x q
+    double* prev = ws + off[k - 1];
+    const int rows = (int)(r[k - 1] * P[k - 1]);
+    QTT_HIP(gemm_f64(st, false, true, rows, q, c, 1.0, prev, c, 0, Rr, c, 0, 0.0, Tmp, q, 0, 1));
+    QTT_HIP(copy_pad_rows(st, Tmp, rows, q, q, prev, rows, q));
+  }
+  return QTT_OK;
+}
+
+// The zip-up proper on right-normalised operand copies; result cores go to out.
+int zip_sweep(qtt_context* h, hipStream_t st, double* ws, const Shape& s, const ZipPlan& Z, int prec, double rel_tol,
+              long max_rank, qtt_tt* out, qtt_round_info* info, std::vector<long>& newr) {
+  const int n = s.n;
+  double* S = ws + Z.offS;
+  double* T = ws + Z.offT;
+  double* Yb = ws + Z.offY;
+  double* Bt = ws + Z.offBt;
+  double* TB = ws + Z.offTB;
+  double* X = ws + Z.offX;
+  double* Xc = ws + Z.offXc;
+  double* Yn = ws + Z.offYn;
+  double* V = ws + Z.offV;
+  double* sig = ws + Z.offSig;
+  int* perm = (int*)(ws + Z.offPerm);
+  TruncOut* tr = (TruncOut*)(ws + Z.offTrunc);
+  unsigned* ctr = (unsigned*)(ws + Z.offCtr);
+  int* sweeps = (int*)(ws + Z.offSweeps);
+  double* nrm = ws + Z.offNrm;
+  double* scr = ws + Z.offScr;
+  newr.assign(n + 1, 1);
+  QTT_HIP(fill_f64(st, S, 1.0, 1));
+  long r = 1, Pleg = 1, rcS = 1;
+  int legs = 0, outc = 0;
+  double err2 = 0.0, first_norm = 0.0, first_delta = 0.0;
+  int maxsw = 0;
+  for (int k = 0; k < n; ++k) {
+    // T = S C_k from the operand cores: (S X_k) then the operator / Hadamard factor
+    const long rho0 = r * Pleg;
+    const long ra0 = Z.ra[k], ra1 = Z.ra[k + 1], rb0 = Z.rb[k], rb1 = Z.rb[k + 1];
+    const long dj = (s.kind == K_MPO) ? s.dj[k] : s.d[k];
+    const double* Ak = ws + Z.offA[k];
+    const double* Bk = ws + Z.offB[k];
+    QTT_HIP(bond_gemm(st, prec, (int)(rho0 * ra0), (int)(dj * rb1), (int)rb0, S, rb0, Bk, dj * rb1, Yb, dj * rb1));
+    if (s.kind == K_MPO)
+      QTT_HIP(bond_mpo_apply(st, Yb, (int)rho0, (int)ra0, (int)dj, (int)rb1, Ak, s.d[k], (int)ra1, T));
+    else
+      QTT_HIP(bond_hadamard_apply(st, Yb, (int)rho0, (int)ra0, s.d[k], (int)rb1, Ak, (int)ra1, T));
+    std::swap(S, T);
+    Pleg *= s.d[k];
+    rcS = ra1 * rb1;
+    ++legs;
+    while ((legs == Z.N && k < n - 1) || (k == n - 1 && legs > 1)) {
+      const long db = s.d[outc];
+      const int m = (int)(r * db), cols = (int)((Pleg / db) * rcS);
+      // SVD of S (m x cols) through its transpose B = S^T: Jacobi on the rows
+      // of F = R (QR of a tall B) or of B itself; U_S = V_B, Sig V_S^T = (B V_B)^T.
+      const bool tall = cols >= m;
+      const int L = m;
+      int p;
+      if (tall) {
+        QTT_HIP(transpose(st, S, m, cols, cols, Bt, m));
+        QTT_HIP(householder_qr(st, Bt, cols, m, m, TB, scr));
+        QTT_HIP(extract_r(st, Bt, m, m, m, X));
+        p = m;
+      } else {
+        QTT_HIP(transpose(st, S, m, cols, cols, X, m));
+        p = cols;
+      }
+      QTT_HIP(copy_pad_rows(st, X, p, L, L, Xc, p, L));
+      QTT_HIP(row_norms_sorted(st, Xc, p, L, sig, perm));
+      QTT_HIP(permute_rows(st, Xc, p, L, perm, X));
+      QTT_HIP(jacobi_rows(st, X, p, L, ctr, kMaxSweeps, sweeps));
+      QTT_HIP(row_norms_sorted(st, X, p, L, sig, perm));
+      QTT_HIP(frob_norm(st, sig, p, nrm));  // ||S||_F of the super-core being split
+      QTT_HIP(truncate_decide(st, sig, p, nrm, rel_tol, n - 1, max_rank, tr));
+      QTT_HIP(hipMemcpyAsync(h->pin_int, sweeps, sizeof(int), hipMemcpyDeviceToHost, st));
+      int e = readback(h, st, tr, sizeof(TruncOut), h->pin_trunc);
+      if (e) return e;
+      const TruncOut t = *h->pin_trunc;
+      const int swp = *h->pin_int;
+      if (!std::isfinite(t.norm)) return QTT_ERR_NONFINITE;
+      if (swp >= kMaxSweeps) return QTT_ERR_NOCONV;
+      {
+        double jb = 0.0, jf = 0.0;
+        jacobi_sweep_cost(p, L, &jb, &jf);
+        prof::amend(prof::JACOBI, swp * jb, swp * jf);
+      }
+      maxsw = std::max(maxsw, swp);
+      const int rn = t.rank;
+      if (outc == 0) {
+        first_norm = t.norm;
+        first_delta = t.delta;
+      }
+      if (info) {
+        const int bnd = outc;
+        if (info->tail) info->tail[bnd] = t.tail_r;
+        if (info->margin_lo) info->margin_lo[bnd] = t.delta > 0 ? t.tail_rm1 / t.delta : INFINITY;
+        if (info->margin_hi) info->margin_hi[bnd] = t.delta > 0 ? t.tail_r / t.delta : 0.0;
+        if (info->maxrank_hit) info->maxrank_hit[bnd] = (uint8_t)t.capped;
+        if (info->sigma && info->sigma_ld > 0) {
+          const long cnt = std::min<long>(p, info->sigma_ld);
+          QTT_HIP(hipMemcpyAsync(info->sigma + (long)bnd * info->sigma_ld, sig, cnt * sizeof(double),
+                                 hipMemcpyDeviceToHost, st));
+          QTT_HIP(hipStreamSynchronize(st));
+          for (long i = cnt; i < info->sigma_ld; ++i) info->sigma[(long)bnd * info->sigma_ld + i] = 0.0;
+        }
+      }
+      err2 += t.tail_r * t.tail_r;
+      // result core = V_B,r (m x rn): rows perm[:rn] of X normalised, transposed
+      QTT_HIP(gather_rows_normalized(st, X, L, perm, sig, tr, V, L, rn));
+      QTT_HIP(transpose(st, V, rn, m, m, (double*)out->cores[outc], rn));
+      // Yn = B V_r (cols x rn); tall B = Q_B R  =>  Q_B [R V_r; 0]
+      QTT_HIP(gemm_f64(st, false, true, p, rn, L, 1.0, Xc, L, 0, V, L, 0, 0.0, Yn, rn, 0, 1));
+      if (tall) {
+        if (cols > p) QTT_HIP(fill_f64(st, Yn + (long)p * rn, 0.0, (long)(cols - p) * rn));
+        QTT_HIP(apply_q(st, Bt, cols, p, m, TB, Yn, rn, rn, false, scr));
+      }
+      // remainder S = Yn^T (rn x cols) = Sig_r V_S,r^T
+      QTT_HIP(transpose(st, Yn, cols, rn, rn, S, cols));
+      newr[outc + 1] = rn;
+      ++outc;
+      r = rn;
+      Pleg /= db;
+      --legs;
+    }
+  }
+  // last core = the one-leg remainder (r x d x 1)
+  QTT_HIP(copy_pad_rows(st, S, (int)(r * s.d[n - 1]), 1, 1, (double*)out->cores[n - 1], (int)(r * s.d[n - 1]), 1));
+  if (n == 1) {
+    QTT_HIP(frob_norm(st, S, s.d[0], nrm));
+    int e = readback(h, st, nrm, sizeof(double), h->pin_dbl);
+    if (e) return e;
+    first_norm = h->pin_dbl[0];
+    if (!std::isfinite(first_norm)) return QTT_ERR_NONFINITE;
+  }
+  QTT_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->norm = first_norm;
+    info->delta = first_delta;
+    info->err_bound = std::sqrt(err2);
+    info->jacobi_sweeps_max = maxsw;
+  }
+  return QTT_OK;
+}
+
+int zip_setup(const char* spec, const qtt_tt* a, const qtt_tt* b, long max_rank, int ncores, Shape& s, ZipPlan& Z) {
+  int st = shape_from_pair(spec, a, b, s);
+  if (st) return st;
+  if (a->dtype != QTT_F64 || b->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  return make_zip_plan(s, a, b, max_rank, ncores, Z);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* qtt_status_string(int status) {
@@ -1264,5 +1569,53 @@ int qtt_batch_plan_destroy(qtt_batch_plan plan) {
   batch_free(plan);
   return QTT_OK;
 }
+
+int qtt_zipup_query(const char* spec, const qtt_tt* a, const qtt_tt* b, int64_t max_rank, int32_t ncores,
+                    int64_t* bounds, size_t* ws_bytes) {
+  Shape s;
+  ZipPlan Z;
+  int st = zip_setup(spec, a, b, max_rank, ncores, s, Z);
+  if (st) return st;
+  if (bounds)
+    for (int k = 0; k <= s.n; ++k) bounds[k] = Z.bound[k];
+  if (ws_bytes) *ws_bytes = (size_t)Z.total * sizeof(double) + 256;
+  return QTT_OK;
+}
+
+int qtt_contract_zipup(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* out,
+                       double rel_tol, int64_t max_rank, int32_t ncores, int prec, qtt_round_info* info, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (!h) return QTT_ERR_ARG;
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return QTT_ERR_ARG;
+  if (prec < QTT_GEMM_FP64 || prec > QTT_GEMM_BF16X6) return QTT_ERR_ARG;
+  Shape s;
+  ZipPlan Z;
+  int st = zip_setup(spec, a, b, max_rank, ncores, s, Z);
+  if (st) return st;
+  if (!out || !out->ranks || !out->cores || out->n != a->n || out->legs != 1) return QTT_ERR_ARG;
+  if (out->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  for (int k = 0; k < out->n; ++k)
+    if (!out->cores[k]) return QTT_ERR_ARG;
+  if (!ws || ws_bytes < (size_t)Z.total * sizeof(double) + 256) return QTT_ERR_WORKSPACE;
+  Scoped sc(h->device);
+  hipStream_t strm = (hipStream_t)stream;
+  double* w = align_ws(ws);
+  const int n = s.n;
+  for (int k = 0; k < n; ++k) {
+    QTT_HIP(hipMemcpyAsync(w + Z.offA[k], a->cores[k], (size_t)(s.ra[k] * Z.Pa[k] * s.ra[k + 1]) * sizeof(double),
+                           hipMemcpyDeviceToDevice, strm));
+    QTT_HIP(hipMemcpyAsync(w + Z.offB[k], b->cores[k], (size_t)(s.rb[k] * Z.Pb[k] * s.rb[k + 1]) * sizeof(double),
+                           hipMemcpyDeviceToDevice, strm));
+  }
+  if ((st = right_sweep(strm, w, Z, Z.offA, s.ra, Z.Pa, Z.ra, n))) return st;
+  if ((st = right_sweep(strm, w, Z, Z.offB, s.rb, Z.Pb, Z.rb, n))) return st;
+  std::vector<long> newr;
+  if ((st = zip_sweep(h, strm, w, s, Z, prec, rel_tol, max_rank, out, info, newr))) return st;
+  out->ranks[0] = 1;
+  out->ranks[n] = 1;
+  for (int k = 1; k < n; ++k) out->ranks[k] = newr[k];
+  return QTT_OK;
+}
+
 
 }  // extern "C"

@@ -33,7 +33,7 @@ EXPORTS = [
     "qtt_orthogonalize", "qtt_round", "qtt_contract_round", "qtt_inner", "qtt_inner_backward",
     "qtt_contract_backward", "qtt_profile_start", "qtt_profile_stop", "qtt_batch_workspace_size",
     "qtt_batch_plan_create", "qtt_batch_plan_launch", "qtt_batch_plan_results", "qtt_batch_plan_info",
-    "qtt_batch_plan_destroy",
+    "qtt_batch_plan_destroy", "qtt_contract_zipup", "qtt_zipup_query",
 ]
 
 
@@ -106,6 +106,9 @@ def load_library():
     L.qtt_batch_plan_results.argtypes = [vp, P(C.c_int64), P(C.c_double), vp]
     L.qtt_batch_plan_info.argtypes = [vp, P(C.c_int32), P(C.c_int32), P(C.c_float)]
     L.qtt_batch_plan_destroy.argtypes = [vp]
+    L.qtt_contract_zipup.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_double, C.c_int64, C.c_int32, C.c_int,
+                                     P(RoundInfoC), vp, C.c_size_t, vp]
+    L.qtt_zipup_query.argtypes = [C.c_char_p, P(TT), P(TT), C.c_int64, C.c_int32, P(C.c_int64), P(C.c_size_t)]
     L.qtt_profile_start.argtypes = [vp, C.c_int, C.c_int]
     L.qtt_profile_stop.argtypes = [vp, P(C.c_int64), P(C.c_double), P(C.c_double), P(C.c_double)]
     for name in EXPORTS:
@@ -391,6 +394,48 @@ def contract_round(spec: str, a, b, rel_tol: float, max_rank: int = 0, prec: str
     ranks = vo.ranks()
     cores = _views_of_compact(out_buffers, ranks, d)
     return info.result(cores, ranks, n)
+
+
+def zipup_query(spec: str, a_struct: TT, b_struct: TT, max_rank: int = 0, ncores: int = 1):
+    """(rank bounds of the zip-up result, workspace bytes) from the shapes alone."""
+    L = load_library()
+    n = a_struct.n
+    bounds = (C.c_int64 * (n + 1))()
+    nb = C.c_size_t()
+    _check(L.qtt_zipup_query(spec.encode(), C.byref(a_struct), C.byref(b_struct), int(max_rank), int(ncores),
+                             bounds, C.byref(nb)), "qtt_zipup_query")
+    return [int(bounds[k]) for k in range(n + 1)], nb.value
+
+
+def contract_zipup(spec: str, a, b, rel_tol: float, max_rank: int = 0, ncores: int = 1, prec: str = "fp64",
+                   want_sigmas: bool = False, out_buffers: Optional[List[torch.Tensor]] = None,
+                   workspace: Optional[torch.Tensor] = None) -> RoundResult:
+    """Contraction by the decomposition (zip-up) algorithm: operands normalised
+    to the left end, super-cores of `ncores` product cores split off one
+    truncated SVD at a time; the contracted train is never formed."""
+    L = load_library()
+    h = handle(a[0].device.index)
+    legs = _legs(spec)
+    va, vb = TTView(list(a), legs), TTView(list(b), 1)
+    n = len(a)
+    d = [c.shape[1] for c in a]
+    bnd, nbytes = zipup_query(spec, va.struct, vb.struct, max_rank, ncores)
+    dev = a[0].device
+    if out_buffers is None:
+        out_buffers = [torch.empty(bnd[k] * d[k] * bnd[k + 1], dtype=torch.float64, device=dev) for k in range(n)]
+    vo = TTView([x.reshape(-1) for x in out_buffers], 1, ranks_override=bnd, phys_override=d)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = _workspace(nbytes, dev)
+    sig_ld = 0
+    if want_sigmas:
+        sig_ld = max(bnd) * max(d)  # singular values per split <= r d
+    info = _Info(n, sig_ld)
+    _check(L.qtt_contract_zipup(h.ptr, spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(vo.struct),
+                                float(rel_tol), int(max_rank), int(ncores), PREC[prec], C.byref(info.c),
+                                C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr()),
+           "qtt_contract_zipup")
+    ranks = vo.ranks()
+    return info.result(_views_of_compact(out_buffers, ranks, d), ranks, n)
 
 
 def round_tt(cores, rel_tol: float, max_rank: int = 0, prec: str = "fp64", want_sigmas: bool = False,

@@ -134,3 +134,46 @@ def test_orthogonalisation_plans_the_largest_unfolding():
     n2 = 26
     too_tall = _fake_tt([min(2 ** k, 4096, 2 ** (n2 - k)) for k in range(n2 + 1)], [2] * n2)  # 8192-row unfolding
     assert ws(Q.OP_ORTHOGONALIZE, too_tall)[0] == -10
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_zipup_query_bounds_equal_untruncated_oracle_ranks(N):
+    """Untruncated zip-up of random operands keeps every singular value, so its
+    ranks equal the planned bounds exactly."""
+    import numpy as np
+    import oracle as O
+    rng = np.random.default_rng(50 + N)
+    rx = [1, 2, 4, 8, 8, 8, 8, 4, 2, 1]
+    rw = [1, 3, 5, 5, 5, 5, 5, 5, 3, 1]
+    X = [rng.standard_normal((rx[k], 2, rx[k + 1])) for k in range(9)]
+    W = [rng.standard_normal((rw[k], 2, 2, rw[k + 1])) for k in range(9)]
+    _, info = O.zipup("ij,j->i", W, X, 0.0, ncores=N, return_info=True)
+    a = _fake_tt(rw, [2] * 18, legs=2)
+    b = _fake_tt(rx, [2] * 9)
+    bnd, nb = Q.zipup_query("ij,j->i", a, b, 0, N)
+    assert bnd == info.ranks
+    assert nb > 0
+    bnd5, _ = Q.zipup_query("ij,j->i", a, b, 5, N)
+    assert max(bnd5) <= 5 and all(x <= y for x, y in zip(bnd5, bnd))
+
+
+def test_zipup_query_errors_and_benchmark_shape():
+    L = Q.load_library()
+    a = _fake_tt([1, 2, 1], [2, 2, 2, 2], legs=2)
+    b = _fake_tt([1, 2, 1], [2, 2])
+    nb = C.c_size_t()
+    assert L.qtt_zipup_query(b"ij,j->i", C.byref(a), C.byref(b), 0, 3, None, C.byref(nb)) == -10
+    assert L.qtt_zipup_query(b"ij,j->i", C.byref(a), C.byref(a), 0, 1, None, C.byref(nb)) == -3
+    assert L.qtt_zipup_query(b"ij->i", C.byref(a), C.byref(b), 0, 1, None, C.byref(nb)) == -2
+    assert L.qtt_contract_zipup(None, b"ij,j->i", C.byref(a), C.byref(b), C.byref(b), 1e-8, 0, 1, 0, None,
+                                None, 0, None) == -1
+    # 3D Laplacian (rank 7) x rank-256 MPS, n = 42: splits up to 512 x 3584
+    n = 42
+    rx = [min(256, 2 ** k, 2 ** (n - k)) for k in range(n + 1)]
+    rw = [1] + [7] * (n - 1) + [1]
+    a = _fake_tt(rw, [2] * (2 * n), legs=2)
+    b = _fake_tt(rx, [2] * n)
+    for N in (1, 2):
+        bnd, nbytes = Q.zipup_query("ij,j->i", a, b, 256, N)
+        assert max(bnd) == 256 and bnd[0] == bnd[-1] == 1
+        assert nbytes < 2 * 1024 ** 3
