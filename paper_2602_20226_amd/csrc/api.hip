@@ -157,9 +157,12 @@ int make_plan(const Shape& s, long max_rank, Plan& P, bool svd = true) {
     // Q_k [Y; 0] lives in Z: m_k x r''_{k+1}  (for k = n-1 the centre is used)
     if (k < n - 1) maxZ = std::max(maxZ, P.m[k] * rr[k + 1]);
     maxZ = std::max(maxZ, rows * D);
+    // D is a bound: the actual d r''_{k+1} can be smaller, which turns a
+    // wide B tall (QR of rows x D', D' <= rows), so the QR factor is sized
+    // for min(rows, D) whichever branch the bound takes.
+    maxTB = std::max(maxTB, qr_t_doubles((int)rows, (int)std::min(rows, D)));
     if (rows >= D) {
       maxX = std::max(maxX, D * D);
-      maxTB = std::max(maxTB, qr_t_doubles((int)rows, (int)D));
       maxP = std::max(maxP, D);
     } else {
       maxX = std::max(maxX, rows * D);
@@ -835,17 +838,16 @@ int make_zip_plan(const Shape& s, const qtt_tt* a, const qtt_tt* b, long max_ran
       const long db = s.d[outc];
       const long m = r * db, cols = (Pleg / db) * rcS;
       if (m > 1024) return QTT_ERR_UNSUPPORTED;  // Jacobi row length
-      long p;
-      if (cols >= m) {
-        if (cols > kMaxRows) return QTT_ERR_UNSUPPORTED;
-        maxBt = std::max(maxBt, cols * m);
-        maxTB = std::max(maxTB, qr_t_doubles((int)cols, (int)m));
-        maxX = std::max(maxX, m * m);
-        p = m;
-      } else {
-        maxX = std::max(maxX, cols * m);
-        p = cols;
-      }
+      // r is a bound: with a smaller kept rank the split can take the tall
+      // branch (QR of the cols x m' transpose, m' <= min(m, cols)) even where
+      // the bound takes the wide one, so both branches are sized.
+      if (cols > kMaxRows) return QTT_ERR_UNSUPPORTED;
+      const long mt = std::min(m, cols);
+      maxBt = std::max(maxBt, cols * mt);
+      maxTB = std::max(maxTB, qr_t_doubles((int)cols, (int)mt));
+      maxX = std::max(maxX, mt * mt);
+      if (cols < m) maxX = std::max(maxX, cols * m);
+      const long p = mt;
       long rn = p;
       if (max_rank > 0) rn = std::min(rn, max_rank);
       maxYn = std::max(maxYn, cols * rn);
