@@ -15,6 +15,7 @@ import numpy as np
 __all__ = [
     "contract",
     "tt_add",
+    "tt_sum",
     "tt_scale",
     "orthogonalize",
     "orthogonalize_right",
@@ -52,6 +53,8 @@ def contract(spec: str, A: Sequence[np.ndarray], B: Sequence[np.ndarray]):
 
     'i,i->i':  C_k[(mu,nu), i, (mu',nu')] = A_k[mu,i,mu'] B_k[nu,i,nu']
     'ij,j->i': C_k[(mu,nu), i, (mu',nu')] = sum_j A_k[mu,i,j,mu'] B_k[nu,j,nu']
+    'ij,jk->ik': C_k[(mu,nu), i, k, (mu',nu')] = sum_j A_k[mu,i,j,mu'] B_k[nu,j,k,nu']
+                 (operator product, both operands MPOs)
     The flattened bond is xi = mu * r_B + nu (mu major), as in the flatten
     xi_q = overline{mu_q nu_q} of the paper.
     """
@@ -69,6 +72,11 @@ def contract(spec: str, A: Sequence[np.ndarray], B: Sequence[np.ndarray]):
             ra, di, dj, rb = a.shape
             rc, _, rd = b.shape
             out.append(c.reshape(ra * rc, di, rb * rd))
+        elif spec == "ij,jk->ik":
+            c = np.einsum("aijb,cjkd->acikbd", a, b)
+            ra, di, dj, rb = a.shape
+            rc, _, dk, rd = b.shape
+            out.append(c.reshape(ra * rc, di, dk, rb * rd))
         else:
             raise ValueError(f"unsupported spec {spec!r}")
     return out
@@ -99,6 +107,22 @@ def tt_add(X, Y, alpha: float = 1.0, beta: float = 1.0):
             c[:rx0, :, :rx1] = x
             c[rx0:, :, rx1:] = y
         out.append(c)
+    return out
+
+
+def tt_sum(terms, coeffs=None):
+    """sum_t c_t X_t as one exact TT (Sec. 3.1, addition of many trains).
+
+    The block structure of tt_add taken over all terms at once: the first
+    core is the row [c_1 X_1, c_2 X_2, ...], the last the column of the
+    terms' last cores, the middle cores block-diagonal in term order; it
+    equals folding tt_add from the left.
+    """
+    if coeffs is None:
+        coeffs = [1.0] * len(terms)
+    out = tt_scale(terms[0], coeffs[0])
+    for X, c in zip(terms[1:], coeffs[1:]):
+        out = tt_add(out, X, 1.0, c)
     return out
 
 
