@@ -21,6 +21,7 @@ __all__ = [
     "orthogonalize_right",
     "round_tt",
     "zipup",
+    "fit",
     "RoundInfo",
     "truncation_rank",
     "inner",
@@ -378,6 +379,62 @@ def zipup(spec: str, A, B, rel_tol: float, max_rank: int = 0, ncores: int = 1, r
     info.sigmas = sigs
     info.err_bound = math.sqrt(sum(t * t for t in tails))
     return (out, info) if return_info else out
+
+
+def _qr_pos(M):
+    """Reduced QR with diag(R) >= 0."""
+    Qm, R = np.linalg.qr(M, mode="reduced")
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    return Qm * s[None, :], R * s[:, None]
+
+
+def fit(spec: str, A, B, C0, nsweeps: int = 1):
+    """Variational fitting of C to the product Y = contract(spec, A, B)
+    (Sec. 3.3, eq. variational), one core at a time with the ranks of C.
+
+    With every core left of q left-orthonormal and every core right of q
+    right-orthonormal, the core that minimises ||C - Y|| is the derivative
+    d<C|Y>/dC_q^* = L_{q-1} Y_q R_{q+1}, where L and R are the left and right
+    environments of <C|Y> (Y's cores are contracted exactly).  The guess is
+    first orthogonalised from the left (centre at core n, as the
+    decomposition algorithm leaves it).  A sweep then updates the cores from
+    right to left -- each updated core except the first is replaced by Q^T
+    from a QR of its transposed unfolding, so that the centre moves left --
+    and back from left to right with a QR of each updated core except the
+    last.  Ranks never grow (a QR may shrink one).  Returns the cores.
+    """
+    Y = [_mat(c) for c in contract(spec, A, B)]
+    C, _ = orthogonalize(C0)
+    C = [_mat(c).copy() for c in C]
+    n = len(C)
+    one = np.ones((1, 1))
+    for _ in range(nsweeps):
+        L = [one]
+        for q in range(n - 1):
+            L.append(np.einsum("ab,aic,bid->cd", L[q], C[q], Y[q], optimize=True))
+        F = [None] * (n + 1)
+        F[n] = one
+        for q in range(n - 1, -1, -1):
+            P = np.einsum("ab,bid,cd->aic", L[q], Y[q], F[q + 1], optimize=True)
+            r0, d, r1 = P.shape
+            if q > 0:
+                Qm, _ = _qr_pos(P.reshape(r0, d * r1).T)
+                C[q] = Qm.T.reshape(Qm.shape[1], d, r1)
+            else:
+                C[q] = P
+            F[q] = np.einsum("aic,bid,cd->ab", C[q], Y[q], F[q + 1], optimize=True)
+        L = [one]
+        for q in range(n):
+            P = np.einsum("ab,bid,cd->aic", L[q], Y[q], F[q + 1], optimize=True)
+            r0, d, r1 = P.shape
+            if q < n - 1:
+                Qm, _ = _qr_pos(P.reshape(r0 * d, r1))
+                C[q] = Qm.reshape(r0, d, Qm.shape[1])
+            else:
+                C[q] = P
+            L.append(np.einsum("ab,aic,bid->cd", L[q], C[q], Y[q], optimize=True))
+    return C
 
 
 def bond_singular_values(X):
