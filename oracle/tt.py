@@ -97,16 +97,17 @@ def tt_add(X, Y, alpha: float = 1.0, beta: float = 1.0):
     out = []
     for k in range(n):
         x, y = X[k], Y[k]
-        rx0, d, rx1 = x.shape
-        ry0, _, ry1 = y.shape
+        rx0, rx1 = x.shape[0], x.shape[-1]
+        ry0, ry1 = y.shape[0], y.shape[-1]
+        mid = x.shape[1:-1]  # physical legs: one (MPS) or two (MPO)
         if k == 0:
-            c = np.concatenate([alpha * x, beta * y], axis=2)
+            c = np.concatenate([alpha * x, beta * y], axis=x.ndim - 1)
         elif k == n - 1:
             c = np.concatenate([x, y], axis=0)
         else:
-            c = np.zeros((rx0 + ry0, d, rx1 + ry1))
-            c[:rx0, :, :rx1] = x
-            c[rx0:, :, rx1:] = y
+            c = np.zeros((rx0 + ry0,) + mid + (rx1 + ry1,))
+            c[:rx0, ..., :rx1] = x
+            c[rx0:, ..., rx1:] = y
         out.append(c)
     return out
 

@@ -74,3 +74,12 @@ def test_laplacian_squared_against_dense():
     perm = O.interleaved_index(4, 2)  # train index (interleaved digits) -> grid index
     L = O.dense_laplacian(4, 2)[np.ix_(perm, perm)]
     np.testing.assert_array_equal(O.mpo_to_dense(P), L @ L)
+
+
+def test_tt_sum_of_operators_is_the_dense_matrix_sum():
+    rng = np.random.default_rng(73)
+    W1 = rand_mpo(rng, [1, 3, 2, 1], [2, 3, 2], [2, 2, 4])
+    W2 = rand_mpo(rng, [1, 2, 4, 1], [2, 3, 2], [2, 2, 4])
+    S = O.tt_sum([W1, W2], [2.0, -0.5])
+    np.testing.assert_allclose(O.mpo_to_dense(S), 2.0 * O.mpo_to_dense(W1) - 0.5 * O.mpo_to_dense(W2),
+                               rtol=0, atol=1e-13)
