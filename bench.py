@@ -83,6 +83,33 @@ def contract_round_flops(ra, rb, d, dj, ranks_out, mpo=True):
     return f
 
 
+def round_flops(ranks, d, ranks_out):
+    """Algorithmic FLOP of qtt_round on a train with bond ranks `ranks`
+    (same conventions): QR sweep (R C_k product, Householder QR of the
+    (rho d) x r unfolding), then the SVD sweep of contract_round_flops."""
+    n = len(d)
+    rho = [1] * (n + 1)
+    f = 0.0
+    for k in range(n - 1):
+        if k > 0:
+            f += 2.0 * rho[k] * ranks[k] * d[k] * ranks[k + 1]
+        f += geqrf_flops(rho[k] * d[k], ranks[k + 1])
+        rho[k + 1] = min(rho[k] * d[k], ranks[k + 1])
+    f += 2.0 * rho[n - 1] * ranks[n - 1] * d[n - 1]
+    rnext = 1
+    for k in range(n - 1, 0, -1):
+        rows = rho[k]
+        D = d[k] * rnext
+        if k < n - 1:
+            f += ormqr_flops(rho[k] * d[k], rho[k + 1], rnext)
+        f += svd_nominal_flops(rows, D)
+        r = ranks_out[k]
+        f += 2.0 * min(rows, D) * r * D
+        rnext = r
+    f += ormqr_flops(d[0], rho[1], rnext)
+    return f
+
+
 def zipup_flops(ra, rb, d, dj, ranks_out, ncores, mpo=True):
     """Algorithmic FLOP of the decomposition (zip-up) path under the same
     conventions: right-to-left QR sweeps of both operands (Householder QR of
@@ -140,7 +167,8 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the measurement, run one plain device copy of this many MiB")
     ap.add_argument("--workload", default="laplacian3d_n42_r256",
-                    choices=["laplacian3d_n42_r256", "laplacian3d_n42_r256_zipup", "hadamard_batch"],
+                    choices=["laplacian3d_n42_r256", "laplacian3d_n42_r256_zipup", "hadamard_batch",
+                             "sum4_n42_r128_round", "laplacian2d_n32_r64_zipup_fit"],
                     help="hadamard_batch: the batched form (512 uneven 1D Hadamard products, one graph launch); "
                          "laplacian3d_n42_r256_zipup: the same product by the decomposition (zip-up) algorithm")
     ap.add_argument("--ncores", type=int, default=2, choices=[1, 2],
@@ -161,6 +189,10 @@ def main():
     dev = "cuda:0"
     if args.workload == "hadamard_batch":
         return bench_batch(args, I, Q, torch, dev)
+    if args.workload == "sum4_n42_r128_round":
+        return bench_sum(args, I, Q, torch, dev)
+    if args.workload == "laplacian2d_n32_r64_zipup_fit":
+        return bench_fit(args, I, Q, torch, dev)
     zipup = args.workload.endswith("_zipup")
     w = I.laplacian3d_r256()
     A = Q.to_device(w.a, dev)
@@ -236,27 +268,7 @@ def main():
     # Per-class kernel time: one extra step per class with every launch of
     # that class bracketed by HIP events on its launch stream inside libqtt.
     # The roofline is reported for the class that takes the most time.
-    classes = {
-        # class: (bound, peak, unit, kernels, source file of the kernel)
-        "jacobi": ("alu", 78600.0, "GFLOP/s", "k_jacobi", "svd.hip"),
-        "qr_panel": ("alu", 78600.0, "GFLOP/s", "k_qr_panel", "qr.hip"),
-        "apply_panel": ("hbm", 8000.0, "GB/s", "k_apply1", "qr.hip"),
-        "block_vty": ("mfma", 78600.0, "GFLOP/s", "k_vty", "qr.hip"),
-        "block_upd": ("mfma", 78600.0, "GFLOP/s", "k_vupd", "qr.hip"),
-    }
-    kernels = {}
-    for cls, (bound, peak, unit, kname, src) in ({} if args.no_kernel_breakdown else classes).items():
-        Q.profile_start(cls, 20000)
-        step(args.prec)
-        launches, kms, kbytes, kflops = Q.profile_stop()
-        work = kbytes if bound == "hbm" else kflops
-        achieved = work / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
-        kernels[cls] = {
-            "kernel": kname, "bound": bound, "launches": launches, "ms_per_step": kms,
-            "avg_us": 1e3 * kms / max(launches, 1), "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "alg_bytes_per_launch": kbytes / max(launches, 1),
-            "alg_flop_per_launch": kflops / max(launches, 1), "source": src,
-        }
+    kernels = {} if args.no_kernel_breakdown else kernel_breakdown(Q, lambda: step(args.prec))
     if kernels:
         add_roofline(out, kernels, sec)
     if args.calib_copy_mb > 0:
@@ -332,6 +344,210 @@ def bench_batch(args, I, Q, torch, dev):
                                "cores": threads, "kind": "oracle",
                                "sample": f"every 8th problem ({len(sample)} of {len(w.a)}), NumPy FP64 + LAPACK",
                                "seconds": dt}
+    print(json.dumps(out), flush=True)
+
+
+KERNEL_CLASSES = {
+    # class: (bound, peak, unit, kernels, source file of the kernel)
+    "jacobi": ("alu", 78600.0, "GFLOP/s", "k_jacobi", "svd.hip"),
+    "qr_panel": ("alu", 78600.0, "GFLOP/s", "k_qr_panel", "qr.hip"),
+    "apply_panel": ("hbm", 8000.0, "GB/s", "k_apply1", "qr.hip"),
+    "block_vty": ("mfma", 78600.0, "GFLOP/s", "k_vty", "qr.hip"),
+    "block_upd": ("mfma", 78600.0, "GFLOP/s", "k_vupd", "qr.hip"),
+}
+
+
+def kernel_breakdown(Q, step):
+    """One extra step per kernel class, every launch of the class bracketed by
+    HIP events on its launch stream inside libqtt."""
+    kernels = {}
+    for cls, (bound, peak, unit, kname, src) in KERNEL_CLASSES.items():
+        Q.profile_start(cls, 20000)
+        step()
+        launches, kms, kbytes, kflops = Q.profile_stop()
+        work = kbytes if bound == "hbm" else kflops
+        achieved = work / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+        kernels[cls] = {
+            "kernel": kname, "bound": bound, "launches": launches, "ms_per_step": kms,
+            "avg_us": 1e3 * kms / max(launches, 1), "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "alg_bytes_per_launch": kbytes / max(launches, 1),
+            "alg_flop_per_launch": kflops / max(launches, 1), "source": src,
+        }
+    return kernels
+
+
+def bench_sum(args, I, Q, torch, dev):
+    """Exact sum of four rank-128 trains (42 cores) followed by rounding to rank
+    256 at 1e-8: one qtt_add into preallocated cores of the summed ranks, then
+    qtt_round in place on them (workspace preallocated)."""
+    import ctypes as C
+    w = I.sum4_n42_r128()
+    coeffs = w.extra["coeffs"]
+    nt = len(w.a)
+    terms = [Q.to_device(t, dev) for t in w.a]
+    n = len(w.a[0])
+    d = [c.shape[1] for c in w.a[0]]
+    rsum = [1] + [sum(t[k].shape[0] for t in w.a) for k in range(1, n)] + [1]
+    bufs = [torch.empty(rsum[k] * d[k] * rsum[k + 1], dtype=torch.float64, device=dev) for k in range(n)]
+    L = Q.load_library()
+    h = Q.handle(0)
+    views = [Q.TTView(t, 1) for t in terms]
+    arr = (Q.TT * nt)(*[v.struct for v in views])
+    cf = (C.c_double * nt)(*coeffs)
+    vo = Q.TTView(bufs, 1, ranks_override=rsum, phys_override=d)
+    nb = C.c_size_t()
+    Q._check(L.qtt_workspace_size(None, Q.OP_ROUND, None, C.byref(vo.struct), None, w.max_rank, 0, C.byref(nb)),
+             "qtt_workspace_size")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    info = Q._Info(n)
+
+    def step():
+        for k in range(n + 1):  # qtt_round rewrote the host ranks of the previous step
+            vo._ranks[k] = rsum[k]
+        Q._check(L.qtt_add(h.ptr, nt, arr, cf, C.byref(vo.struct), Q._stream_ptr()), "qtt_add")
+        Q._check(L.qtt_round(h.ptr, C.byref(vo.struct), float(w.rel_tol), int(w.max_rank), 0, C.byref(info.c),
+                             C.c_void_p(ws.data_ptr()), ws.numel(), Q._stream_ptr()), "qtt_round")
+        return vo.ranks()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ranks_out = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    flops = round_flops(rsum, d, ranks_out)
+    out = {
+        "metric": "QTT add+round TFLOP/s (sum of four rank-128 MPS, n=42, rounded to rank 256 at 1e-8)",
+        "value": flops / sec / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "cores": n, "terms": nt, "term_rank": 128, "sum_rank": max(rsum),
+                   "max_rank": w.max_rank, "rel_tol": w.rel_tol},
+        "algorithmic_gflop_per_step": flops / 1e9,
+        "ranks_out_max": max(ranks_out),
+        "jacobi_sweeps_max": info.c.jacobi_sweeps_max,
+    }
+    if not args.no_kernel_breakdown:
+        add_roofline(out, kernel_breakdown(Q, step), sec)
+    if not args.no_cpu_baseline:
+        import oracle as O
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
+        except Exception:
+            threads = os.cpu_count() or 1
+        reps = 0
+        t0 = time.perf_counter()
+        while reps == 0 or time.perf_counter() - t0 < 10.0:  # ~10 s of CPU work
+            Y, oinfo = O.round_tt(O.tt_sum(w.a, coeffs), w.rel_tol, w.max_rank, return_info=True)
+            reps += 1
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": reps * round_flops(rsum, d, oinfo.ranks) / dt / 1e12, "unit": "TFLOP/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"{reps} full sum + rounding runs of the same workload (NumPy FP64, "
+                                         f"LAPACK QR/SVD)", "seconds": dt}
+    print(json.dumps(out), flush=True)
+
+
+def fit_flops(ry, rc, d, dj, nsweeps, mpo=True):
+    """Algorithmic FLOP of qtt_fit (same conventions): the exactly contracted
+    product, the initial left environments, and per sweep and core one
+    projection L Y_q R^T, one QR with explicit Q and one environment step,
+    twice (down and up); rc are the ranks of the fitted train."""
+    n = len(d)
+    f = 0.0
+    for k in range(n):
+        f += 2.0 * (dj[k] if mpo else 1) * ry[k] * d[k] * ry[k + 1]
+    env = lambda k: 2.0 * rc[k] * ry[k] * d[k] * ry[k + 1] + 2.0 * rc[k + 1] * rc[k] * d[k] * ry[k + 1]
+    f += sum(env(k) for k in range(n - 1))
+    for _ in range(nsweeps):
+        for k in range(n):
+            proj = 2.0 * rc[k] * ry[k] * d[k] * ry[k + 1] + 2.0 * rc[k] * d[k] * rc[k + 1] * ry[k + 1]
+            m, c = rc[k] * d[k], rc[k + 1]
+            q = min(m, c)
+            f += 2.0 * (proj + env(k)) + 2.0 * (geqrf_flops(m, c) + ormqr_flops(m, q, q))
+    return f
+
+
+def bench_fit(args, I, Q, torch, dev):
+    """The pipeline the paper recommends for a product: the decomposition
+    (zip-up, super-cores of one core) result truncated to rank 64 as the
+    guess, then one variational sweep (Sec. 3.3), on the 2D Laplacian x
+    rank-64 MPS workload (n = 32).  A step is zip-up + fit."""
+    import ctypes as C
+    w = I.laplacian2d_r64()
+    A = Q.to_device(w.a, dev)
+    B = Q.to_device(w.b, dev)
+    nsweeps = 1
+    va, vb = Q.TTView(A, 2), Q.TTView(B, 1)
+    bnd, nbytes = Q.zipup_query(w.spec, va.struct, vb.struct, w.max_rank, 1)
+    d = [c.shape[1] for c in w.a]
+    dj = [c.shape[2] for c in w.a]
+    outs = [torch.empty(bnd[k] * d[k] * bnd[k + 1], dtype=torch.float64, device=dev) for k in range(len(d))]
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    z = Q.contract_zipup(w.spec, A, B, w.rel_tol, w.max_rank, ncores=1, out_buffers=outs, workspace=ws)
+    L = Q.load_library()
+    vc = Q.TTView([o.reshape(-1) for o in outs], 1, ranks_override=z.ranks, phys_override=d)
+    nb = C.c_size_t()
+    Q._check(L.qtt_fit_workspace_size(w.spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(vc.struct),
+                                      C.byref(nb)), "qtt_fit_workspace_size")
+    fws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    h = Q.handle(0)
+    nrm = C.c_double()
+
+    def step():
+        r = Q.contract_zipup(w.spec, A, B, w.rel_tol, w.max_rank, ncores=1, out_buffers=outs, workspace=ws)
+        for k, x in enumerate(r.ranks):
+            vc._ranks[k] = x
+        Q._check(L.qtt_fit(h.ptr, w.spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(vc.struct),
+                           nsweeps, C.byref(nrm), C.c_void_p(fws.data_ptr()), fws.numel(), Q._stream_ptr()),
+                 "qtt_fit")
+        return r.ranks, vc.ranks()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        zr, fr = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    ra = [1] + [c.shape[-1] for c in w.a]
+    rb = [1] + [c.shape[-1] for c in w.b]
+    ry = [x * y for x, y in zip(ra, rb)]
+    flops = zipup_flops(ra, rb, d, dj, zr, 1) + fit_flops(ry, zr, d, dj, nsweeps)
+    out = {
+        "metric": "QTT zip-up + variational sweep TFLOP/s (2D Laplacian MPO x rank-64 MPS, n=32, rank 64)",
+        "value": flops / sec / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "cores": len(d), "mps_rank": 64, "mpo_rank": 5, "max_rank": w.max_rank,
+                   "rel_tol": w.rel_tol, "zipup_ncores": 1, "fit_sweeps": nsweeps},
+        "algorithmic_gflop_per_step": flops / 1e9,
+        "ranks_out_max": max(fr),
+    }
+    if not args.no_kernel_breakdown:
+        add_roofline(out, kernel_breakdown(Q, step), sec)
+    if not args.no_cpu_baseline:
+        import oracle as O
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
+        except Exception:
+            threads = os.cpu_count() or 1
+        reps = 0
+        t0 = time.perf_counter()
+        while reps == 0 or time.perf_counter() - t0 < 10.0:  # ~10 s of CPU work
+            Z, zinfo = O.zipup(w.spec, w.a, w.b, w.rel_tol, w.max_rank, ncores=1, return_info=True)
+            O.fit(w.spec, w.a, w.b, Z, nsweeps=nsweeps)
+            reps += 1
+        dt = time.perf_counter() - t0
+        of = zipup_flops(ra, rb, d, dj, zinfo.ranks, 1) + fit_flops(ry, zinfo.ranks, d, dj, nsweeps)
+        out["cpu_baseline"] = {"value": reps * of / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+                               "sample": f"{reps} full zip-up + variational sweep runs of the same workload "
+                                         f"(NumPy FP64)", "seconds": dt}
     print(json.dumps(out), flush=True)
 
 

@@ -107,11 +107,15 @@ int qtt_workspace_size(qtt_handle h, int op, const char *spec, const qtt_tt *a, 
                        int64_t max_rank, int prec, size_t *bytes);
 
 /* Exact core-by-core Einstein summation (paper Sec. 3.1, eqs. quant_sum and
- * einsum): "i,i->i" (Hadamard, a and b MPS) or "ij,j->i" (a an MPO applied to
- * the MPS b).  C_k[(mu,nu), i, (mu',nu')] with the flattened bond
- * xi = mu * r_B + nu.  c must be an MPS whose host ranks equal
- * ranks_a * ranks_b and whose cores are caller-allocated; c's dtype must
- * match a's and b's (FP64 or FP32).  Asynchronous. */
+ * einsum): "i,i->i" (Hadamard, a and b MPS), "ij,j->i" (a an MPO applied to
+ * the MPS b) or "ij,jk->ik" (operator product of the MPOs a and b, c an MPO
+ * with cores [r, d_out(a), d_in(b), r']).  C_k[(mu,nu), i, (mu',nu')] with
+ * the flattened bond xi = mu * r_B + nu.  c's host ranks must equal
+ * ranks_a * ranks_b and its cores are caller-allocated; c's dtype must match
+ * a's and b's (FP64 or FP32).  An MPO result is rounded by passing it to
+ * qtt_round as an MPS of the combined physical size d_out * d_in (same
+ * memory).  The fused calls (qtt_contract_round, qtt_contract_zipup) take
+ * the two MPS-valued products only.  Asynchronous. */
 int qtt_contract(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qtt_tt *c,
                  void *ws, size_t ws_bytes, void *stream);
 
@@ -166,11 +170,39 @@ int qtt_contract_zipup(qtt_handle h, const char *spec, const qtt_tt *a, const qt
                        double rel_tol, int64_t max_rank, int32_t ncores, int prec,
                        qtt_round_info *info, void *ws, size_t ws_bytes, void *stream);
 
+/* Variational fitting of c to the product of a and b ("i,i->i" or
+ * "ij,j->i"; paper Sec. 3.3, eq. variational).  The guess c (FP64 MPS,
+ * caller-owned cores) is first orthogonalised from the left; then each of
+ * `nsweeps` sweeps replaces, from core n down to core 1 and back up to core
+ * n, one core at a time by the derivative of <c|a*b> with respect to it
+ * (left and right environments of <c|Y> with the exactly contracted product
+ * Y formed in the workspace), which is the core minimising ||c - a*b|| when
+ * every other core is orthonormal; a QR of the updated core (of its
+ * transpose on the way down) keeps the others orthonormal.  Ranks never
+ * grow (a QR may shrink one; c->ranks is rewritten).  On return cores 1..n-1
+ * are left-orthonormal and *norm_host (nullable) is ||c||.  The result of
+ * qtt_contract_zipup is the intended guess.  Synchronous. */
+int qtt_fit(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qtt_tt *c, int32_t nsweeps,
+            double *norm_host, void *ws, size_t ws_bytes, void *stream);
+/* Device workspace (bytes) of qtt_fit; pure shape arithmetic. */
+int qtt_fit_workspace_size(const char *spec, const qtt_tt *a, const qtt_tt *b, const qtt_tt *c, size_t *bytes);
+
 /* Shape query of qtt_contract_zipup: per-bond rank bounds of the result
  * (n+1 entries, nullable) and the device workspace in bytes (nullable).
  * Pure shape arithmetic; core pointers are not dereferenced. */
 int qtt_zipup_query(const char *spec, const qtt_tt *a, const qtt_tt *b, int64_t max_rank, int32_t ncores,
                     int64_t *bounds, size_t *ws_bytes);
+
+/* Exact sum out = sum_t coeffs[t] * terms[t] of `count` (1..16) trains of
+ * equal length, legs, physical sizes and dtype (paper Sec. 3.1, addition):
+ * core 1 is the row [c_1 X_1 ... c_count X_count], core n the column of the
+ * terms' last cores, the others block-diagonal in term order, so out's
+ * interior ranks are the sums of the terms' ranks (checked; its cores are
+ * caller-allocated).  coeffs may be NULL (all ones).  With one core the
+ * result is the weighted sum itself.  Rounding the sum (qtt_round) gives the
+ * add-and-truncate of the paper's add().  Asynchronous. */
+int qtt_add(qtt_handle h, int32_t count, const qtt_tt *terms, const double *coeffs, qtt_tt *out,
+            void *stream);
 
 /* <a, b> = E_n, E_0 = [[1]], E_k = sum_i a_k(i)^T E_{k-1} b_k(i) (the <C|C>
  * contractions of Sec. 3.3).  MPS operands of equal length and physical

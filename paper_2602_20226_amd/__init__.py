@@ -7,10 +7,12 @@ library; the first call does, and raises ImportError if it was not built.
 from . import qtt  # noqa: F401
 from .qtt import (  # noqa: F401
     QttError,
+    add,
     contract,
     contract_backward,
     contract_round,
     contract_zipup,
+    fit,
     inner,
     inner_backward,
     load_library,

@@ -75,7 +75,7 @@ int check_tt(const qtt_tt* t, int legs_expected) {
 inline int dphys(const qtt_tt* t, int k) { return t->phys[k * t->legs]; }          // output leg
 inline int dphys_in(const qtt_tt* t, int k) { return t->phys[k * t->legs + t->legs - 1]; }  // input leg
 
-enum Kind { K_TT = 0, K_HAD = 1, K_MPO = 2 };
+enum Kind { K_TT = 0, K_HAD = 1, K_MPO = 2, K_OPOP = 3 };
 
 // Shapes of the operand(s) of a rounding sweep.
 struct Shape {
@@ -221,6 +221,10 @@ int parse_spec(const char* spec, Kind& kind) {
     kind = K_MPO;
     return QTT_OK;
   }
+  if (t == "ij,jk->ik") {
+    kind = K_OPOP;
+    return QTT_OK;
+  }
   return QTT_ERR_SPEC;
 }
 
@@ -228,6 +232,9 @@ int shape_from_pair(const char* spec, const qtt_tt* a, const qtt_tt* b, Shape& s
   Kind kind;
   int st = parse_spec(spec, kind);
   if (st) return st;
+  // the operator product has its own entry (qtt_contract); the fused sweeps
+  // take an MPS result
+  if (kind == K_OPOP) return QTT_ERR_UNSUPPORTED;
   if ((st = check_tt(a, kind == K_MPO ? 2 : 1))) return st;
   if ((st = check_tt(b, 1))) return st;
   if (a->n != b->n) return QTT_ERR_SHAPE;
@@ -1060,6 +1067,152 @@ int zip_setup(const char* spec, const qtt_tt* a, const qtt_tt* b, long max_rank,
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------- variational fitting
+// Sec. 3.3: with the cores left of q left-orthonormal and those right of q
+// right-orthonormal, the best core q is L_{q-1} Y_q R_{q+1} (the derivative
+// of <C|Y> with respect to C_q), Y the exactly contracted product.
+struct FitPlan {
+  std::vector<long> ry, rc;        // product ranks, ranks of the fitted train (bounds)
+  std::vector<long> offY, offL, offF;
+  long offT = 0, offP = 0, offG = 0, offTq = 0, offQe = 0, offScr = 0, offNrm = 0;
+  long total = 0;
+};
+
+int make_fit_plan(const Shape& s, const qtt_tt* c, FitPlan& F) {
+  const int n = s.n;
+  F.ry = s.rc;
+  F.rc.assign(n + 1, 1);
+  for (int k = 0; k <= n; ++k) F.rc[k] = c->ranks[k];
+  long off = 0;
+  auto take = [&](long cnt) {
+    long o = off;
+    off += round_up(std::max(cnt, 1L), 32);
+    return o;
+  };
+  F.offY.assign(n, 0);
+  F.offL.assign(n + 1, 0);
+  F.offF.assign(n + 1, 0);
+  long maxT = 1, maxP = 1, maxG = 1, maxTq = 1, maxQe = 1, maxc = 1;
+  for (int k = 0; k < n; ++k) {
+    const long d = s.d[k];
+    F.offY[k] = take(F.ry[k] * d * F.ry[k + 1]);
+    maxT = std::max(maxT, F.rc[k] * d * F.ry[k + 1]);
+    maxT = std::max(maxT, F.rc[k] * d * F.ry[k + 1]);
+    const long P = F.rc[k] * d * F.rc[k + 1];
+    maxP = std::max(maxP, P);
+    // right-to-left: QR of the (d rc1) x rc0 transpose; left-to-right: of (rc0 d) x rc1
+    const long m1 = d * F.rc[k + 1], n1 = F.rc[k], m2 = F.rc[k] * d, n2 = F.rc[k + 1];
+    if (m1 > kMaxRows || m2 > kMaxRows) return QTT_ERR_UNSUPPORTED;
+    maxG = std::max(maxG, m1 * n1);
+    maxTq = std::max({maxTq, qr_t_doubles((int)m1, (int)n1), qr_t_doubles((int)m2, (int)n2)});
+    maxQe = std::max({maxQe, m1 * std::min(m1, n1), m2 * std::min(m2, n2)});
+    maxc = std::max({maxc, n1, n2});
+  }
+  for (int k = 0; k <= n; ++k) {
+    F.offL[k] = take(F.rc[k] * F.ry[k]);
+    F.offF[k] = take(F.rc[k] * F.ry[k]);
+  }
+  F.offT = take(maxT);
+  F.offP = take(maxP);
+  F.offG = take(maxG);
+  F.offTq = take(maxTq);
+  F.offQe = take(maxQe);
+  F.offScr = take(qr_scratch_doubles(maxc));
+  F.offNrm = take(1);
+  F.total = off;
+  return QTT_OK;
+}
+
+// P = L Y_q R^T: (rc0 x ry0)(ry0 x d ry1) then ((rc0 d) x ry1)(ry1 x rc1)
+hipError_t fit_project(hipStream_t st, const double* L, const double* Yq, const double* R, long rc0, long rc1,
+                       long ry0, long ry1, long d, double* T, double* P) {
+  hipError_t e = gemm_f64(st, false, false, (int)rc0, (int)(d * ry1), (int)ry0, 1.0, L, ry0, 0, Yq, d * ry1, 0, 0.0,
+                          T, d * ry1, 0, 1);
+  if (e != hipSuccess) return e;
+  return gemm_f64(st, false, true, (int)(rc0 * d), (int)rc1, (int)ry1, 1.0, T, ry1, 0, R, ry1, 0, 0.0, P, rc1, 0, 1);
+}
+
+int fit_sweeps(hipStream_t st, double* ws, const Shape& s, const FitPlan& F, qtt_tt* c, std::vector<long>& rc,
+               int nsweeps) {
+  const int n = s.n;
+  double* T = ws + F.offT;
+  double* P = ws + F.offP;
+  double* G = ws + F.offG;
+  double* Tq = ws + F.offTq;
+  double* Qe = ws + F.offQe;
+  double* scr = ws + F.offScr;
+  auto core = [&](int k) { return (double*)c->cores[k]; };
+  auto Y = [&](int k) { return (const double*)(ws + F.offY[k]); };
+  QTT_HIP(fill_f64(st, ws + F.offL[0], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + F.offF[n], 1.0, 1));
+  for (int k = 0; k + 1 < n; ++k)
+    QTT_HIP(env_step_left<double>(st, ws + F.offL[k], core(k), Y(k), rc[k], rc[k + 1], F.ry[k], F.ry[k + 1], s.d[k],
+                                  T, ws + F.offL[k + 1]));
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    // right to left: the centre moves to core 1
+    for (int q = n - 1; q >= 0; --q) {
+      const long d = s.d[q];
+      QTT_HIP(fit_project(st, ws + F.offL[q], Y(q), ws + F.offF[q + 1], rc[q], rc[q + 1], F.ry[q], F.ry[q + 1], d, T,
+                          P));
+      if (q > 0) {
+        const int m = (int)(d * rc[q + 1]), nn = (int)rc[q], qq = std::min(m, nn);
+        QTT_HIP(transpose(st, P, nn, m, m, G, nn));
+        QTT_HIP(householder_qr(st, G, m, nn, nn, Tq, scr));
+        QTT_HIP(set_eye_rect(st, Qe, m, qq));
+        QTT_HIP(apply_q(st, G, m, qq, nn, Tq, Qe, qq, qq, false, scr));
+        QTT_HIP(transpose(st, Qe, m, qq, qq, core(q), m));
+        rc[q] = qq;
+      } else {
+        QTT_HIP(copy_pad_rows(st, P, (int)(d * rc[1]), 1, 1, core(0), (int)(d * rc[1]), 1));
+      }
+      QTT_HIP(env_step_right<double>(st, ws + F.offF[q + 1], core(q), Y(q), rc[q], rc[q + 1], F.ry[q], F.ry[q + 1], d,
+                                     T, ws + F.offF[q]));
+    }
+    // left to right: the centre moves back to core n
+    for (int q = 0; q < n; ++q) {
+      const long d = s.d[q];
+      QTT_HIP(fit_project(st, ws + F.offL[q], Y(q), ws + F.offF[q + 1], rc[q], rc[q + 1], F.ry[q], F.ry[q + 1], d, T,
+                          P));
+      if (q < n - 1) {
+        const int m = (int)(rc[q] * d), nn = (int)rc[q + 1], qq = std::min(m, nn);
+        QTT_HIP(householder_qr(st, P, m, nn, nn, Tq, scr));
+        QTT_HIP(set_eye_rect(st, Qe, m, qq));
+        QTT_HIP(apply_q(st, P, m, qq, nn, Tq, Qe, qq, qq, false, scr));
+        QTT_HIP(copy_pad_rows(st, Qe, m, qq, qq, core(q), m, qq));
+        rc[q + 1] = qq;
+        QTT_HIP(env_step_left<double>(st, ws + F.offL[q], core(q), Y(q), rc[q], rc[q + 1], F.ry[q], F.ry[q + 1], d, T,
+                                      ws + F.offL[q + 1]));
+      } else {
+        QTT_HIP(copy_pad_rows(st, P, (int)(rc[q] * d), 1, 1, core(q), (int)(rc[q] * d), 1));
+      }
+    }
+  }
+  QTT_HIP(frob_norm(st, core(n - 1), rc[n - 1] * s.d[n - 1], ws + F.offNrm));
+  return QTT_OK;
+}
+
+int fit_setup(const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt* c, Shape& s, FitPlan& F,
+              size_t& orth_bytes) {
+  int st = shape_from_pair(spec, a, b, s);
+  if (st) return st;
+  if (a->dtype != QTT_F64 || b->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  if ((st = check_tt(c, 1))) return st;
+  if (c->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  if (c->n != s.n) return QTT_ERR_SHAPE;
+  for (int k = 0; k < s.n; ++k)
+    if (dphys(c, k) != s.d[k]) return QTT_ERR_SHAPE;
+  Shape sc;
+  shape_from_tt(c, sc);
+  Plan P;
+  if ((st = make_plan(sc, 0, P, false))) return st;
+  orth_bytes = ws_bytes_of(P);
+  return make_fit_plan(s, c, F);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* qtt_status_string(int status) {
@@ -1156,11 +1309,46 @@ int qtt_workspace_size(qtt_handle h, int op, const char* spec, const qtt_tt* a, 
   (void)prec;
 }
 
+static int contract_opop(qtt_handle h, const qtt_tt* a, const qtt_tt* b, qtt_tt* c, void* stream) {
+  int st;
+  if ((st = check_tt(a, 2)) || (st = check_tt(b, 2)) || (st = check_tt(c, 2))) return st;
+  const int n = a->n;
+  if (b->n != n || c->n != n) return QTT_ERR_SHAPE;
+  if (a->dtype != b->dtype || c->dtype != a->dtype) return QTT_ERR_SHAPE;
+  for (int k = 0; k < n; ++k) {
+    if (dphys_in(a, k) != dphys(b, k)) return QTT_ERR_SHAPE;
+    if (dphys(c, k) != dphys(a, k) || dphys_in(c, k) != dphys_in(b, k)) return QTT_ERR_SHAPE;
+  }
+  for (int k = 0; k <= n; ++k)
+    if (c->ranks[k] != a->ranks[k] * b->ranks[k]) return QTT_ERR_SHAPE;
+  Scoped sc(h->device);
+  hipStream_t strm = (hipStream_t)stream;
+  for (int k = 0; k < n; ++k) {
+    const int ra0 = (int)a->ranks[k], ra1 = (int)a->ranks[k + 1], rb0 = (int)b->ranks[k], rb1 = (int)b->ranks[k + 1];
+    const int di = dphys(a, k), dj = dphys_in(a, k), dk = dphys_in(b, k);
+    hipError_t e;
+    if (a->dtype == QTT_F64)
+      e = contract_mpo_mpo<double>(strm, (const double*)a->cores[k], ra0, di, dj, ra1, (const double*)b->cores[k],
+                                   rb0, dk, rb1, (double*)c->cores[k]);
+    else
+      e = contract_mpo_mpo<float>(strm, (const float*)a->cores[k], ra0, di, dj, ra1, (const float*)b->cores[k], rb0,
+                                  dk, rb1, (float*)c->cores[k]);
+    if (e != hipSuccess) return QTT_ERR_HIP;
+  }
+  return QTT_OK;
+}
+
 int qtt_contract(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* c, void* ws,
                  size_t ws_bytes, void* stream) {
   (void)ws;
   (void)ws_bytes;
   if (!h) return QTT_ERR_ARG;
+  {
+    Kind kind;
+    const int st = parse_spec(spec, kind);
+    if (st) return st;
+    if (kind == K_OPOP) return contract_opop(h, a, b, c, stream);
+  }
   Shape s;
   int st = shape_from_pair(spec, a, b, s);
   if (st) return st;
@@ -1619,5 +1807,117 @@ int qtt_contract_zipup(qtt_handle h, const char* spec, const qtt_tt* a, const qt
   return QTT_OK;
 }
 
+
+int qtt_add(qtt_handle h, int32_t count, const qtt_tt* terms, const double* coeffs, qtt_tt* out, void* stream) {
+  if (!h || !terms || !out) return QTT_ERR_ARG;
+  if (count < 1) return QTT_ERR_ARG;
+  if (count > kMaxAddTerms) return QTT_ERR_UNSUPPORTED;
+  int st;
+  const int legs = terms[0].legs;
+  for (int t = 0; t < count; ++t)
+    if ((st = check_tt(&terms[t], legs))) return st;
+  if ((st = check_tt(out, legs))) return st;
+  const int n = terms[0].n;
+  const qtt_dtype dt = terms[0].dtype;
+  if (out->n != n || out->dtype != dt) return QTT_ERR_SHAPE;
+  for (int t = 0; t < count; ++t) {
+    if (terms[t].n != n) return QTT_ERR_SHAPE;
+    if (terms[t].dtype != dt) return QTT_ERR_DTYPE;
+    for (int k = 0; k < n * legs; ++k)
+      if (terms[t].phys[k] != terms[0].phys[k]) return QTT_ERR_SHAPE;
+  }
+  for (int k = 0; k < n * legs; ++k)
+    if (out->phys[k] != terms[0].phys[k]) return QTT_ERR_SHAPE;
+  for (int k = 1; k < n; ++k) {
+    long sum = 0;
+    for (int t = 0; t < count; ++t) sum += terms[t].ranks[k];
+    if (out->ranks[k] != sum) return QTT_ERR_SHAPE;
+  }
+  Scoped sc(h->device);
+  hipStream_t strm = (hipStream_t)stream;
+  for (int k = 0; k < n; ++k) {
+    int P = 1;
+    for (int l = 0; l < legs; ++l) P *= terms[0].phys[k * legs + l];
+    const int first = (k == 0), last = (k == n - 1);
+    hipError_t e;
+    auto fill = [&](auto& at) {
+      int o0 = 0, o1 = 0;
+      for (int t = 0; t < count; ++t) {
+        at.r0[t] = (int)terms[t].ranks[k];
+        at.r1[t] = (int)terms[t].ranks[k + 1];
+        at.off0[t] = first ? 0 : o0;
+        at.off1[t] = last ? 0 : o1;
+        at.coef[t] = coeffs ? coeffs[t] : 1.0;
+        o0 += at.r0[t];
+        o1 += at.r1[t];
+      }
+    };
+    if (dt == QTT_F64) {
+      AddTerms<double> at{};
+      for (int t = 0; t < count; ++t) at.src[t] = (const double*)terms[t].cores[k];
+      fill(at);
+      e = tt_add_core<double>(strm, at, count, P, (int)out->ranks[k], (int)out->ranks[k + 1], first, last,
+                              (double*)out->cores[k]);
+    } else {
+      AddTerms<float> at{};
+      for (int t = 0; t < count; ++t) at.src[t] = (const float*)terms[t].cores[k];
+      fill(at);
+      e = tt_add_core<float>(strm, at, count, P, (int)out->ranks[k], (int)out->ranks[k + 1], first, last,
+                             (float*)out->cores[k]);
+    }
+    if (e != hipSuccess) return QTT_ERR_HIP;
+  }
+  return QTT_OK;
+}
+
+int qtt_fit_workspace_size(const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt* c, size_t* bytes) {
+  if (!bytes) return QTT_ERR_ARG;
+  Shape s;
+  FitPlan F;
+  size_t ob = 0;
+  int st = fit_setup(spec, a, b, c, s, F, ob);
+  if (st) return st;
+  *bytes = std::max(ob, (size_t)F.total * sizeof(double) + 256);
+  return QTT_OK;
+}
+
+int qtt_fit(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* c, int32_t nsweeps,
+            double* norm_host, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return QTT_ERR_ARG;
+  if (nsweeps < 0) return QTT_ERR_ARG;
+  Shape s;
+  FitPlan F;
+  size_t ob = 0;
+  int st = fit_setup(spec, a, b, c, s, F, ob);
+  if (st) return st;
+  if (!ws || ws_bytes < std::max(ob, (size_t)F.total * sizeof(double) + 256)) return QTT_ERR_WORKSPACE;
+  double nrm = 0.0;
+  // the guess, orthogonalised from the left (centre at core n; ranks may shrink)
+  if ((st = qtt_orthogonalize(h, c, &nrm, ws, ws_bytes, stream))) return st;
+  Scoped sc(h->device);
+  hipStream_t strm = (hipStream_t)stream;
+  double* w = align_ws(ws);
+  const int n = s.n;
+  for (int k = 0; k < n; ++k) {
+    const int ra0 = (int)s.ra[k], ra1 = (int)s.ra[k + 1], rb0 = (int)s.rb[k], rb1 = (int)s.rb[k + 1];
+    hipError_t e;
+    if (s.kind == K_HAD)
+      e = contract_hadamard<double>(strm, (const double*)a->cores[k], ra0, s.d[k], ra1, (const double*)b->cores[k],
+                                    rb0, rb1, w + F.offY[k]);
+    else
+      e = contract_mpo<double>(strm, (const double*)a->cores[k], ra0, s.d[k], s.dj[k], ra1,
+                               (const double*)b->cores[k], rb0, rb1, w + F.offY[k]);
+    if (e != hipSuccess) return QTT_ERR_HIP;
+  }
+  std::vector<long> rc(n + 1);
+  for (int k = 0; k <= n; ++k) rc[k] = c->ranks[k];
+  if ((st = fit_sweeps(strm, w, s, F, c, rc, nsweeps))) return st;
+  int e = readback(h, strm, w + F.offNrm, sizeof(double), h->pin_dbl);
+  if (e) return e;
+  if (!std::isfinite(h->pin_dbl[0])) return QTT_ERR_NONFINITE;
+  if (norm_host) *norm_host = h->pin_dbl[0];
+  for (int k = 0; k <= n; ++k) c->ranks[k] = rc[k];
+  return QTT_OK;
+}
 
 }  // extern "C"

@@ -189,6 +189,63 @@ __global__ __launch_bounds__(1024) void k_frob(const double* __restrict__ x, lon
   if (threadIdx.x == 0) out[0] = sqrt(s);
 }
 
+// C[(a,c), i, k, (b,dd)] = sum_j A[a,i,j,b] * B[c,j,k,dd]   (operator product)
+template <typename T>
+__global__ void k_mpo_mpo(const T* __restrict__ A, int ra0, int di, int dj, int ra1, const T* __restrict__ B,
+                          int rb0, int dk, int rb1, T* __restrict__ C) {
+  const long total = (long)ra0 * rb0 * di * dk * ra1 * rb1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    long t = e;
+    const int dd = t % rb1; t /= rb1;
+    const int b = t % ra1; t /= ra1;
+    const int k = t % dk; t /= dk;
+    const int i = t % di; t /= di;
+    const int c = t % rb0; t /= rb0;
+    const int a = (int)t;
+    T acc = 0;
+    for (int j = 0; j < dj; ++j)
+      acc += A[(((long)a * di + i) * dj + j) * ra1 + b] * B[(((long)c * dj + j) * dk + k) * rb1 + dd];
+    C[e] = acc;
+  }
+}
+
+// One core of the exact sum of `count` trains (block structure of Sec. 3.1):
+// core 0 is the row [c_1 X_1, c_2 X_2, ...] (terms side by side on the right
+// bond), the last core the column of the terms (stacked on the left bond),
+// the others block-diagonal in term order; with a single core the weighted
+// sum itself (products and sums rounded separately, in term order: no
+// fused multiply-add).
+template <typename T>
+__global__ void k_tt_add_core(AddTerms<T> t, int count, int P, int R0, int R1, int first, int last,
+                              T* __restrict__ out) {
+#pragma clang fp contract(off)
+  const long total = (long)R0 * P * R1;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int b = (int)(e % R1);
+    const long ai = e / R1;
+    const int i = (int)(ai % P);
+    const int a = (int)(ai / P);
+    T v = 0;
+    if (first && last) {
+      for (int q = 0; q < count; ++q) v = v + (T)t.coef[q] * t.src[q][i];
+    } else {
+      int q = 0;
+      if (last) {
+        while (q + 1 < count && a >= t.off0[q + 1]) ++q;
+      } else {
+        while (q + 1 < count && b >= t.off1[q + 1]) ++q;
+      }
+      const int la = first ? 0 : a - t.off0[q];
+      const int lb = last ? 0 : b - t.off1[q];
+      if (la >= 0 && la < t.r0[q] && lb >= 0 && lb < t.r1[q]) {
+        const T x = t.src[q][((long)la * P + i) * t.r1[q] + lb];
+        v = first ? (T)t.coef[q] * x : x;
+      }
+    }
+    out[e] = v;
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -207,6 +264,32 @@ hipError_t contract_mpo(hipStream_t s, const T* W, int rw0, int di, int dj, int 
   hipLaunchKernelGGL(k_mpo<T>, dim3(grid_for(total)), dim3(256), 0, s, W, rw0, di, dj, rw1, X, rx0, rx1, C);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t contract_mpo_mpo(hipStream_t s, const T* A, int ra0, int di, int dj, int ra1, const T* B, int rb0,
+                            int dk, int rb1, T* C) {
+  const long total = (long)ra0 * rb0 * di * dk * ra1 * rb1;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mpo_mpo<T>, dim3(grid_for(total)), dim3(256), 0, s, A, ra0, di, dj, ra1, B, rb0, dk, rb1, C);
+  return hipGetLastError();
+}
+template hipError_t contract_mpo_mpo<double>(hipStream_t, const double*, int, int, int, int, const double*, int, int,
+                                             int, double*);
+template hipError_t contract_mpo_mpo<float>(hipStream_t, const float*, int, int, int, int, const float*, int, int,
+                                            int, float*);
+
+template <typename T>
+hipError_t tt_add_core(hipStream_t s, const AddTerms<T>& terms, int count, int P, int R0, int R1, int first,
+                       int last, T* out) {
+  if (count < 1 || count > kMaxAddTerms) return hipErrorInvalidValue;
+  const long total = (long)R0 * P * R1;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tt_add_core<T>, dim3(grid_for(total)), dim3(256), 0, s, terms, count, P, R0, R1, first, last,
+                     out);
+  return hipGetLastError();
+}
+template hipError_t tt_add_core<double>(hipStream_t, const AddTerms<double>&, int, int, int, int, int, int, double*);
+template hipError_t tt_add_core<float>(hipStream_t, const AddTerms<float>&, int, int, int, int, int, int, float*);
+
 template hipError_t contract_hadamard<double>(hipStream_t, const double*, int, int, int, const double*, int, int, double*);
 template hipError_t contract_hadamard<float>(hipStream_t, const float*, int, int, int, const float*, int, int, float*);
 template hipError_t contract_mpo<double>(hipStream_t, const double*, int, int, int, int, const double*, int, int, double*);

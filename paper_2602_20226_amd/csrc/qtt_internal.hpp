@@ -34,6 +34,24 @@ hipError_t contract_hadamard(hipStream_t s, const T* A, int ra0, int d, int ra1,
 template <typename T>
 hipError_t contract_mpo(hipStream_t s, const T* W, int rw0, int di, int dj, int rw1,
                         const T* X, int rx0, int rx1, T* C);
+// Operator product C[(a,c), i, k, (b,d)] = sum_j A[a,i,j,b] B[c,j,k,d].
+template <typename T>
+hipError_t contract_mpo_mpo(hipStream_t s, const T* A, int ra0, int di, int dj, int ra1, const T* B, int rb0,
+                            int dk, int rb1, T* C);
+// One core of an exact sum of up to kMaxAddTerms trains: term q's core
+// (r0[q] x P x r1[q]) sits at row offset off0[q] / column offset off1[q] of
+// the R0 x P x R1 output core (first: one row, terms side by side, scaled by
+// coef[q]; last: one column; first && last: the weighted sum).
+constexpr int kMaxAddTerms = 16;
+template <typename T>
+struct AddTerms {
+  const T* src[kMaxAddTerms];
+  int r0[kMaxAddTerms], r1[kMaxAddTerms], off0[kMaxAddTerms], off1[kMaxAddTerms];
+  double coef[kMaxAddTerms];
+};
+template <typename T>
+hipError_t tt_add_core(hipStream_t s, const AddTerms<T>& terms, int count, int P, int R0, int R1, int first,
+                       int last, T* out);
 // M[(a,i),(mu',nu')] = sum_{mu,j} Y[a,mu,j,nu'] W[mu,i,j,mu']  (FP64)
 hipError_t bond_mpo_apply(hipStream_t s, const double* Y, int rho, int rw0, int dj, int rx1,
                           const double* W, int di, int rw1, double* M);

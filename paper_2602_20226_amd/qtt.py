@@ -33,7 +33,8 @@ EXPORTS = [
     "qtt_orthogonalize", "qtt_round", "qtt_contract_round", "qtt_inner", "qtt_inner_backward",
     "qtt_contract_backward", "qtt_profile_start", "qtt_profile_stop", "qtt_batch_workspace_size",
     "qtt_batch_plan_create", "qtt_batch_plan_launch", "qtt_batch_plan_results", "qtt_batch_plan_info",
-    "qtt_batch_plan_destroy", "qtt_contract_zipup", "qtt_zipup_query",
+    "qtt_batch_plan_destroy", "qtt_contract_zipup", "qtt_zipup_query", "qtt_add",
+    "qtt_fit", "qtt_fit_workspace_size",
 ]
 
 
@@ -108,6 +109,9 @@ def load_library():
     L.qtt_batch_plan_destroy.argtypes = [vp]
     L.qtt_contract_zipup.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_double, C.c_int64, C.c_int32, C.c_int,
                                      P(RoundInfoC), vp, C.c_size_t, vp]
+    L.qtt_fit.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_int32, P(C.c_double), vp, C.c_size_t, vp]
+    L.qtt_fit_workspace_size.argtypes = [C.c_char_p, P(TT), P(TT), P(TT), P(C.c_size_t)]
+    L.qtt_add.argtypes = [vp, C.c_int32, P(TT), P(C.c_double), P(TT), vp]
     L.qtt_zipup_query.argtypes = [C.c_char_p, P(TT), P(TT), C.c_int64, C.c_int32, P(C.c_int64), P(C.c_size_t)]
     L.qtt_profile_start.argtypes = [vp, C.c_int, C.c_int]
     L.qtt_profile_stop.argtypes = [vp, P(C.c_int64), P(C.c_double), P(C.c_double), P(C.c_double)]
@@ -232,18 +236,48 @@ def _legs(spec: str) -> int:
 
 
 def contract(spec: str, a: Sequence[torch.Tensor], b: Sequence[torch.Tensor]) -> List[torch.Tensor]:
-    """Exact core-by-core einsum; returns the contracted cores (device tensors)."""
+    """Exact core-by-core einsum; returns the contracted cores (device tensors).
+    "ij,jk->ik" multiplies two MPOs and returns MPO cores."""
     L = load_library()
     h = handle(a[0].device.index)
-    va, vb = TTView(list(a), _legs(spec)), TTView(list(b), 1)
+    opop = spec.replace(" ", "") == "ij,jk->ik"
+    va, vb = TTView(list(a), 2 if opop else _legs(spec)), TTView(list(b), 2 if opop else 1)
     dev = a[0].device
     out = []
     for ca, cb in zip(a, b):
-        shp = (ca.shape[0] * cb.shape[0], ca.shape[1], ca.shape[-1] * cb.shape[-1])
+        if opop:
+            shp = (ca.shape[0] * cb.shape[0], ca.shape[1], cb.shape[2], ca.shape[-1] * cb.shape[-1])
+        else:
+            shp = (ca.shape[0] * cb.shape[0], ca.shape[1], ca.shape[-1] * cb.shape[-1])
         out.append(torch.empty(shp, dtype=ca.dtype, device=dev))
-    vc = TTView(out, 1)
+    vc = TTView(out, 2 if opop else 1)
     _check(L.qtt_contract(h.ptr, spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(vc.struct),
                           None, 0, _stream_ptr()), "qtt_contract")
+    return out
+
+
+def add(terms: Sequence[Sequence[torch.Tensor]], coeffs: Optional[Sequence[float]] = None) -> List[torch.Tensor]:
+    """Exact sum of trains (MPS cores [r, d, r'] or MPO cores [r, d_out, d_in, r'])
+    with block cores; returns the summed cores (device tensors)."""
+    L = load_library()
+    h = handle(terms[0][0].device.index)
+    legs = terms[0][0].dim() - 2
+    views = [TTView(list(t), legs) for t in terms]
+    arr = (TT * len(terms))(*[v.struct for v in views])
+    n = len(terms[0])
+    ranks = [1] * (n + 1)
+    for k in range(1, n):
+        ranks[k] = sum(v.ranks()[k] for v in views)
+    dev = terms[0][0].device
+    out = []
+    for k in range(n):
+        shp = (ranks[k],) + tuple(terms[0][k].shape[1:-1]) + (ranks[k + 1],)
+        out.append(torch.empty(shp, dtype=terms[0][0].dtype, device=dev))
+    vo = TTView(out, legs)
+    cf = None
+    if coeffs is not None:
+        cf = (C.c_double * len(terms))(*[float(c) for c in coeffs])
+    _check(L.qtt_add(h.ptr, len(terms), arr, cf, C.byref(vo.struct), _stream_ptr()), "qtt_add")
     return out
 
 
@@ -436,6 +470,28 @@ def contract_zipup(spec: str, a, b, rel_tol: float, max_rank: int = 0, ncores: i
            "qtt_contract_zipup")
     ranks = vo.ranks()
     return info.result(_views_of_compact(out_buffers, ranks, d), ranks, n)
+
+
+def fit(spec: str, a, b, guess, nsweeps: int = 1, workspace: Optional[torch.Tensor] = None):
+    """Variational fitting of a copy of `guess` (FP64 MPS cores) to the product
+    of a and b; returns (cores, ranks, norm)."""
+    L = load_library()
+    h = handle(a[0].device.index)
+    legs = _legs(spec)
+    va, vb = TTView(list(a), legs), TTView(list(b), 1)
+    bufs = [g.detach().clone().reshape(-1) for g in guess]
+    d = [g.shape[1] for g in guess]
+    vc = TTView(bufs, 1, ranks_override=[guess[0].shape[0]] + [g.shape[-1] for g in guess], phys_override=d)
+    nb = C.c_size_t()
+    _check(L.qtt_fit_workspace_size(spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(vc.struct),
+                                    C.byref(nb)), "qtt_fit_workspace_size")
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = _workspace(nb.value, a[0].device)
+    nrm = C.c_double()
+    _check(L.qtt_fit(h.ptr, spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(vc.struct), int(nsweeps),
+                     C.byref(nrm), C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr()), "qtt_fit")
+    ranks = vc.ranks()
+    return _views_of_compact(bufs, ranks, d), ranks, nrm.value
 
 
 def round_tt(cores, rel_tol: float, max_rank: int = 0, prec: str = "fp64", want_sigmas: bool = False,

@@ -42,6 +42,7 @@ __all__ = [
     "hadamard_batch",
     "laplacian3d_r256",
     "residual_grad_2d",
+    "sum4_n42_r128",
 ]
 
 
@@ -374,3 +375,12 @@ def residual_grad_2d(seed: int = 4, m: int = 12, rx: int = 32, rb: int = 16) -> 
     x = random_mps(2 * m, rx, rng)
     b = random_mps(2 * m, rb, rng)
     return Workload("residual_grad2d_n24_r32", "ij,j->i", W, x, 0.0, 0, {"rhs": b})
+
+
+def sum4_n42_r128(seed: int = 5, n: int = 42, rmax: int = 128) -> Workload:
+    """Four Gaussian rank-128 MPS on the 42-core grid (drawn in order), to be
+    summed with coefficients (1, -0.5, 0.25, 2) and rounded to rank 256 at
+    1e-8 (exact sum of rank 512, then truncation)."""
+    rng = np.random.default_rng(seed)
+    terms = [random_mps(n, rmax, rng) for _ in range(4)]
+    return Workload("sum4_n42_r128", "sum", terms, [], 1e-8, 256, {"coeffs": [1.0, -0.5, 0.25, 2.0]})

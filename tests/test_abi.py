@@ -83,7 +83,9 @@ def test_workspace_planning_and_shape_errors():
     bad = _fake_tt([2, 2, 1], [2, 2])
     assert ws(Q.OP_ROUND, bad)[0] == -3
     # unsupported einsum string
-    assert ws(Q.OP_CONTRACT_ROUND, a, a, b"ij,jk->ik")[0] == -2
+    assert ws(Q.OP_CONTRACT_ROUND, a, a, b"ijk->i")[0] == -2
+    # the operator product has no fused rounding (its result is an MPO)
+    assert ws(Q.OP_CONTRACT_ROUND, a, a, b"ij,jk->ik")[0] == -10
     # MPO operand must have two legs
     assert ws(Q.OP_CONTRACT_ROUND, a, a, b"ij,j->i")[0] == -3
     # physical size mismatch in a Hadamard product
@@ -177,3 +179,12 @@ def test_zipup_query_errors_and_benchmark_shape():
         bnd, nbytes = Q.zipup_query("ij,j->i", a, b, 256, N)
         assert max(bnd) == 256 and bnd[0] == bnd[-1] == 1
         assert nbytes < 2 * 1024 ** 3
+
+
+def test_add_rejects_null_handle_and_arguments():
+    L = Q.load_library()
+    a = _fake_tt([1, 2, 1], [2, 2])
+    arr = (Q.TT * 2)(a, a)
+    out = _fake_tt([1, 4, 1], [2, 2])
+    assert L.qtt_add(None, 2, arr, None, C.byref(out), None) == -1
+    assert L.qtt_contract(None, b"ij,jk->ik", C.byref(a), C.byref(a), C.byref(a), None, 0, None) == -1
