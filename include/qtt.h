@@ -14,8 +14,9 @@
  * library allocates no device memory after qtt_create.  Host arrays (phys,
  * ranks, info arrays) are caller-owned too.  All work is ordered on the
  * caller's stream.  Calls that return host values (qtt_inner, qtt_round,
- * qtt_orthogonalize, qtt_contract_round) synchronise that stream before
- * returning; qtt_contract and the backward calls do not.
+ * qtt_orthogonalize, qtt_contract_round, qtt_contract_zipup, qtt_fit)
+ * synchronise that stream before returning; qtt_contract, qtt_add and the
+ * backward calls do not.
  *
  * Errors: every call returns a qtt_status; QTT_OK == 0, errors are negative.
  * On error the outputs are unspecified and host rank arrays are unchanged.
