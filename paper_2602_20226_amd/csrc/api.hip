@@ -406,7 +406,7 @@ int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_in
     QTT_HIP(copy_pad_rows(w.st, X, p, L, L, Xc, p, L));
     QTT_HIP(row_norms_sorted(w.st, Xc, p, L, sig, perm));
     QTT_HIP(permute_rows(w.st, Xc, p, L, perm, X));
-    QTT_HIP(jacobi_rows(w.st, X, p, L, ctr, kMaxSweeps, sweeps));
+    QTT_HIP(jacobi_rows(w.st, X, p, L, ctr, kMaxSweeps, sweeps, sig));  // sig[0]: largest row norm
     QTT_HIP(row_norms_sorted(w.st, X, p, L, sig, perm));
     QTT_HIP(truncate_decide(w.st, sig, p, ws + P.offNorm, rel_tol, n - 1, max_rank, tr));
     QTT_HIP(hipMemcpyAsync(w.h->pin_int, sweeps, sizeof(int), hipMemcpyDeviceToHost, w.st));
@@ -984,7 +984,7 @@ int zip_sweep(qtt_context* h, hipStream_t st, double* ws, const Shape& s, const 
       QTT_HIP(copy_pad_rows(st, X, p, L, L, Xc, p, L));
       QTT_HIP(row_norms_sorted(st, Xc, p, L, sig, perm));
       QTT_HIP(permute_rows(st, Xc, p, L, perm, X));
-      QTT_HIP(jacobi_rows(st, X, p, L, ctr, kMaxSweeps, sweeps));
+      QTT_HIP(jacobi_rows(st, X, p, L, ctr, kMaxSweeps, sweeps, sig));  // sig[0]: largest row norm
       QTT_HIP(row_norms_sorted(st, X, p, L, sig, perm));
       QTT_HIP(frob_norm(st, sig, p, nrm));  // ||S||_F of the super-core being split
       QTT_HIP(truncate_decide(st, sig, p, nrm, rel_tol, n - 1, max_rank, tr));

@@ -89,11 +89,12 @@ hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, do
 // One-sided Jacobi on the rows of X (p x L, row-major, ld L): on return the
 // rows are mutually orthogonal (X <- Z^T X, Z orthogonal, not formed).
 // counter: 8 + ceil(p / 8) unsigned of device scratch (cleared by the routine).  Sweeps
-// used go to *sweeps_dev.
+// used go to *sweeps_dev.  ref_norm (device, nullable): the largest input row
+// norm; rows whose norm falls below eps^2 times it are deflated to zero.
 // Algorithmic bytes and FLOP of one Jacobi sweep on p rows of length L.
 void jacobi_sweep_cost(int p, int L, double* bytes, double* flops);
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
-                       int* sweeps_dev);
+                       int* sweeps_dev, const double* ref_norm = nullptr);
 // dst[j] = src[perm[j]] (row gather).
 hipError_t permute_rows(hipStream_t s, const double* src, int p, int L, const int* perm, double* dst);
 // sigma_i = ||X_i||, perm = argsort descending (stable on ties).

@@ -36,9 +36,11 @@ __device__ __forceinline__ int rr_item(int pos, int round, int n) {
 }
 
 // Rotate the pair (u, v) of rows (E elements per lane, zero past the row end)
-// so that they become orthogonal; returns true when a rotation was applied.
+// so that they become orthogonal; returns true when a rotation was applied
+// or a row was deflated.  A nonzero row whose squared norm is below negl is
+// set to zero instead (see k_jacobi).
 template <int E>
-__device__ __forceinline__ bool rotate_pair(double (&u)[E], double (&v)[E], double tol) {
+__device__ __forceinline__ bool rotate_pair(double (&u)[E], double (&v)[E], double tol, double negl) {
   double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
@@ -49,6 +51,20 @@ __device__ __forceinline__ bool rotate_pair(double (&u)[E], double (&v)[E], doub
   al = wave_sum_bc(al);
   be = wave_sum_bc(be);
   ga = wave_sum_bc(ga);
+  if (al < negl || be < negl) {
+    bool changed = false;
+    if (al < negl && al > 0.0) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) u[q] = 0.0;
+      changed = true;
+    }
+    if (be < negl && be > 0.0) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) v[q] = 0.0;
+      changed = true;
+    }
+    return changed;
+  }
   double cs, sn;
   if (!jacobi_rotation(al, be, ga, tol, cs, sn)) return false;
 #pragma unroll
@@ -102,9 +118,18 @@ __device__ __forceinline__ void lds_get(const double* slot, double (&r)[E]) {
 
 // ctr[0..1]: grid barrier; ctr[2..4]: rotation counts of three consecutive
 // sweeps; ctr[JCTR + b]: rounds completed by block b.
+// Rows are deflated to exact zeros once their squared norm falls below
+// negl = 2^-208 max_i ||x_i||^2 of the input (norm below eps^2 times the
+// largest): a row that has become an exact tiny multiple of another cannot
+// be rotated away (each rotation shrinks it by about eps while it stays
+// parallel, so the relative test would fire on every sweep), and at that
+// size it is zero to working precision.  ref (nullable) points at the
+// largest input row norm.
 template <int E>
 __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, int L, unsigned* __restrict__ ctr,
-                                                int max_sweeps, int* sweeps_out, double tol) {
+                                                int max_sweeps, int* sweeps_out, double tol,
+                                                const double* __restrict__ ref) {
+  const double negl = ref ? 0x1p-208 * (ref[0] * ref[0]) : 0.0;
   extern __shared__ double sh[];  // 16 row slots of 64 E doubles
   __shared__ double bes[2][JB];   // squared norms travelling with the bottom rows
   __shared__ unsigned s_tot;
@@ -146,7 +171,7 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
           double u[E], v[E];
           lds_get<E>(sa, u);
           lds_get<E>(sc, v);
-          if (rotate_pair<E>(u, v, tol)) {
+          if (rotate_pair<E>(u, v, tol, negl)) {
             lds_put<E>(sa, u);
             lds_put<E>(sc, v);
             if (lane == 0) ++local_rot;
@@ -170,6 +195,18 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
       }
       al = wave_sum_bc(al);
       be = wave_sum_bc(be);
+      if (al < negl && al > 0.0) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) top[q] = 0.0;
+        al = 0.0;
+        if (lane == 0) ++local_rot;
+      }
+      if (be < negl && be > 0.0) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) bot[q] = 0.0;
+        be = 0.0;
+        if (lane == 0) ++local_rot;
+      }
       for (int s = 0; s < JB; ++s) {
         double ga = 0.0;
 #pragma unroll
@@ -328,7 +365,7 @@ inline int gsz(long n) {
 }  // namespace
 
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
-                       int* sweeps_dev) {
+                       int* sweeps_dev, const double* ref_norm) {
   if (p <= 0 || L <= 0) return hipSuccess;
   if (L > 1024 || p > 1024) return hipErrorInvalidValue;
   const int nblk = (p + JB - 1) / JB;
@@ -338,7 +375,7 @@ hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter
   const int grid = nb2 / 2;
   // tolerance on |a.c| / (||a|| ||c||)
   const double tol = 2.220446049250313e-16 * sqrt((double)L);
-  void* args[] = {&X, &p, &L, &counter, &max_sweeps, &sweeps_dev, (void*)&tol};
+  void* args[] = {&X, &p, &L, &counter, &max_sweeps, &sweeps_dev, (void*)&tol, (void*)&ref_norm};
   const void* fn;
   int E;
   if (L <= 64) {
