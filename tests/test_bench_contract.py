@@ -43,3 +43,36 @@ def test_flop_model_reduces_to_textbook_counts():
     # a rank-1 single-core train has no QR and no SVD: only the bond products
     f = bench.contract_round_flops([1, 1], [1, 1], [2], [2], [1, 1], mpo=True)
     assert f == 2.0 * 1 * 2 * 1 + 2.0 * 2 * 1 * 2 + bench.ormqr_flops(2, 1, 1)
+
+
+def test_round_flop_model_on_two_cores():
+    """qtt_round of [1, 3, 1] with d = 2, kept rank 2: QR of the 2 x 3 first
+    unfolding, R times the last core, nominal SVD of the 2 x 2 centre, the
+    U Sigma product and one Q application."""
+    f = bench.round_flops([1, 3, 1], [2, 2], [1, 2, 1])
+    expect = (bench.geqrf_flops(2, 3) + 2.0 * 2 * 3 * 2 + bench.svd_nominal_flops(2, 2) + 2.0 * 2 * 2 * 2
+              + bench.ormqr_flops(2, 2, 2))
+    assert f == expect
+
+
+def test_zipup_and_fit_flop_models():
+    import qtt_inputs as I
+    w = I.laplacian3d_r256()
+    ra = [1] + [c.shape[-1] for c in w.a]
+    rb = [1] + [c.shape[-1] for c in w.b]
+    d = [c.shape[1] for c in w.a]
+    dj = [c.shape[2] for c in w.a]
+    n = len(d)
+    out = [min(256, 2 ** k, 2 ** (n - k)) for k in range(n + 1)]
+    full = bench.contract_round_flops(ra, rb, d, dj, out)
+    z1 = bench.zipup_flops(ra, rb, d, dj, out, 1)
+    z2 = bench.zipup_flops(ra, rb, d, dj, out, 2)
+    # the decomposition algorithm never factors the 3584 x 1792 unfoldings
+    assert 0 < z1 < z2 < full
+    # no sweep: the product and the first left environments only
+    ry, rc, dd = [1, 4, 1], [1, 2, 1], [2, 2]
+    f0 = bench.fit_flops(ry, rc, dd, dd, 0)
+    prod = sum(2.0 * dd[k] * ry[k] * dd[k] * ry[k + 1] for k in range(2))
+    env0 = 2.0 * rc[0] * ry[0] * dd[0] * ry[1] + 2.0 * rc[1] * rc[0] * dd[0] * ry[1]
+    assert f0 == prod + env0
+    assert bench.fit_flops(ry, rc, dd, dd, 2) > bench.fit_flops(ry, rc, dd, dd, 1) > f0
