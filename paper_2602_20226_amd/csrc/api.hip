@@ -1098,8 +1098,7 @@ int make_fit_plan(const Shape& s, const qtt_tt* c, FitPlan& F) {
   for (int k = 0; k < n; ++k) {
     const long d = s.d[k];
     F.offY[k] = take(F.ry[k] * d * F.ry[k + 1]);
-    maxT = std::max(maxT, F.rc[k] * d * F.ry[k + 1]);
-    maxT = std::max(maxT, F.rc[k] * d * F.ry[k + 1]);
+    maxT = std::max(maxT, F.rc[k] * d * F.ry[k + 1]);  // E Y_k, C_k F and L Y_k share this size
     const long P = F.rc[k] * d * F.rc[k + 1];
     maxP = std::max(maxP, P);
     // right-to-left: QR of the (d rc1) x rc0 transpose; left-to-right: of (rc0 d) x rc1
