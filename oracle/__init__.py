@@ -20,7 +20,13 @@ numpy.linalg, written from the paper's definitions:
   * inner product: the <C|C>-type contractions of Sec. 3.3;
   * decomposition ("zip-up") algorithm of Sec. 3.2: operands normalised to
     the left end, then a super-core of N exact product cores split off one
-    truncated-SVD core at a time while the next product core is added.
+    truncated-SVD core at a time while the next product core is added;
+  * variational fitting of Sec. 3.3 (eq. variational): one core at a time,
+    the derivative of <C|Y> with every other core orthonormal;
+  * sums of many trains (the block structure of Sec. 3.1, operators
+    included) and the operator product 'ij,jk->ik';
+  * general digit bases (factorised dimensions, Sec. 2): every function takes
+    per-core physical sizes.
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: dense reconstruction + numpy.einsum on tiny grids, the closed forms of
