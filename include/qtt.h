@@ -165,7 +165,8 @@ int qtt_contract_round(qtt_handle h, const char *spec, const qtt_tt *a, const qt
  * qtt_zipup_query returns; its ranks are written on return.  info->norm and
  * info->delta refer to the first split; tail/margins/sigma per bond as for
  * qtt_round.  FP64 operands; prec selects the bond-product arithmetic.
- * Limits: (r d) <= 1024 at every split, operand unfoldings <= 4096 rows.
+ * Limits: (r d) <= 1024 rows and <= 4096 columns at every split (bounds
+ * from qtt_zipup_query), operand unfoldings <= 4096 rows.
  * Synchronous. */
 int qtt_contract_zipup(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qtt_tt *out,
                        double rel_tol, int64_t max_rank, int32_t ncores, int prec,
