@@ -14,7 +14,10 @@ Hadamard products in one graph-replayed persistent launch), and
 `--workload laplacian3d_n42_r256_zipup` the same product computed by the
 decomposition ("zip-up") algorithm of Sec. 3.2 (`--ncores` product cores per
 super-core), whose FLOP are counted under the same conventions for the work
-that algorithm does.
+that algorithm does; `--workload sum4_n42_r128_round` the exact sum of four
+rank-128 trains followed by rounding, and `--workload
+laplacian2d_n32_r64_zipup_fit` a zip-up guess followed by one variational
+sweep (Sec. 3.3).
 """
 from __future__ import annotations
 

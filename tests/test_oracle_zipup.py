@@ -186,3 +186,26 @@ def test_zipup_laplacian_error_near_tolerance():
             Z, info = O.zipup("ij,j->i", W, X, tol, ncores=N, return_info=True)
             err = np.linalg.norm(O.to_dense(Z) - ref)
             assert err <= 4 * tol * nref, (N, tol, err / nref)
+
+
+def test_zipup_and_fit_on_closed_form_products():
+    """exp(a x) exp(b x) = exp((a+b) x) and sin(x) cos(x) = sin(2x)/2 (the
+    closed forms of Sec. 4.1) through the decomposition algorithm and one
+    variational sweep from its result: the closed-form values and ranks."""
+    n = 12
+    e1, e2 = Q.exp_qtt(n, 0.7), Q.exp_qtt(n, -1.9)
+    ref = O.to_dense(Q.exp_qtt(n, 0.7 - 1.9))
+    for N in (1, 2):
+        Z = O.zipup("i,i->i", e1, e2, 1e-12, 0, ncores=N)
+        assert max(O.ranks_of(Z)) == 1
+        np.testing.assert_allclose(O.to_dense(Z), ref, rtol=1e-12)
+    s = Q.trig_qtt(n, 1.3, 0.0, "sin")
+    c = Q.trig_qtt(n, 1.3, 0.0, "cos")
+    ref2 = 0.5 * O.to_dense(Q.trig_qtt(n, 2.6, 0.0, "sin"))
+    Z = O.zipup("i,i->i", s, c, 1e-12, 0, ncores=1)
+    # one-core super-cores can keep more than the minimal rank near the right
+    # end (the exact right part is not orthonormal); rounding finds rank 2
+    assert max(O.ranks_of(Z)) <= 4 and max(O.ranks_of(O.round_tt(Z, 1e-12))) == 2
+    np.testing.assert_allclose(O.to_dense(Z), ref2, rtol=0, atol=1e-12 * np.abs(ref2).max())
+    F = O.fit("i,i->i", s, c, Z, nsweeps=1)
+    np.testing.assert_allclose(O.to_dense(F), ref2, rtol=0, atol=1e-12 * np.abs(ref2).max())
