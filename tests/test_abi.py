@@ -188,3 +188,21 @@ def test_add_rejects_null_handle_and_arguments():
     out = _fake_tt([1, 4, 1], [2, 2])
     assert L.qtt_add(None, 2, arr, None, C.byref(out), None) == -1
     assert L.qtt_contract(None, b"ij,jk->ik", C.byref(a), C.byref(a), C.byref(a), None, 0, None) == -1
+
+
+def test_fit_workspace_size_and_shape_errors():
+    L = Q.load_library()
+    n = 42
+    rx = [min(256, 2 ** k, 2 ** (n - k)) for k in range(n + 1)]
+    rw = [1] + [7] * (n - 1) + [1]
+    a = _fake_tt(rw, [2] * (2 * n), legs=2)
+    b = _fake_tt(rx, [2] * n)
+    c = _fake_tt(rx, [2] * n)
+    nb = C.c_size_t()
+    assert L.qtt_fit_workspace_size(b"ij,j->i", C.byref(a), C.byref(b), C.byref(c), C.byref(nb)) == 0
+    # the exactly contracted product (rank 7 x 256) alone is 1.4 GB
+    assert 1.3e9 < nb.value < 3e9
+    bad = _fake_tt(rx, [3] * n)
+    assert L.qtt_fit_workspace_size(b"ij,j->i", C.byref(a), C.byref(b), C.byref(bad), C.byref(nb)) == -3
+    assert L.qtt_fit_workspace_size(b"ij,jk->ik", C.byref(a), C.byref(b), C.byref(c), C.byref(nb)) == -10
+    assert L.qtt_fit(None, b"ij,j->i", C.byref(a), C.byref(b), C.byref(c), 1, None, None, 0, None) == -1
