@@ -24,6 +24,8 @@ __all__ = [
     "fit",
     "RoundInfo",
     "truncation_rank",
+    "cut_gaps",
+    "noise_amplification",
     "inner",
     "norm",
     "rel_error",
@@ -184,6 +186,8 @@ class RoundInfo:
     margin_hi: List[float] = field(default_factory=list)   # tail(r)/delta
     maxrank_hit: List[bool] = field(default_factory=list)
     sigmas: List[np.ndarray] = field(default_factory=list)  # per bond 1..n-1
+    gaps: List[float] = field(default_factory=list)         # per bond: (s_r - s_{r+1}) / s_r
+    deltas: List[float] = field(default_factory=list)       # per bond: truncation threshold used
 
 
 def truncation_rank(sig: np.ndarray, delta: float, max_rank: int):
@@ -260,8 +264,61 @@ def round_tt(X, rel_tol: float, max_rank: int = 0, return_info: bool = False):
     info.margin_hi = mhi
     info.maxrank_hit = hit
     info.sigmas = sigs
+    info.gaps = cut_gaps(sigs, info.ranks)
+    info.deltas = [delta] * (n - 1)
     info.err_bound = math.sqrt(sum(t * t for t in tails))
     return (cores, info) if return_info else cores
+
+
+def cut_gaps(sigmas, ranks) -> List[float]:
+    """Relative singular-value gap at every bond's cut: (s_r - s_{r+1}) / s_r.
+
+    r is the kept rank at the bond and s the bond's singular values before
+    truncation.  When nothing is discarded (r equals the number of singular
+    values) the kept subspace is the whole space and the gap is reported as
+    inf.  The rounding of a perturbed input moves the kept subspace by about
+    ||perturbation|| / (s_r - s_{r+1}) (Wedin's bound for the truncated SVD),
+    so a small gap marks a bond where several truncations are equally valid
+    and a tiny input change is amplified.
+    """
+    out = []
+    for b, s in enumerate(sigmas):
+        s = np.asarray(s, dtype=np.float64)
+        r = ranks[b + 1]
+        if r >= s.size or s[r - 1] <= 0.0:
+            out.append(math.inf)
+        else:
+            out.append(float((s[r - 1] - s[r]) / s[r - 1]))
+    return out
+
+
+def noise_amplification(X, rel_tol: float, max_rank: int = 0, eps: float = 1e-10, seed: int = 0,
+                        trials: int = 2):
+    """How much the rounding amplifies a small relative change of its input.
+
+    Every core of X receives independent Gaussian noise of relative Frobenius
+    size eps (X_k + eps ||X_k|| G / ||G||); the perturbed train is rounded with
+    the same tolerance and rank cap, and the change of the rounded tensor is
+    divided by the change of the input tensor, both measured exactly through
+    difference trains.  Returns (largest ratio over the trials, list of
+    ratios).  A ratio near 1 means the truncation decisions are stable; a
+    large one means an error of a given size in any implementation's
+    contraction (different rounding order, reduced-precision products) shows
+    up multiplied by that factor in the rounded result.
+    """
+    rng = np.random.default_rng(seed)
+    base = round_tt(X, rel_tol, max_rank)
+    ratios = []
+    for _ in range(trials):
+        Xp = []
+        for c in X:
+            g = rng.standard_normal(c.shape)
+            Xp.append(c + eps * np.linalg.norm(c) / np.linalg.norm(g) * g)
+        d_in = diff_norm(Xp, X)
+        out = round_tt(Xp, rel_tol, max_rank)
+        d_out = diff_norm(out, base)
+        ratios.append(d_out / d_in if d_in > 0 else 0.0)
+    return max(ratios), ratios
 
 
 def orthogonalize_right(X):
@@ -340,6 +397,7 @@ def zipup(spec: str, A, B, rel_tol: float, max_rank: int = 0, ncores: int = 1, r
     mhi = [0.0] * nb
     hit = [False] * nb
     sigs = [None] * nb
+    deltas = [0.0] * nb
     out = []
     S = np.ones((1, 1, 1))  # [r, P, r_C]
     legs = 0
@@ -362,6 +420,7 @@ def zipup(spec: str, A, B, rel_tol: float, max_rank: int = 0, ncores: int = 1, r
             if nrm == 0.0:
                 r, t_r, t_rm1 = 1, 0.0, 0.0
             sigs[b] = Sig.copy()
+            deltas[b] = delta
             tails[b] = t_r
             hit[b] = capped
             mlo[b] = (t_rm1 / delta) if delta > 0 else math.inf
@@ -378,6 +437,8 @@ def zipup(spec: str, A, B, rel_tol: float, max_rank: int = 0, ncores: int = 1, r
     info.margin_hi = mhi
     info.maxrank_hit = hit
     info.sigmas = sigs
+    info.deltas = deltas
+    info.gaps = cut_gaps(sigs, info.ranks)
     info.err_bound = math.sqrt(sum(t * t for t in tails))
     return (out, info) if return_info else out
 

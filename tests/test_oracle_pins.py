@@ -402,3 +402,89 @@ def test_grad_euler_identity():
     rhs = 2 * O.inner(y, y) - 2 * O.inner(y, b)
     for k in range(len(x)):
         assert abs(np.sum(g[k] * x[k]) - rhs) < 1e-11 * (1 + abs(rhs))
+
+
+@pytest.mark.parametrize("spec", ["ij,j->i", "i,i->i"])
+def test_contract_grad_is_the_adjoint_of_contract(spec):
+    """contract_grad's dW and dX against the definition of a gradient.
+
+    The product is bilinear in (W, X), so for any direction D the central
+    difference <G, C(W + hD, X)> - <G, C(W - hD, X)> equals 2h <dW, D> with no
+    truncation error, and likewise for X; C here is the contraction written
+    out entry by entry from eq. einsum (independent of contract()).  A
+    transposed index or a swapped operand in either output fails it."""
+    rng = np.random.default_rng(41)
+    if spec == "ij,j->i":
+        W = [rng.standard_normal(s) for s in [(1, 2, 3, 3), (3, 2, 3, 2), (2, 3, 2, 1)]]
+        X = [rng.standard_normal(s) for s in [(1, 3, 2), (2, 3, 4), (4, 2, 1)]]
+    else:
+        W = [rng.standard_normal(s) for s in [(1, 2, 3), (3, 3, 2), (2, 2, 1)]]
+        X = [rng.standard_normal(s) for s in [(1, 2, 2), (2, 3, 4), (4, 2, 1)]]
+
+    def core_product(w, x):
+        # C[(mu,nu), i, (mu',nu')] = sum_j W[mu,i,j,mu'] X[nu,j,nu'] (or W[mu,i,mu'] X[nu,i,nu'])
+        if spec == "ij,j->i":
+            ra, di, dj, rb = w.shape
+        else:
+            ra, di, rb = w.shape
+            dj = di
+        rc, _, rd = x.shape
+        c = np.zeros((ra * rc, di, rb * rd))
+        for mu, nu, i, mu2, nu2 in itertools.product(range(ra), range(rc), range(di), range(rb), range(rd)):
+            if spec == "ij,j->i":
+                v = sum(w[mu, i, j, mu2] * x[nu, j, nu2] for j in range(dj))
+            else:
+                v = w[mu, i, mu2] * x[nu, i, nu2]
+            c[mu * rc + nu, i, mu2 * rd + nu2] = v
+        return c
+
+    G = [rng.standard_normal(core_product(w, x).shape) for w, x in zip(W, X)]
+    dW, dX = O.contract_grad(spec, W, X, G)
+    h = 0.37  # any step: the pairing is linear in each operand
+    for k in range(len(W)):
+        assert dW[k].shape == W[k].shape and dX[k].shape == X[k].shape
+        for _ in range(3):
+            D = rng.standard_normal(W[k].shape)
+            lhs = np.sum(G[k] * core_product(W[k] + h * D, X[k])) - np.sum(G[k] * core_product(W[k] - h * D, X[k]))
+            assert abs(lhs - 2 * h * np.sum(dW[k] * D)) <= 1e-12 * max(1.0, abs(lhs))
+            E = rng.standard_normal(X[k].shape)
+            lhs = np.sum(G[k] * core_product(W[k], X[k] + h * E)) - np.sum(G[k] * core_product(W[k], X[k] - h * E))
+            assert abs(lhs - 2 * h * np.sum(dX[k] * E)) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def _two_core_with_sigmas(rng, s, d=16):
+    """X = U diag(s) V^T as a two-core train: the bond's singular values are s."""
+    U, _ = np.linalg.qr(rng.standard_normal((d, len(s))))
+    V, _ = np.linalg.qr(rng.standard_normal((d, len(s))))
+    return [U.reshape(1, d, len(s)), (np.diag(s) @ V.T).reshape(len(s), d, 1)]
+
+
+@pytest.mark.parametrize("g", [0.5, 1e-2, 1e-4])
+def test_cut_gap_is_the_constructed_gap(g):
+    rng = np.random.default_rng(42)
+    s = np.array([1.0, 0.5, 0.5 * (1.0 - g), 0.1])
+    X = _two_core_with_sigmas(rng, s)
+    _, info = O.round_tt(X, 0.0, 2, return_info=True)
+    assert info.ranks == [1, 2, 1]
+    assert np.allclose(info.sigmas[0], s, rtol=0, atol=1e-15)
+    assert abs(info.gaps[0] - g) <= 1e-12
+    # nothing discarded: no cut, no gap
+    _, info = O.round_tt(X, 0.0, 0, return_info=True)
+    assert info.ranks == [1, 4, 1] and info.gaps == [math.inf]
+
+
+def test_noise_amplification_follows_the_gap():
+    """Wide gap: the rounded tensor moves by about the input change.  Narrow
+    gap: the kept pair of singular vectors rotates by about eps / gap, so the
+    ratio grows like 1 / gap (Wedin)."""
+    rng = np.random.default_rng(43)
+    wide = _two_core_with_sigmas(rng, np.array([1.0, 0.5, 0.25, 0.1]))
+    amp, ratios = O.noise_amplification(wide, 0.0, 2, eps=1e-9, seed=1, trials=4)
+    assert 0.3 <= min(ratios) and amp <= 3.0
+    g = 1e-4
+    narrow = _two_core_with_sigmas(rng, np.array([1.0, 0.5, 0.5 * (1.0 - g), 0.1]))
+    amp, _ = O.noise_amplification(narrow, 0.0, 2, eps=1e-9, seed=1, trials=4)
+    assert amp >= 0.01 / g
+    # no truncation: rounding is the identity on the tensor, ratio 1
+    amp, ratios = O.noise_amplification(wide, 0.0, 0, eps=1e-9, seed=1, trials=2)
+    assert all(abs(r - 1.0) <= 1e-4 for r in ratios)
