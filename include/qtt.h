@@ -89,6 +89,15 @@ int qtt_create(qtt_handle *h, int device);
 int qtt_destroy(qtt_handle h);
 const char *qtt_status_string(int status);
 
+/* Sweep cap of the one-sided Jacobi SVD used by this handle's rounding,
+ * decomposition and batched calls (a batch plan reads it when it is
+ * created).  A call whose Jacobi iteration has not reached a sweep without
+ * rotations after max_sweeps sweeps returns QTT_ERR_NOCONV; one that
+ * reaches it on the last allowed sweep succeeds.  0 restores the default
+ * (80); negative values are QTT_ERR_ARG.  Not thread-safe against calls in
+ * flight on the same handle. */
+int qtt_set_jacobi_max_sweeps(qtt_handle h, int32_t max_sweeps);
+
 /* Operation codes for qtt_workspace_size. */
 typedef enum {
   QTT_OP_CONTRACT = 0,

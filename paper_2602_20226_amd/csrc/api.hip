@@ -25,6 +25,7 @@ using namespace qtt;
 
 struct qtt_context {
   int device;
+  int max_sweeps;       // Jacobi sweep cap of this handle's calls
   TruncOut* pin_trunc;  // pinned host readback
   int* pin_int;
   double* pin_dbl;
@@ -32,10 +33,11 @@ struct qtt_context {
 
 namespace {
 
-// Jacobi sweep cap.  Full-rank inputs converge in 10-15 sweeps; inputs with
-// exactly null directions (structurally rank-deficient super-cores of the
-// decomposition algorithm) need up to about 40, since the rows that collapse
-// to rounding level are made orthogonal only after the others have settled.
+// Default Jacobi sweep cap.  Full-rank inputs converge in 10-15 sweeps;
+// inputs with exactly null directions (structurally rank-deficient
+// super-cores of the decomposition algorithm) need up to about 40, since the
+// rows that collapse to rounding level are made orthogonal only after the
+// others have settled.  qtt_set_jacobi_max_sweeps changes it per handle.
 constexpr int kMaxSweeps = 80;
 constexpr int kMaxRows = 4096;
 
@@ -406,15 +408,15 @@ int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_in
     QTT_HIP(copy_pad_rows(w.st, X, p, L, L, Xc, p, L));
     QTT_HIP(row_norms_sorted(w.st, Xc, p, L, sig, perm));
     QTT_HIP(permute_rows(w.st, Xc, p, L, perm, X));
-    QTT_HIP(jacobi_rows(w.st, X, p, L, ctr, kMaxSweeps, sweeps, sig));  // sig[0]: largest row norm
+    QTT_HIP(jacobi_rows(w.st, X, p, L, ctr, w.h->max_sweeps, sweeps, sig));  // sig[0]: largest row norm
     QTT_HIP(row_norms_sorted(w.st, X, p, L, sig, perm));
     QTT_HIP(truncate_decide(w.st, sig, p, ws + P.offNorm, rel_tol, n - 1, max_rank, tr));
-    QTT_HIP(hipMemcpyAsync(w.h->pin_int, sweeps, sizeof(int), hipMemcpyDeviceToHost, w.st));
+    QTT_HIP(hipMemcpyAsync(w.h->pin_int, sweeps, 2 * sizeof(int), hipMemcpyDeviceToHost, w.st));
     int e = readback(w.h, w.st, tr, sizeof(TruncOut), w.h->pin_trunc);
     if (e) return e;
     const TruncOut t = *w.h->pin_trunc;
-    const int swp = *w.h->pin_int;
-    if (swp >= kMaxSweeps) return QTT_ERR_NOCONV;
+    const int swp = w.h->pin_int[0];
+    if (!w.h->pin_int[1]) return QTT_ERR_NOCONV;
     {
       double jb = 0.0, jf = 0.0;
       jacobi_sweep_cost(p, L, &jb, &jf);
@@ -740,6 +742,7 @@ struct qtt_batch {
   int variant = 0, grid = 0, maxL = 1;
   double tol = 0.0;
   long max_rank = 0;
+  int max_sweeps = 0;
   float tuned_ms[4] = {0, 0, 0, 0};
 };
 
@@ -761,8 +764,8 @@ hipError_t batch_run(qtt_batch* p, hipStream_t s, int variant) {
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->h->device);
   const int grid = std::min(p->count, cus * ((variant & 2) ? 2 : 1));
   p->grid = grid;
-  return batched_launch(s, variant, grid, p->dtab, p->dorder, p->count, p->dqueue, p->tol, p->max_rank, p->dranks,
-                        p->dtails, p->dstatus, p->maxL);
+  return batched_launch(s, variant, grid, p->dtab, p->dorder, p->count, p->dqueue, p->tol, p->max_rank,
+                        p->max_sweeps, p->dranks, p->dtails, p->dstatus, p->maxL);
 }
 
 }  // namespace
@@ -984,17 +987,17 @@ int zip_sweep(qtt_context* h, hipStream_t st, double* ws, const Shape& s, const 
       QTT_HIP(copy_pad_rows(st, X, p, L, L, Xc, p, L));
       QTT_HIP(row_norms_sorted(st, Xc, p, L, sig, perm));
       QTT_HIP(permute_rows(st, Xc, p, L, perm, X));
-      QTT_HIP(jacobi_rows(st, X, p, L, ctr, kMaxSweeps, sweeps, sig));  // sig[0]: largest row norm
+      QTT_HIP(jacobi_rows(st, X, p, L, ctr, h->max_sweeps, sweeps, sig));  // sig[0]: largest row norm
       QTT_HIP(row_norms_sorted(st, X, p, L, sig, perm));
       QTT_HIP(frob_norm(st, sig, p, nrm));  // ||S||_F of the super-core being split
       QTT_HIP(truncate_decide(st, sig, p, nrm, rel_tol, n - 1, max_rank, tr));
-      QTT_HIP(hipMemcpyAsync(h->pin_int, sweeps, sizeof(int), hipMemcpyDeviceToHost, st));
+      QTT_HIP(hipMemcpyAsync(h->pin_int, sweeps, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
       int e = readback(h, st, tr, sizeof(TruncOut), h->pin_trunc);
       if (e) return e;
       const TruncOut t = *h->pin_trunc;
-      const int swp = *h->pin_int;
+      const int swp = h->pin_int[0];
       if (!std::isfinite(t.norm)) return QTT_ERR_NONFINITE;
-      if (swp >= kMaxSweeps) return QTT_ERR_NOCONV;
+      if (!h->pin_int[1]) return QTT_ERR_NOCONV;
       {
         double jb = 0.0, jf = 0.0;
         jacobi_sweep_cost(p, L, &jb, &jf);
@@ -1241,12 +1244,19 @@ int qtt_create(qtt_handle* h, int device) {
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return QTT_ERR_NODEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return QTT_ERR_NODEVICE;
   Scoped sc(device);
+  // kernels with more than 64 KiB of dynamic LDS get their limit raised on
+  // this device before any launch
+  if (configure_kernels() != hipSuccess) return QTT_ERR_HIP;
   qtt_context* c = new (std::nothrow) qtt_context();
   if (!c) return QTT_ERR_ARG;
   c->device = device;
+  c->max_sweeps = kMaxSweeps;
   if (hipHostMalloc((void**)&c->pin_trunc, sizeof(TruncOut), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->pin_int, 64, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->pin_dbl, 64, hipHostMallocDefault) != hipSuccess) {
+    if (c->pin_trunc) (void)hipHostFree(c->pin_trunc);
+    if (c->pin_int) (void)hipHostFree(c->pin_int);
+    if (c->pin_dbl) (void)hipHostFree(c->pin_dbl);
     delete c;
     return QTT_ERR_HIP;
   }
@@ -1256,10 +1266,17 @@ int qtt_create(qtt_handle* h, int device) {
 
 int qtt_destroy(qtt_handle h) {
   if (!h) return QTT_ERR_ARG;
+  Scoped sc(h->device);
   (void)hipHostFree(h->pin_trunc);
   (void)hipHostFree(h->pin_int);
   (void)hipHostFree(h->pin_dbl);
   delete h;
+  return QTT_OK;
+}
+
+int qtt_set_jacobi_max_sweeps(qtt_handle h, int32_t max_sweeps) {
+  if (!h || max_sweeps < 0 || max_sweeps > 100000) return QTT_ERR_ARG;
+  h->max_sweeps = max_sweeps == 0 ? kMaxSweeps : max_sweeps;
   return QTT_OK;
 }
 
@@ -1635,6 +1652,7 @@ int qtt_batch_plan_create(qtt_handle h, const char* spec, int32_t count, const q
   p->count = count;
   p->tol = rel_tol;
   p->max_rank = max_rank;
+  p->max_sweeps = h->max_sweeps;
   p->maxL = Lo.maxL;
   p->dtab = (BInst*)(base + Lo.offTab);
   p->dorder = (int*)(base + Lo.offOrder);

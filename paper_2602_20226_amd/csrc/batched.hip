@@ -150,16 +150,39 @@ __device__ __forceinline__ int rr_item(int pos, int round, int n) {
 // rows, block pairs visited sequentially in the round-robin order, each pair
 // staged in LDS with its squared row norms.  A visit rotates the JB x JB cross pairs (JB steps of JB
 // disjoint pairs, waves taking pairs in turn); the pairs inside each block
-// are rotated once per sweep, in the first round.  Returns the sweep count
-// (max_sweeps when not converged).
+// are rotated once per sweep, in the first round.  Returns the sweeps
+// executed when a sweep without rotations was reached within max_sweeps,
+// -1 otherwise.
 constexpr int JEMAX = 12;  // row elements per lane: L <= 768
 
 // Rotate rows xa, xc (LDS, length L) whose squared norms *na, *nc (LDS) are
 // carried through the visit: one dot product and one wave sum per pair, each
 // row read once; the new norms are ||a||^2 - t a.c and ||c||^2 + t a.c.
+// A nonzero row whose squared norm is below negl is set to zero instead of
+// being rotated (same rule as the single-chain Jacobi: a row that has become
+// an exact tiny multiple of another cannot be rotated away).
 __device__ __forceinline__ int wg_rotate(double* __restrict__ xa, double* __restrict__ xc, double* __restrict__ na,
-                                         double* __restrict__ nc, int L, double tol) {
+                                         double* __restrict__ nc, int L, double tol, double negl) {
   const int lane = threadIdx.x & 63;
+  {
+    const double al = *na, be = *nc;
+    if (al < negl || be < negl) {
+      int changed = 0;
+      if (al < negl && al > 0.0) {
+        for (int c = lane; c < L; c += 64) xa[c] = 0.0;
+        changed = 1;
+      }
+      if (be < negl && be > 0.0) {
+        for (int c = lane; c < L; c += 64) xc[c] = 0.0;
+        changed = 1;
+      }
+      if (changed && lane == 0) {
+        if (al < negl) *na = 0.0;
+        if (be < negl) *nc = 0.0;
+      }
+      return changed;
+    }
+  }
   double u[JEMAX], w[JEMAX];
   double ga = 0.0;
 #pragma unroll
@@ -197,7 +220,20 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
   const int nb2 = nblk + (nblk & 1);
   const int npairs = nb2 / 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // deflation level: 2^-208 times the largest squared input row norm
+  {
+    double mx = 0.0;
+    for (int i = wave; i < p; i += NW) {
+      double s2 = 0.0;
+      for (int c = lane; c < L; c += 64) s2 += X[(long)i * L + c] * X[(long)i * L + c];
+      mx = fmax(mx, wave_sum_bc(s2));
+    }
+    if (lane == 0) sm.scal[12 + wave] = mx;
+    wg_sync();
+  }
+  const double negl = 0x1p-208 * fmax(fmax(sm.scal[12], sm.scal[13]), fmax(sm.scal[14], sm.scal[15]));
   int sweep = 0;
+  bool converged = false;
   for (; sweep < max_sweeps; ++sweep) {
     if (tid == 0) sm.iscal[0] = 0;
     wg_sync();
@@ -225,7 +261,7 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
             for (int q = wave; q < JB; q += NW) {
               const int blk = q / (JB / 2), i = q % (JB / 2);
               const int ta = blk * JB + rr_item(i, st, JB), tc = blk * JB + rr_item(JB - 1 - i, st, JB);
-              rot += wg_rotate(sh + ta * L, sh + tc * L, &sm.jn[ta], &sm.jn[tc], L, tol);
+              rot += wg_rotate(sh + ta * L, sh + tc * L, &sm.jn[ta], &sm.jn[tc], L, tol, negl);
             }
             wg_sync();
           }
@@ -234,7 +270,7 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
         for (int s = 0; s < JB; ++s) {
           for (int q = wave; q < JB; q += NW) {
             const int tc = JB + (q + s) % JB;
-            rot += wg_rotate(sh + q * L, sh + tc * L, &sm.jn[q], &sm.jn[tc], L, tol);
+            rot += wg_rotate(sh + q * L, sh + tc * L, &sm.jn[q], &sm.jn[tc], L, tol, negl);
           }
           wg_sync();
         }
@@ -250,11 +286,12 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
     const int tot = sm.iscal[0];
     wg_sync();
     if (tot == 0) {
+      converged = true;
       ++sweep;
       break;
     }
   }
-  return sweep;
+  return converged ? sweep : -1;
 }
 
 // sigma (sorted descending) and perm of the row norms of X (p x L).
@@ -285,7 +322,8 @@ __device__ void wg_norms_sort(const double* __restrict__ X, int p, int L, double
 }
 
 template <int JB>
-__device__ void process_instance(const BInst& I, double rel_tol, long max_rank, double* __restrict__ sh, Smem& sm,
+__device__ void process_instance(const BInst& I, double rel_tol, long max_rank, int max_sweeps, double* __restrict__ sh,
+                                 Smem& sm,
                                  long* __restrict__ ranks_out, double* __restrict__ tail_out, int* __restrict__ status) {
   const int n = I.n;
   double* ws = I.ws;
@@ -372,8 +410,8 @@ __device__ void process_instance(const BInst& I, double rel_tol, long max_rank, 
       p = rows;
     }
     wg_copy_pad(X, p, L, L, Xc, p, L);
-    const int sweeps = wg_jacobi<JB>(X, p, L, sh, QTT_BATCH_MAX_SWEEPS, eps * sqrt((double)L), sm);
-    if (sweeps >= QTT_BATCH_MAX_SWEEPS && tid == 0) status[0] = QTT_BSTATUS_NOCONV;
+    const int sweeps = wg_jacobi<JB>(X, p, L, sh, max_sweeps, eps * sqrt((double)L), sm);
+    if (sweeps < 0 && tid == 0) status[0] = QTT_BSTATUS_NOCONV;
     wg_norms_sort(X, p, L, sig, perm, tmp);
     // rank decision (smallest r with discarded 2-norm <= delta, capped)
     if (tid == 0) {
@@ -423,7 +461,7 @@ __device__ void process_instance(const BInst& I, double rel_tol, long max_rank, 
 template <int JB>
 __global__ __launch_bounds__(BNT) void k_batched(const BInst* __restrict__ insts, const int* __restrict__ order,
                                                  int count, unsigned* __restrict__ queue, double rel_tol,
-                                                 long max_rank, long* __restrict__ ranks_out,
+                                                 long max_rank, int max_sweeps, long* __restrict__ ranks_out,
                                                  double* __restrict__ tails_out, int* __restrict__ status) {
   extern __shared__ double sh[];
   __shared__ Smem sm;
@@ -435,7 +473,7 @@ __global__ __launch_bounds__(BNT) void k_batched(const BInst* __restrict__ insts
     __syncthreads();
     if (idx >= count) break;
     const int inst = order[idx];
-    process_instance<JB>(insts[inst], rel_tol, max_rank, sh, sm, ranks_out + (long)inst * (QTT_BATCH_MAXN + 1),
+    process_instance<JB>(insts[inst], rel_tol, max_rank, max_sweeps, sh, sm, ranks_out + (long)inst * (QTT_BATCH_MAXN + 1),
                          tails_out + (long)inst * QTT_BATCH_MAXN, status + inst);
     __syncthreads();
   }
@@ -443,31 +481,28 @@ __global__ __launch_bounds__(BNT) void k_batched(const BInst* __restrict__ insts
 
 }  // namespace
 
+hipError_t batched_configure() {
+  // up to 96 KiB of dynamic LDS (the Jacobi visit's 2 JB rows); raised for
+  // both instances when a handle is created
+  hipError_t e = hipFuncSetAttribute((const void*)k_batched<4>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_batched<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+}
+
 hipError_t batched_launch(hipStream_t s, int variant, int grid, const BInst* insts, const int* order, int count,
-                          unsigned* queue, double rel_tol, long max_rank, long* ranks_out, double* tails_out,
-                          int* status, int max_L) {
+                          unsigned* queue, double rel_tol, long max_rank, int max_sweeps, long* ranks_out,
+                          double* tails_out, int* status, int max_L) {
   hipError_t e = fill_u32(s, queue, 0u, 1);
   if (e != hipSuccess) return e;
   const int jb = (variant & 1) ? 4 : 8;
   const size_t shmem = (size_t)2 * jb * max_L * sizeof(double);
   if (shmem > 96 * 1024) return hipErrorInvalidValue;
-  static bool attr4 = false, attr8 = false;
   if (jb == 4) {
-    if (!attr4) {
-      e = hipFuncSetAttribute((const void*)k_batched<4>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-      if (e != hipSuccess) return e;
-      attr4 = true;
-    }
     hipLaunchKernelGGL(k_batched<4>, dim3(grid), dim3(BNT), shmem, s, insts, order, count, queue, rel_tol, max_rank,
-                       ranks_out, tails_out, status);
+                       max_sweeps, ranks_out, tails_out, status);
   } else {
-    if (!attr8) {
-      e = hipFuncSetAttribute((const void*)k_batched<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-      if (e != hipSuccess) return e;
-      attr8 = true;
-    }
     hipLaunchKernelGGL(k_batched<8>, dim3(grid), dim3(BNT), shmem, s, insts, order, count, queue, rel_tol, max_rank,
-                       ranks_out, tails_out, status);
+                       max_sweeps, ranks_out, tails_out, status);
   }
   return hipGetLastError();
 }

@@ -6,7 +6,6 @@
 namespace qtt {
 
 constexpr int QTT_BATCH_MAXN = 32;        // cores per instance
-constexpr int QTT_BATCH_MAX_SWEEPS = 40;  // Jacobi sweep cap
 constexpr int QTT_BSTATUS_OK = 0, QTT_BSTATUS_NONFINITE = 1, QTT_BSTATUS_NOCONV = 2;
 
 struct BInst {
@@ -25,9 +24,10 @@ struct BInst {
 };
 
 // Reset the work queue and launch the persistent kernel (variant bit 0:
-// Jacobi blocks of 4 rows instead of 8).  max_L bounds the Jacobi row length.
+// Jacobi blocks of 4 rows instead of 8).  max_L bounds the Jacobi row length;
+// max_sweeps caps each Jacobi iteration (status NOCONV when reached).
 hipError_t batched_launch(hipStream_t s, int variant, int grid, const BInst* insts, const int* order, int count,
-                          unsigned* queue, double rel_tol, long max_rank, long* ranks_out, double* tails_out,
-                          int* status, int max_L);
+                          unsigned* queue, double rel_tol, long max_rank, int max_sweeps, long* ranks_out,
+                          double* tails_out, int* status, int max_L);
 
 }  // namespace qtt

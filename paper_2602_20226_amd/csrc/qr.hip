@@ -487,6 +487,8 @@ inline Scr scr_of(double* scratch, long ncols) {
   return r;
 }
 
+constexpr int kPanelBigLds = 512 * 17 * 8;  // k_qr_panel<512, 4, 16>: 512 x 17 doubles of staging
+
 hipError_t launch_panel(hipStream_t s, double* A, long lda, int m, int j0, int pw, PanelCfg c, double* T,
                         double* tau) {
   if (prof::active(prof::QR_PANEL)) {
@@ -494,13 +496,9 @@ hipError_t launch_panel(hipStream_t s, double* A, long lda, int m, int j0, int p
     prof::begin(s, prof::QR_PANEL, 8.0 * 2.0 * mp * pw, 4.0 * mp * pw * pw);
   }
   const size_t sh = (size_t)c.nt * (c.pw + 1) * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {  // 512 x 17 doubles of staging exceed the default 64 KiB
-    hipError_t e = hipFuncSetAttribute((const void*)k_qr_panel<512, 4, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       512 * 17 * 8);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // only the 512-thread, 16-column instance stages more than the default
+  // 64 KiB; its limit is raised by qr_configure() when a handle is created
+  if (sh > (c.nt == 512 && c.pw == 16 ? kPanelBigLds : 64 * 1024)) return hipErrorInvalidValue;
   if (c.nt == 256 && c.rpt == 1)
     hipLaunchKernelGGL((k_qr_panel<256, 1, 16>), dim3(1), dim3(256), sh, s, A, lda, m, j0, pw, T, tau);
   else if (c.nt == 256 && c.rpt == 2)
@@ -576,6 +574,11 @@ inline hipError_t for_each_outer(int kmax, F f) {
 }
 
 }  // namespace
+
+hipError_t qr_configure() {
+  return hipFuncSetAttribute((const void*)k_qr_panel<512, 4, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             kPanelBigLds);
+}
 
 long qr_t_doubles(int m, int n) { return (long)ceil_div(std::min(m, n), OB) * OB * OB; }
 

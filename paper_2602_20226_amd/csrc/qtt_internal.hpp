@@ -88,9 +88,11 @@ hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, do
 // ---------------------------------------------------------------- SVD
 // One-sided Jacobi on the rows of X (p x L, row-major, ld L): on return the
 // rows are mutually orthogonal (X <- Z^T X, Z orthogonal, not formed).
-// counter: 8 + ceil(p / 8) unsigned of device scratch (cleared by the routine).  Sweeps
-// used go to *sweeps_dev.  ref_norm (device, nullable): the largest input row
-// norm; rows whose norm falls below eps^2 times it are deflated to zero.
+// counter: 8 + ceil(p / 8) unsigned of device scratch (cleared by the routine).
+// sweeps_dev[0] receives the sweeps executed, sweeps_dev[1] 1 if a sweep
+// without rotations was reached within max_sweeps (converged), else 0.
+// ref_norm (device, nullable): the largest input row norm; rows whose norm
+// falls below eps^2 times it are deflated to zero.
 // Algorithmic bytes and FLOP of one Jacobi sweep on p rows of length L.
 void jacobi_sweep_cost(int p, int L, double* bytes, double* flops);
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
@@ -128,6 +130,19 @@ hipError_t truncate_decide(hipStream_t s, const double* sig, int cnt, const doub
 hipError_t gather_rows_normalized(hipStream_t s, const double* X, int L, const int* perm, const double* sig,
                                   const TruncOut* t, double* out, long ldo, int rmax_host);
 long qr_t_doubles(int m, int n);
+
+// ---------------------------------------------------------------- kernel setup
+// Raise the dynamic-LDS limit of the kernels that stage more than 64 KiB
+// (on the current device); called once per handle before any launch.
+hipError_t qr_configure();
+hipError_t jacobi_configure();
+hipError_t batched_configure();
+inline hipError_t configure_kernels() {
+  hipError_t e = qr_configure();
+  if (e == hipSuccess) e = jacobi_configure();
+  if (e == hipSuccess) e = batched_configure();
+  return e;
+}
 
 // ---------------------------------------------------------------- launch profiling
 namespace prof {

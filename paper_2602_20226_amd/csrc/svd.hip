@@ -141,7 +141,7 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   unsigned* ver = ctr + JCTR;
   unsigned local_rot = 0;
-  int sweep = 0;
+  int sweep = 0, converged = 0;
   for (; sweep < max_sweeps; ++sweep) {
     for (int round = 0; round < nrounds; ++round) {
       const int b0 = rr_item(pair, round, nb2);
@@ -254,11 +254,17 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
     }
     __syncthreads();
     if (s_tot == 0) {
+      converged = 1;
       ++sweep;
       break;
     }
   }
-  if (blockIdx.x == 0 && tid == 0) sweeps_out[0] = sweep;
+  // sweeps executed (the last one without any rotation when converged) and
+  // whether a sweep without rotations was reached within the cap
+  if (blockIdx.x == 0 && tid == 0) {
+    sweeps_out[0] = sweep;
+    sweeps_out[1] = converged;
+  }
 }
 
 // sigma_i = ||X_i||, perm sorts them descending (ties by index).
@@ -362,7 +368,13 @@ inline int gsz(long n) {
   return (int)g;
 }
 
+constexpr int kJacobiBigLds = 2 * JB * 64 * 16 * 8;  // k_jacobi<16>: 16 row slots of 1024 doubles
+
 }  // namespace
+
+hipError_t jacobi_configure() {
+  return hipFuncSetAttribute((const void*)k_jacobi<16>, hipFuncAttributeMaxDynamicSharedMemorySize, kJacobiBigLds);
+}
 
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
                        int* sweeps_dev, const double* ref_norm) {
@@ -390,14 +402,9 @@ hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter
     fn = (const void*)k_jacobi<16>, E = 16;
   }
   const size_t shmem = (size_t)2 * JB * 64 * E * sizeof(double);
-  if (shmem > 64 * 1024) {
-    static bool attr_set = false;  // only the E = 16 instance needs more than 64 KiB
-    if (!attr_set) {
-      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
-  }
+  // only the E = 16 instance needs more than 64 KiB; jacobi_configure()
+  // raises its limit when a handle is created
+  if (shmem > (E == 16 ? kJacobiBigLds : 64 * 1024)) return hipErrorInvalidValue;
   // Work is recorded per sweep by the caller once the sweep count is known
   // (jacobi_sweep_cost); the launch itself is only timed here.
   if (prof::active(prof::JACOBI)) prof::begin(s, prof::JACOBI, 0.0, 0.0);

@@ -7,9 +7,11 @@ The names follow include/qtt.h.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
 import os
+import weakref
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -34,7 +36,7 @@ EXPORTS = [
     "qtt_contract_backward", "qtt_profile_start", "qtt_profile_stop", "qtt_batch_workspace_size",
     "qtt_batch_plan_create", "qtt_batch_plan_launch", "qtt_batch_plan_results", "qtt_batch_plan_info",
     "qtt_batch_plan_destroy", "qtt_contract_zipup", "qtt_zipup_query", "qtt_add",
-    "qtt_fit", "qtt_fit_workspace_size",
+    "qtt_fit", "qtt_fit_workspace_size", "qtt_set_jacobi_max_sweeps",
 ]
 
 
@@ -113,13 +115,35 @@ def load_library():
     L.qtt_fit_workspace_size.argtypes = [C.c_char_p, P(TT), P(TT), P(TT), P(C.c_size_t)]
     L.qtt_add.argtypes = [vp, C.c_int32, P(TT), P(C.c_double), P(TT), vp]
     L.qtt_zipup_query.argtypes = [C.c_char_p, P(TT), P(TT), C.c_int64, C.c_int32, P(C.c_int64), P(C.c_size_t)]
+    L.qtt_set_jacobi_max_sweeps.argtypes = [vp, C.c_int32]
     L.qtt_profile_start.argtypes = [vp, C.c_int, C.c_int]
     L.qtt_profile_stop.argtypes = [vp, P(C.c_int64), P(C.c_double), P(C.c_double), P(C.c_double)]
     for name in EXPORTS:
         if name != "qtt_status_string":
             getattr(L, name).restype = C.c_int
     _lib = L
+    atexit.register(_release_all)
     return L
+
+
+_plans = weakref.WeakSet()
+
+
+def _release_all():
+    """Destroy batch plans, then handles, at interpreter exit while the HIP
+    runtime is still alive (instead of leaving it to __del__ during module
+    teardown, whose order is unspecified)."""
+    for p in list(_plans):
+        try:
+            p.close()
+        except Exception:
+            pass
+    for h in list(_handles.values()):
+        try:
+            h.close()
+        except Exception:
+            pass
+    _handles.clear()
 
 
 def _status_string(st: int) -> str:
@@ -170,6 +194,12 @@ def handle(device: Optional[int] = None) -> Handle:
         h = Handle(device)
         _handles[device] = h
     return h
+
+
+def set_jacobi_max_sweeps(max_sweeps: int, device: Optional[int] = None):
+    """Sweep cap of the Jacobi SVD for this device's handle (0: default)."""
+    _check(load_library().qtt_set_jacobi_max_sweeps(handle(device).ptr, int(max_sweeps)),
+           "qtt_set_jacobi_max_sweeps")
 
 
 @dataclass
@@ -573,6 +603,7 @@ class BatchPlan:
         _check(L.qtt_batch_plan_create(self.h.ptr, spec.encode(), self.count, ta, tb, to, float(rel_tol),
                                        int(max_rank), 1 if tune else 0, C.c_void_p(self.ws.data_ptr()),
                                        self.ws.numel(), _stream_ptr(), C.byref(self._plan)), "qtt_batch_plan_create")
+        _plans.add(self)
 
     def launch(self):
         _check(load_library().qtt_batch_plan_launch(self._plan, _stream_ptr()), "qtt_batch_plan_launch")

@@ -191,7 +191,7 @@ def check_round(got, ref_cores, ref_info, tol=1e-12, sig_tol=1e-12, ranks_exact=
     gh = host(got.cores)
     assert got.ranks[0] == 1 and got.ranks[-1] == 1
     if ranks_exact:
-        assert ranks_agree(got.ranks, ref_info.ranks, ref_info.sigmas), (got.ranks, ref_info.ranks)
+        assert ranks_agree(got.ranks, ref_info), (got.ranks, ref_info.ranks)
     err = O.rel_error(gh, ref_cores)
     assert err <= tol, err
     # right-orthonormal cores 2..n
@@ -306,3 +306,32 @@ def test_laplacian_eigenvector_full_size(m, D):
     got = Q.contract_round("ij,j->i", dev(W), dev(f), 1e-12, 0)
     assert max(got.ranks) == 2 ** D
     assert O.rel_error(host(got.cores), O.tt_scale(f, lam)) <= 1e-12
+
+
+# ------------------------------------------------------------------ Jacobi sweep cap
+def test_jacobi_sweep_cap_edge_and_noconv():
+    """A rounding whose Jacobi needs s sweeps succeeds with the cap at s (it
+    converges on its last allowed sweep) and fails with QTT_ERR_NOCONV at
+    s - 1; the handle's cap is restored afterwards."""
+    log("jacobi sweep cap")
+    rng = np.random.default_rng(77)
+    X = [rng.standard_normal(s) for s in [(1, 2, 8), (8, 2, 24), (24, 2, 24), (24, 2, 8), (8, 2, 1)]]
+    try:
+        got = Q.round_tt(dev(X), 1e-10, 0)
+        s = got.jacobi_sweeps_max
+        assert 2 <= s < 80
+        Q.set_jacobi_max_sweeps(s)
+        again = Q.round_tt(dev(X), 1e-10, 0)
+        assert again.ranks == got.ranks and again.jacobi_sweeps_max == s
+        Q.set_jacobi_max_sweeps(s - 1)
+        with pytest.raises(Q.QttError) as ei:
+            Q.round_tt(dev(X), 1e-10, 0)
+        assert ei.value.status == -9
+        Q.set_jacobi_max_sweeps(1)
+        Y = [rng.standard_normal(s) for s in [(1, 2, 2), (2, 2, 2), (2, 2, 2), (2, 2, 2), (2, 2, 1)]]
+        with pytest.raises(Q.QttError) as ei:
+            Q.contract_zipup("i,i->i", dev(X), dev(Y), 1e-10, 0, ncores=1)
+        assert ei.value.status == -9
+    finally:
+        Q.set_jacobi_max_sweeps(0)
+    assert Q.round_tt(dev(X), 1e-10, 0).jacobi_sweeps_max == s
