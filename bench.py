@@ -164,7 +164,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="bf16x6", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--no-fp64-leg", action="store_true")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (its timing and the error of the timed result against it)")
+    ap.add_argument("--no-amplification", action="store_true",
+                    help="skip the oracle's noise-amplification estimate of the rounding")
     ap.add_argument("--no-kernel-breakdown", action="store_true",
                     help="skip the per-class profiled steps (and the roofline object)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -237,6 +240,8 @@ def main():
         return (time.perf_counter() - t0) / steps, res
 
     sec, res = timed(args.prec, args.steps, args.warmup)
+    # host copies of the timed results (the output buffers are reused below)
+    got = (Q.to_host(res.cores), list(res.ranks))
     if zipup:
         flops = zipup_flops(ra, rb, d, dj, res.ranks, args.ncores)
         metric = ("QTT contract+truncate by zip-up TFLOP/s (3D Laplacian MPO x rank-256 MPS, n=42, "
@@ -263,8 +268,10 @@ def main():
         "ranks_out_max": max(res.ranks),
         "jacobi_sweeps_max": res.jacobi_sweeps_max,
     }
+    got64 = None
     if not args.no_fp64_leg and args.prec != "fp64":
         sec64, res64 = timed("fp64", max(1, args.steps // 2), 1)
+        got64 = (Q.to_host(res64.cores), list(res64.ranks))
         out["fp64_ms_per_step"] = sec64 * 1e3
         out["speedup_vs_fp64_path"] = sec64 / sec
 
@@ -284,7 +291,23 @@ def main():
         del src_t, dst_t
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, ra, rb, d, dj, args.ncores if zipup else 0)
+        base, ref, ref_info, C_exact = cpu_baseline(w, ra, rb, d, dj, args.ncores if zipup else 0)
+        out["cpu_baseline"] = base
+        # the timed results against the oracle's result of the same workload
+        import oracle as O
+        out["rel_err_vs_oracle"] = O.rel_error(got[0], ref)
+        out["ranks_identical"] = got[1] == ref_info.ranks
+        if got64 is not None:
+            out["fp64_rel_err_vs_oracle"] = O.rel_error(got64[0], ref)
+            out["fp64_ranks_identical"] = got64[1] == ref_info.ranks
+        gaps = [g for g in ref_info.gaps if math.isfinite(g)]
+        out["oracle_min_cut_gap"] = min(gaps) if gaps else None
+        if C_exact is not None and not args.no_amplification:
+            # how much the rounding magnifies a relative input change of 1e-7
+            # (the size of the reduced-precision GEMM error): one perturbed
+            # oracle rounding of the exact product
+            amp, _ = O.noise_amplification(C_exact, w.rel_tol, w.max_rank, eps=1e-7, seed=5, trials=1)
+            out["oracle_amplification"] = amp
     print(json.dumps(out), flush=True)
 
 
@@ -339,10 +362,15 @@ def bench_batch(args, I, Q, torch, dev):
         except Exception:
             threads = os.cpu_count() or 1
         sample = list(range(0, len(w.a), 8))
+        refs = {}
         t0 = time.perf_counter()
         for i in sample:
-            O.round_tt(O.contract(w.spec, w.a[i], w.b[i]), w.rel_tol, w.max_rank)
+            refs[i] = O.round_tt(O.contract(w.spec, w.a[i], w.b[i]), w.rel_tol, w.max_rank, return_info=True)
         dt = time.perf_counter() - t0
+        # the timed result against the oracle on the same problems
+        out["rel_err_vs_oracle"] = max(O.rel_error(Q.to_host(plan.cores(i)), refs[i][0]) for i in sample)
+        out["ranks_identical"] = all(ranks[i] == refs[i][1].ranks for i in sample)
+        out["oracle_checked_problems"] = len(sample)
         out["cpu_baseline"] = {"value": sum(flops[i] for i in sample) / dt / 1e12, "unit": "TFLOP/s",
                                "cores": threads, "kind": "oracle",
                                "sample": f"every 8th problem ({len(sample)} of {len(w.a)}), NumPy FP64 + LAPACK",
@@ -593,15 +621,30 @@ def measured_traffic(kernel, alg_bytes_per_launch):
     return rec["ratio"] * alg_bytes_per_launch
 
 
-def cpu_baseline(w, ra, rb, d, dj, zipup_ncores=0):
-    """The FP64 oracle (NumPy + LAPACK) on this host's cores: one full
-    contract+round (or zip-up with super-cores of zipup_ncores cores)."""
-    import oracle as O
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
     except Exception:
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w, ra, rb, d, dj, zipup_ncores=0):
+    """The FP64 oracle (NumPy + LAPACK) on this host's cores.
+
+    value: one full contract+round (or zip-up with super-cores of
+    zipup_ncores cores) of the workload with every BLAS thread; its result
+    is returned as the reference for the GPU result.  Beside it, a bounded
+    sample timed with all threads and with one (median of 3 each): the
+    oracle's QR-sweep step on one interior bond of the workload (reduced
+    Householder QR of the (2 r_C) x r_C unfolding of the contracted core
+    C_21, R into the next core).  Returns (record, reference cores,
+    reference info, exact contracted train or None)."""
+    import numpy as np
+
+    import oracle as O
+    threads = _blas_threads()
+    C = None
     t0 = time.perf_counter()
     if zipup_ncores:
         Y, info = O.zipup(w.spec, w.a, w.b, w.rel_tol, w.max_rank, ncores=zipup_ncores, return_info=True)
@@ -614,9 +657,40 @@ def cpu_baseline(w, ra, rb, d, dj, zipup_ncores=0):
         dt = time.perf_counter() - t0
         flops = contract_round_flops(ra, rb, d, dj, info.ranks)
         what = "one full contract+round"
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what} of the same 42-core workload (NumPy FP64, LAPACK QR/SVD)",
-            "seconds": dt}
+    rec = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"{what} of the same 42-core workload (NumPy FP64, LAPACK QR/SVD), all BLAS threads",
+           "seconds": dt}
+    # bounded sample, all threads and one thread, median of 3
+    k = len(d) // 2
+    Ck = C[k] if C is not None else O.contract(w.spec, [w.a[k]], [w.b[k]])[0]
+    nxt = C[k + 1] if C is not None else O.contract(w.spec, [w.a[k + 1]], [w.b[k + 1]])[0]
+    sample = [Ck.reshape(1, -1, Ck.shape[-1]), nxt[:, :, :1]]  # the unfolding as a one-row core, then R C_{k+1}
+    m, c = Ck.shape[0] * Ck.shape[1], Ck.shape[-1]
+    q = min(m, c)
+    sflops = geqrf_flops(m, c) + (2.0 * m * q * q - 2.0 * q ** 3 / 3.0) + 2.0 * q * c * nxt.shape[1]  # geqrf+orgqr+R C
+
+    def med3():
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            O.orthogonalize(sample)
+            ts.append(time.perf_counter() - t)
+        return sorted(ts)[1]
+
+    t_all = med3()
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t_one = med3()
+        one = {"value": sflops / t_one / 1e12, "seconds_median": t_one, "cores": 1}
+    except Exception:
+        one = None
+    rec["bond_sample"] = {"what": f"QR-sweep step of one interior bond: QR of the {m} x {c} unfolding of C_{k + 1}, "
+                                  f"R into the next core (oracle.orthogonalize), median of 3",
+                          "gflop": sflops / 1e9,
+                          "all_threads": {"value": sflops / t_all / 1e12, "seconds_median": t_all, "cores": threads},
+                          "one_thread": one, "unit": "TFLOP/s"}
+    return rec, Y, info, C
 
 
 if __name__ == "__main__":
