@@ -156,6 +156,24 @@ int qtt_contract_round(qtt_handle h, const char *spec, const qtt_tt *a, const qt
                        double rel_tol, int64_t max_rank, int prec, qtt_round_info *info,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * contraction + rounding as qtt_contract_round, with its workspace in a
+ * fixed device array of QTT_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every device it runs on until the process ends (its address is taken
+ * once per device by qtt_create).  Allocates no device memory and calls no
+ * allocating routine; the caller still passes the operands and the output
+ * cores.  A product whose workspace (qtt_workspace_size, QTT_OP_CONTRACT_ROUND)
+ * exceeds the array is rejected with QTT_ERR_WORKSPACE before any launch.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (other host threads, or other streams before this call has
+ * returned) race and must not be issued.  Synchronous, like
+ * qtt_contract_round. */
+#define QTT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int qtt_contract_round_noalloc(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b,
+                               qtt_tt *out, double rel_tol, int64_t max_rank, int prec,
+                               qtt_round_info *info, void *stream);
+
 /* Decomposition ("zip-up") algorithm of Sec. 3.2 for the same products:
  * copies of both operands are first normalised to the left end (a
  * right-to-left QR sweep, cores 2..n right-orthonormal); a super-core of

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <sstream>
@@ -29,7 +30,38 @@ struct qtt_context {
   TruncOut* pin_trunc;  // pinned host readback
   int* pin_int;
   double* pin_dbl;
+  void* scratch;        // device address of this device's copy of `scratch`
 };
+
+// Workspace of qtt_contract_round_noalloc: one fixed array per device, held
+// until the process ends.  Host code never uses the name `scratch` as an
+// address (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, once per device, in qtt_create.
+static_assert(QTT_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) double scratch[QTT_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device` (looked up on
+// the first call for that device).
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_dev[device] = ptr;
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -1251,6 +1283,10 @@ int qtt_create(qtt_handle* h, int device) {
   if (!c) return QTT_ERR_ARG;
   c->device = device;
   c->max_sweeps = kMaxSweeps;
+  if (scratch_address(device, &c->scratch) != hipSuccess) {
+    delete c;
+    return QTT_ERR_HIP;
+  }
   if (hipHostMalloc((void**)&c->pin_trunc, sizeof(TruncOut), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->pin_int, 64, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->pin_dbl, 64, hipHostMallocDefault) != hipSuccess) {
@@ -1462,11 +1498,7 @@ int qtt_round(qtt_handle h, qtt_tt* t, double rel_tol, int64_t max_rank, int pre
   return round_common(h, s, t, nullptr, nullptr, t, rel_tol, max_rank, prec, info, ws, ws_bytes, stream);
 }
 
-int qtt_contract_round(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* out,
-                       double rel_tol, int64_t max_rank, int prec, qtt_round_info* info, void* ws, size_t ws_bytes,
-                       void* stream) {
-  if (!h) return QTT_ERR_ARG;
-  Shape s;
+static int contract_round_args(const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt* out, Shape& s) {
   int st = shape_from_pair(spec, a, b, s);
   if (st) return st;
   if (a->dtype != QTT_F64 || b->dtype != QTT_F64) return QTT_ERR_DTYPE;
@@ -1474,7 +1506,31 @@ int qtt_contract_round(qtt_handle h, const char* spec, const qtt_tt* a, const qt
   if (out->dtype != QTT_F64) return QTT_ERR_DTYPE;
   for (int k = 0; k < out->n; ++k)
     if (!out->cores[k]) return QTT_ERR_ARG;
+  return QTT_OK;
+}
+
+int qtt_contract_round(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* out,
+                       double rel_tol, int64_t max_rank, int prec, qtt_round_info* info, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (!h) return QTT_ERR_ARG;
+  Shape s;
+  int st = contract_round_args(spec, a, b, out, s);
+  if (st) return st;
   return round_common(h, s, nullptr, a, b, out, rel_tol, max_rank, prec, info, ws, ws_bytes, stream);
+}
+
+int qtt_contract_round_noalloc(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* out,
+                               double rel_tol, int64_t max_rank, int prec, qtt_round_info* info, void* stream) {
+  if (!h) return QTT_ERR_ARG;
+  if (!h->scratch) return QTT_ERR_HIP;
+  Shape s;
+  int st = contract_round_args(spec, a, b, out, s);
+  if (st) return st;
+  // the same sweeps as qtt_contract_round on this device's fixed array;
+  // round_common rejects a plan larger than the array with QTT_ERR_WORKSPACE
+  // before anything is launched
+  return round_common(h, s, nullptr, a, b, out, rel_tol, max_rank, prec, info, h->scratch,
+                      (size_t)QTT_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 int qtt_inner(qtt_handle h, const qtt_tt* a, const qtt_tt* b, double* out_host, void* ws, size_t ws_bytes,

@@ -36,8 +36,10 @@ EXPORTS = [
     "qtt_contract_backward", "qtt_profile_start", "qtt_profile_stop", "qtt_batch_workspace_size",
     "qtt_batch_plan_create", "qtt_batch_plan_launch", "qtt_batch_plan_results", "qtt_batch_plan_info",
     "qtt_batch_plan_destroy", "qtt_contract_zipup", "qtt_zipup_query", "qtt_add",
-    "qtt_fit", "qtt_fit_workspace_size", "qtt_set_jacobi_max_sweeps",
+    "qtt_fit", "qtt_fit_workspace_size", "qtt_set_jacobi_max_sweeps", "qtt_contract_round_noalloc",
 ]
+# size of the fixed device array behind qtt_contract_round_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class QttError(RuntimeError):
@@ -99,6 +101,8 @@ def load_library():
     L.qtt_round.argtypes = [vp, P(TT), C.c_double, C.c_int64, C.c_int, P(RoundInfoC), vp, C.c_size_t, vp]
     L.qtt_contract_round.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_double, C.c_int64, C.c_int,
                                      P(RoundInfoC), vp, C.c_size_t, vp]
+    L.qtt_contract_round_noalloc.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_double, C.c_int64, C.c_int,
+                                             P(RoundInfoC), vp]
     L.qtt_inner.argtypes = [vp, P(TT), P(TT), P(C.c_double), vp, C.c_size_t, vp]
     L.qtt_inner_backward.argtypes = [vp, P(TT), P(TT), C.c_double, P(TT), P(TT), vp, C.c_size_t, vp]
     L.qtt_contract_backward.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), P(TT), P(TT), vp, C.c_size_t, vp]
@@ -458,6 +462,36 @@ def contract_round(spec: str, a, b, rel_tol: float, max_rank: int = 0, prec: str
     ranks = vo.ranks()
     cores = _views_of_compact(out_buffers, ranks, d)
     return info.result(cores, ranks, n)
+
+
+def contract_round_noalloc(spec: str, a, b, rel_tol: float, max_rank: int, out_buffers: List[torch.Tensor],
+                           prec: str = "fp64") -> RoundResult:
+    """contract_round through the allocation-free entry point.
+
+    The caller passes the output buffers (each large enough for the rank
+    bounds of `rank_bounds`); the library's fixed device array is the
+    workspace, so nothing is allocated on the device by this call.
+    """
+    L = load_library()
+    h = handle(a[0].device.index)
+    va, vb = TTView(list(a), _legs(spec)), TTView(list(b), 1)
+    n = len(a)
+    d = [c.shape[1] for c in a]
+    rc = [x * y for x, y in zip(va.ranks(), vb.ranks())]
+    bnd = rank_bounds(rc, d, max_rank)
+    if len(out_buffers) != n:
+        raise ValueError("one output buffer per core")
+    for k in range(n):
+        if out_buffers[k].numel() < bnd[k] * d[k] * bnd[k + 1]:
+            raise ValueError(f"output buffer {k} smaller than its rank bound")
+    vo = TTView([x.reshape(-1) for x in out_buffers], 1, ranks_override=bnd, phys_override=d)
+    info = _Info(n)
+    _check(L.qtt_contract_round_noalloc(h.ptr, spec.encode(), C.byref(va.struct), C.byref(vb.struct),
+                                        C.byref(vo.struct), float(rel_tol), int(max_rank), PREC[prec],
+                                        C.byref(info.c), _stream_ptr()),
+           "qtt_contract_round_noalloc")
+    ranks = vo.ranks()
+    return info.result(_views_of_compact(out_buffers, ranks, d), ranks, n)
 
 
 def zipup_query(spec: str, a_struct: TT, b_struct: TT, max_rank: int = 0, ncores: int = 1):

@@ -64,6 +64,8 @@ def test_null_handle_rejected_by_compute_calls():
     assert L.qtt_contract(None, b"i,i->i", C.byref(a), C.byref(a), C.byref(a), None, 0, None) == -1
     assert L.qtt_round(None, C.byref(a), 1e-8, 0, 0, None, None, 0, None) == -1
     assert L.qtt_set_jacobi_max_sweeps(None, 5) == -1
+    assert L.qtt_contract_round_noalloc(None, b"i,i->i", C.byref(a), C.byref(a), C.byref(a), 1e-8, 0, 0,
+                                        None, None) == -1
 
 
 def ws(op, a, b=None, spec=None, max_rank=0, prec=0):
