@@ -22,7 +22,9 @@ numpy.linalg, written from the paper's definitions:
     the left end, then a super-core of N exact product cores split off one
     truncated-SVD core at a time while the next product core is added;
   * variational fitting of Sec. 3.3 (eq. variational): one core at a time,
-    the derivative of <C|Y> with every other core orthonormal;
+    the derivative of <C|Y> with every other core orthonormal, and the
+    multi-core strategy with super-cores of two cores, decomposed again by a
+    truncated SVD so that the ranks adapt;
   * sums of many trains (the block structure of Sec. 3.1, operators
     included) and the operator product 'ij,jk->ik';
   * general digit bases (factorised dimensions, Sec. 2): every function takes

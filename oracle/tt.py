@@ -22,6 +22,7 @@ __all__ = [
     "round_tt",
     "zipup",
     "fit",
+    "fit_two_core",
     "RoundInfo",
     "truncation_rank",
     "cut_gaps",
@@ -496,6 +497,75 @@ def fit(spec: str, A, B, C0, nsweeps: int = 1):
             else:
                 C[q] = P
             L.append(np.einsum("ab,aic,bid->cd", L[q], C[q], Y[q], optimize=True))
+    return C
+
+
+def fit_two_core(spec: str, A, B, C0, rel_tol: float = 0.0, max_rank: int = 0, nsweeps: int = 1,
+                 return_info: bool = False):
+    """Variational fitting with super-cores of two adjacent cores (Sec. 3.3,
+    multi-core strategy): the ranks of C adapt to the product
+    Y = contract(spec, A, B).
+
+    With the cores left of the pair (q, q+1) left-orthonormal and those right
+    of it right-orthonormal, the best super-core is the derivative of <C|Y>
+    with respect to it (eq. variational applied to the fused pair):
+    S[a, i, j, c] = sum L_{q-1}[a, b] Y_q[b, i, d] Y_{q+1}[d, j, e] R_{q+2}[c, e].
+    S is then decomposed again by a truncated SVD of its (r_a i) x (j r_c)
+    unfolding, keeping the smallest rank r whose discarded singular values
+    have 2-norm <= delta = rel_tol * ||S||_F / sqrt(n-1), capped at max_rank.
+    The guess is first orthogonalised from the left (centre at core n), so
+    a sweep runs over the pairs from the right end to the left -- core q+1
+    becomes V^T, core q takes U Sigma -- and back from the left, core q
+    becoming U and core q+1 Sigma V^T.  Returns the cores (and, with
+    return_info, the ranks and the discarded tail of each split)."""
+    Y = [_mat(c) for c in contract(spec, A, B)]
+    C, _ = orthogonalize(C0)
+    C = [_mat(c).copy() for c in C]
+    n = len(C)
+    if n == 1:
+        out = [Y[0].copy()]
+        return (out, {"ranks": [1, 1], "tails": []}) if return_info else out
+    one = np.ones((1, 1))
+    tails = []
+
+    def split(S, q, left_orthonormal):
+        a, i, j, c = S.shape
+        U, sg, Vt = np.linalg.svd(S.reshape(a * i, j * c), full_matrices=False)
+        delta = rel_tol * float(np.linalg.norm(sg)) / math.sqrt(n - 1)
+        r, t_r, _, _ = truncation_rank(sg, delta, max_rank)
+        tails.append(t_r)
+        if left_orthonormal:
+            C[q] = U[:, :r].reshape(a, i, r)
+            C[q + 1] = (sg[:r, None] * Vt[:r]).reshape(r, j, c)
+        else:
+            C[q] = (U[:, :r] * sg[None, :r]).reshape(a, i, r)
+            C[q + 1] = Vt[:r].reshape(r, j, c)
+
+    def supercore(Lq, q, Rq2):
+        return np.einsum("ab,bid,dje,ce->aijc", Lq, Y[q], Y[q + 1], Rq2, optimize=True)
+
+    def left_env(Lq, q):
+        return np.einsum("ab,aic,bid->cd", Lq, C[q], Y[q], optimize=True)
+
+    def right_env(Rq1, q):
+        return np.einsum("aic,bid,cd->ab", C[q], Y[q], Rq1, optimize=True)
+
+    for _ in range(nsweeps):
+        L = [one]
+        for q in range(n - 2):
+            L.append(left_env(L[q], q))
+        R = [None] * (n + 1)
+        R[n] = one
+        for q in range(n - 2, -1, -1):  # pairs (q, q+1) from the right end
+            split(supercore(L[q], q, R[q + 2]), q, left_orthonormal=False)
+            R[q + 1] = right_env(R[q + 2], q + 1)
+        L = [one]
+        for q in range(n - 1):  # and back from the left end
+            split(supercore(L[q], q, R[q + 2]), q, left_orthonormal=True)
+            L.append(left_env(L[q], q))
+    ranks = [1] + [c.shape[-1] for c in C]
+    if return_info:
+        return C, {"ranks": ranks, "tails": tails}
     return C
 
 
