@@ -588,7 +588,7 @@ def inner(A, B) -> float:
     E = np.ones((1, 1))
     for a, b in zip(A, B):
         a3, b3 = _mat(a), _mat(b)
-        E = np.einsum("ab,aic,bid->cd", E, a3, b3)
+        E = sum(a3[:, i, :].T @ E @ b3[:, i, :] for i in range(a3.shape[1]))
     return float(E[0, 0])
 
 
