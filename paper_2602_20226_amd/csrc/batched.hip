@@ -7,17 +7,22 @@
 // ones start first and the small ones fill the tail.  A workgroup runs the
 // whole pipeline of its instance with workgroup-level versions of the
 // single-chain steps:
-//   QR sweep:  bond product R_{k-1} C_k (factored, FP32 accumulation),
-//              blocked Householder QR (qr_panel_dev + apply_tile_dev);
+//   QR sweep:  bond product R_{k-1} C_k (factored: R X_k, then the A or
+//              W core), blocked Householder QR (qr_panel_dev + apply_tile_dev);
 //   SVD sweep: Q_k [U Sigma; 0], QR of tall unfoldings, one-sided block
 //              Jacobi on the rows, device-side rank decision, V^T into the
-//              output core and U Sigma = F V (FP32 accumulation).
+//              output core and U Sigma = F V.
+// The three product steps (R X_k, the core product, F V) run on the bf16
+// matrix cores (wg_gemm.hpp: six products of a three-piece split, FP32
+// accumulation inside each 32-deep step, FP64 across steps), with the tile
+// shape of each shape bucket taken from the plan's TileMap.
 // Ranks never leave the device during the launch, so the launch (with the
 // queue reset before it) can be captured in a hipGraph and replayed.
 #include "qtt_device.hpp"
 #include "qtt_internal.hpp"
 #include "qr_device.hpp"
 #include "batched.hpp"
+#include "wg_gemm.hpp"
 
 namespace qtt {
 
@@ -26,7 +31,10 @@ namespace {
 constexpr int BNT = 256;
 
 struct Smem {
-  double red[BNT / 16][16][17];
+  union {  // the QR's tile reductions, or the staging of a matrix-core GEMM step
+    double red[BNT / 16][16][17];
+    GemmTiles gt;
+  };
   double wsh[16][17];
   double w2sh[16][17];
   double tsh[16][17];
@@ -37,59 +45,50 @@ struct Smem {
 
 __device__ __forceinline__ void wg_sync() { __syncthreads(); }
 
-// Y = R (rows x K, ld ldr) * B (K x N, ld N)  accumulated in FP32, stored FP64
-__device__ void wg_gemm_nn_f32(int rows, int N, int K, const double* __restrict__ R, long ldr,
-                               const double* __restrict__ B, double* __restrict__ Y) {
-  const long total = (long)rows * N;
-  for (long e = threadIdx.x; e < total; e += BNT) {
-    const long i = e / N;
-    const int j = (int)(e % N);
-    float acc = 0.f;
-    for (int k = 0; k < K; ++k) acc += (float)R[i * ldr + k] * (float)B[(long)k * N + j];
-    Y[e] = (double)acc;
-  }
-  wg_sync();
+// Y = R (rows x K, ld ldr) * B (K x N, ld N)
+__device__ void wg_gemm_nn(const TileMap& tm, int rows, int N, int K, const double* __restrict__ R, long ldr,
+                           const double* __restrict__ B, double* __restrict__ Y, Smem& sm) {
+  wg_gemm_split(
+      tm, rows, N, K, [=](int m, int k) { return R[(long)m * ldr + k]; },
+      [=](int k, int n) { return B[(long)k * N + n]; }, [=](int m, int n, double v) { Y[(long)m * N + n] = v; },
+      sm.gt);
 }
 
-// Y (p x r) = F (p x L) * V^T, V = out core rows (r x L); FP32 accumulation
-__device__ void wg_gemm_nt_f32(int p, int r, int L, const double* __restrict__ F, const double* __restrict__ V,
-                               double* __restrict__ Y) {
-  const long total = (long)p * r;
-  for (long e = threadIdx.x; e < total; e += BNT) {
-    const long i = e / r;
-    const int j = (int)(e % r);
-    float acc = 0.f;
-    for (int c = 0; c < L; ++c) acc += (float)F[i * L + c] * (float)V[(long)j * L + c];
-    Y[e] = (double)acc;
-  }
-  wg_sync();
+// Y (p x r) = F (p x L) * V^T, V = out core rows (r x L)
+__device__ void wg_gemm_nt(const TileMap& tm, int p, int r, int L, const double* __restrict__ F,
+                           const double* __restrict__ V, double* __restrict__ Y, Smem& sm) {
+  wg_gemm_split(
+      tm, p, r, L, [=](int m, int k) { return F[(long)m * L + k]; },
+      [=](int k, int n) { return V[(long)n * L + k]; }, [=](int m, int n, double v) { Y[(long)m * r + n] = v; },
+      sm.gt);
 }
 
 // Hadamard bond: M[(a,i),(b,dd)] = sum_mu Y[a,mu,i,dd] A[mu,i,b]
 // MPO bond:      M[(a,i),(b,dd)] = sum_{mu,j} Y[a,mu,j,dd] W[mu,i,j,b]
-__device__ void wg_bond_apply(bool mpo, const double* __restrict__ Y, int rho, int ra0, int d, int dj, int rb1,
-                              const double* __restrict__ A, int ra1, double* __restrict__ M) {
-  const long total = (long)rho * d * ra1 * rb1;
-  for (long e = threadIdx.x; e < total; e += BNT) {
-    long t = e;
-    const int dd = t % rb1;
-    t /= rb1;
-    const int b = t % ra1;
-    t /= ra1;
-    const int i = t % d;
-    const long a = t / d;
-    float acc = 0.f;
-    if (mpo) {
-      for (int mu = 0; mu < ra0; ++mu)
-        for (int j = 0; j < dj; ++j)
-          acc += (float)Y[((a * ra0 + mu) * dj + j) * rb1 + dd] * (float)A[(((long)mu * d + i) * dj + j) * ra1 + b];
-    } else {
-      for (int mu = 0; mu < ra0; ++mu)
-        acc += (float)Y[((a * ra0 + mu) * d + i) * rb1 + dd] * (float)A[((long)mu * d + i) * ra1 + b];
+// One GEMM per (i, dd): rows a, columns b, depth (mu, j).
+__device__ void wg_bond_apply(const TileMap& tm, bool mpo, const double* __restrict__ Y, int rho, int ra0, int d,
+                              int dj, int rb1, const double* __restrict__ A, int ra1, double* __restrict__ M,
+                              Smem& sm) {
+  const int dk = mpo ? dj : 1;  // contracted physical leg per mu
+  const long ldo = (long)d * ra1 * rb1;
+  for (int i = 0; i < d; ++i)
+    for (int dd = 0; dd < rb1; ++dd) {
+      if (mpo) {
+        wg_gemm_split(
+            tm, rho, ra1, ra0 * dk,
+            [=](int a, int kk) { return Y[((long)a * ra0 * dk + kk) * rb1 + dd]; },
+            [=](int kk, int b) {
+              const int mu = kk / dk, j = kk % dk;
+              return A[(((long)mu * d + i) * dj + j) * ra1 + b];
+            },
+            [=](int a, int b, double v) { M[(long)a * ldo + ((long)i * ra1 + b) * rb1 + dd] = v; }, sm.gt);
+      } else {
+        wg_gemm_split(
+            tm, rho, ra1, ra0, [=](int a, int mu) { return Y[(((long)a * ra0 + mu) * d + i) * rb1 + dd]; },
+            [=](int mu, int b) { return A[((long)mu * d + i) * ra1 + b]; },
+            [=](int a, int b, double v) { M[(long)a * ldo + ((long)i * ra1 + b) * rb1 + dd] = v; }, sm.gt);
+      }
     }
-    M[e] = (double)acc;
-  }
-  wg_sync();
 }
 
 __device__ void wg_copy_pad(const double* __restrict__ src, int rows, int cols, long lds, double* __restrict__ dst,
@@ -322,8 +321,8 @@ __device__ void wg_norms_sort(const double* __restrict__ X, int p, int L, double
 }
 
 template <int JB>
-__device__ void process_instance(const BInst& I, double rel_tol, long max_rank, int max_sweeps, double* __restrict__ sh,
-                                 Smem& sm,
+__device__ void process_instance(const BInst& I, const TileMap& tm, double rel_tol, long max_rank, int max_sweeps,
+                                 double* __restrict__ sh, Smem& sm,
                                  long* __restrict__ ranks_out, double* __restrict__ tail_out, int* __restrict__ status) {
   const int n = I.n;
   double* ws = I.ws;
@@ -346,8 +345,8 @@ __device__ void process_instance(const BInst& I, double rel_tol, long max_rank, 
       wg_sync();
       Rk = one;
     }
-    wg_gemm_nn_f32(rho0 * ra0, dj * rb1, rb0, Rk, rb0, I.b[k], Yb);
-    wg_bond_apply(mpo, Yb, rho0, ra0, d, dj, rb1, I.a[k], ra1, M);
+    wg_gemm_nn(tm, rho0 * ra0, dj * rb1, rb0, Rk, rb0, I.b[k], Yb, sm);
+    wg_bond_apply(tm, mpo, Yb, rho0, ra0, d, dj, rb1, I.a[k], ra1, M, sm);
     if (!last) {
       const int m = rho0 * d;
       wg_householder_qr(M, m, cols, cols, ws + I.offT[k], sm);
@@ -440,7 +439,7 @@ __device__ void process_instance(const BInst& I, double rel_tol, long max_rank, 
       core[(long)j * L + c] = (s > 0.0) ? X[(long)perm[j] * L + c] / s : 0.0;
     }
     wg_sync();
-    wg_gemm_nt_f32(p, r, L, Xc, core, Yn);
+    wg_gemm_nt(tm, p, r, L, Xc, core, Yn, sm);
     if (tall) {
       for (long e = tid; e < (long)(rows - p) * r; e += BNT) Yn[(long)p * r + e] = 0.0;
       wg_sync();
@@ -460,7 +459,7 @@ __device__ void process_instance(const BInst& I, double rel_tol, long max_rank, 
 
 template <int JB>
 __global__ __launch_bounds__(BNT) void k_batched(const BInst* __restrict__ insts, const int* __restrict__ order,
-                                                 int count, unsigned* __restrict__ queue, double rel_tol,
+                                                 int count, unsigned* __restrict__ queue, TileMap tm, double rel_tol,
                                                  long max_rank, int max_sweeps, long* __restrict__ ranks_out,
                                                  double* __restrict__ tails_out, int* __restrict__ status) {
   extern __shared__ double sh[];
@@ -473,13 +472,48 @@ __global__ __launch_bounds__(BNT) void k_batched(const BInst* __restrict__ insts
     __syncthreads();
     if (idx >= count) break;
     const int inst = order[idx];
-    process_instance<JB>(insts[inst], rel_tol, max_rank, max_sweeps, sh, sm, ranks_out + (long)inst * (QTT_BATCH_MAXN + 1),
+    process_instance<JB>(insts[inst], tm, rel_tol, max_rank, max_sweeps, sh, sm, ranks_out + (long)inst * (QTT_BATCH_MAXN + 1),
                          tails_out + (long)inst * QTT_BATCH_MAXN, status + inst);
     __syncthreads();
   }
 }
 
+// Tuner probe: every workgroup of the grid computes the same C = A B (A M x K,
+// B K x N, row-major) with one tile variant, as the persistent kernel's
+// workgroups do side by side; workgroup 0 writes C.
+template <int TM, int TN>
+__global__ __launch_bounds__(BNT) void k_tile_probe(int M, int N, int K, const double* __restrict__ A,
+                                                    const double* __restrict__ B, double* __restrict__ C) {
+  __shared__ GemmTiles gt;
+  const bool w = blockIdx.x == 0;
+  wg_gemm_split_tile<TM, TN>(
+      M, N, K, [=](int m, int k) { return A[(long)m * K + k]; }, [=](int k, int n) { return B[(long)k * N + n]; },
+      [=](int m, int n, double v) {
+        if (w) C[(long)m * N + n] = v;
+      },
+      gt);
+}
+
 }  // namespace
+
+hipError_t tile_probe_launch(hipStream_t s, int variant, int grid, int M, int N, int K, const double* A,
+                             const double* B, double* C) {
+  switch (variant) {
+    case 1:
+      hipLaunchKernelGGL((k_tile_probe<64, 32>), dim3(grid), dim3(BNT), 0, s, M, N, K, A, B, C);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_tile_probe<32, 64>), dim3(grid), dim3(BNT), 0, s, M, N, K, A, B, C);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_tile_probe<32, 32>), dim3(grid), dim3(BNT), 0, s, M, N, K, A, B, C);
+      break;
+    default:
+      hipLaunchKernelGGL((k_tile_probe<64, 64>), dim3(grid), dim3(BNT), 0, s, M, N, K, A, B, C);
+      break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t batched_configure() {
   // up to 96 KiB of dynamic LDS (the Jacobi visit's 2 JB rows); raised for
@@ -490,18 +524,18 @@ hipError_t batched_configure() {
 }
 
 hipError_t batched_launch(hipStream_t s, int variant, int grid, const BInst* insts, const int* order, int count,
-                          unsigned* queue, double rel_tol, long max_rank, int max_sweeps, long* ranks_out,
-                          double* tails_out, int* status, int max_L) {
+                          unsigned* queue, const TileMap& tm, double rel_tol, long max_rank, int max_sweeps,
+                          long* ranks_out, double* tails_out, int* status, int max_L) {
   hipError_t e = fill_u32(s, queue, 0u, 1);
   if (e != hipSuccess) return e;
   const int jb = (variant & 1) ? 4 : 8;
   const size_t shmem = (size_t)2 * jb * max_L * sizeof(double);
   if (shmem > 96 * 1024) return hipErrorInvalidValue;
   if (jb == 4) {
-    hipLaunchKernelGGL(k_batched<4>, dim3(grid), dim3(BNT), shmem, s, insts, order, count, queue, rel_tol, max_rank,
+    hipLaunchKernelGGL(k_batched<4>, dim3(grid), dim3(BNT), shmem, s, insts, order, count, queue, tm, rel_tol, max_rank,
                        max_sweeps, ranks_out, tails_out, status);
   } else {
-    hipLaunchKernelGGL(k_batched<8>, dim3(grid), dim3(BNT), shmem, s, insts, order, count, queue, rel_tol, max_rank,
+    hipLaunchKernelGGL(k_batched<8>, dim3(grid), dim3(BNT), shmem, s, insts, order, count, queue, tm, rel_tol, max_rank,
                        max_sweeps, ranks_out, tails_out, status);
   }
   return hipGetLastError();

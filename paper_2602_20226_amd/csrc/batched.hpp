@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "wg_gemm.hpp"
+
 namespace qtt {
 
 constexpr int QTT_BATCH_MAXN = 32;        // cores per instance
@@ -27,7 +29,11 @@ struct BInst {
 // Jacobi blocks of 4 rows instead of 8).  max_L bounds the Jacobi row length;
 // max_sweeps caps each Jacobi iteration (status NOCONV when reached).
 hipError_t batched_launch(hipStream_t s, int variant, int grid, const BInst* insts, const int* order, int count,
-                          unsigned* queue, double rel_tol, long max_rank, int max_sweeps, long* ranks_out,
-                          double* tails_out, int* status, int max_L);
+                          unsigned* queue, const TileMap& tm, double rel_tol, long max_rank, int max_sweeps,
+                          long* ranks_out, double* tails_out, int* status, int max_L);
+// One launch of the tuner probe: grid workgroups each computing C = A B
+// (row-major M x K times K x N) with tile variant `variant` (wg_gemm.hpp).
+hipError_t tile_probe_launch(hipStream_t s, int variant, int grid, int M, int N, int K, const double* A,
+                             const double* B, double* C);
 
 }  // namespace qtt

@@ -149,26 +149,7 @@ hipError_t launch_gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, T a
 }
 
 // ------------------------------------------------------------------ bf16 split
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ unsigned short bf16_bits_rne(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ double bf16_bits_to_double(unsigned short h) {
-  return (double)__uint_as_float(((unsigned)h) << 16);
-}
-// a = p0 + p1 + p2 (+ remainder), each p the RNE bf16 of what is left.
-__device__ __forceinline__ void split3(double a, unsigned short& p0, unsigned short& p1,
-                                      unsigned short& p2) {
-  p0 = bf16_bits_rne((float)a);
-  double r = a - bf16_bits_to_double(p0);
-  p1 = bf16_bits_rne((float)r);
-  r -= bf16_bits_to_double(p1);
-  p2 = bf16_bits_rne((float)r);
-}
-
+// (bf16 split helpers: qtt_device.hpp)
 constexpr int SBM = 64, SBN = 64, SBK = 32;
 
 // 16x16x32 bf16 MFMA operand layout: lane holds 8 consecutive k of

@@ -20,10 +20,13 @@ def log(msg):
 
 
 def check_instance(plan, i, A, B, tol, max_rank, err_tol):
+    """Problem i of the plan against the oracle: identical ranks, the rounded
+    tensor to err_tol (relative Frobenius, through the exact difference
+    train), and right-orthonormal cores 2..n."""
     C = O.contract("i,i->i", A, B)
     ref, info = O.round_tt(C, tol, max_rank, return_info=True)
     got = Q.to_host(plan.cores(i))
-    assert plan.ranks[i] == info.ranks, (i, plan.ranks[i], info.ranks)
+    assert plan.ranks[i] == info.ranks, (i, plan.ranks[i], info.ranks, info.margin_lo, info.margin_hi)
     err = O.rel_error(got, ref)
     assert err <= err_tol, (i, err)
     for c in got[1:]:
@@ -44,11 +47,12 @@ def test_small_uneven_batch_all_instances():
     plan = Q.BatchPlan("i,i->i", [Q.to_device(a) for a in A], [Q.to_device(b) for b in B], 1e-8, 0, tune=False)
     plan.launch()
     plan.results()
-    worst = max(check_instance(plan, i, A[i], B[i], 1e-8, 0, 1e-5) for i in range(len(A)))
+    worst = max(check_instance(plan, i, A[i], B[i], 1e-8, 0, 1e-6) for i in range(len(A)))
     log(f"batched small worst rel err {worst:.2e}")
 
 
-def test_hadamard_batch_sampled_parity_and_graph_replay():
+@pytest.mark.timeout(900)
+def test_hadamard_batch_all_problems_parity_and_graph_replay():
     log("batched hadamard_batch")
     w = I.hadamard_batch()
     A = [Q.to_device(a) for a in w.a]
@@ -68,12 +72,16 @@ def test_hadamard_batch_sampled_parity_and_graph_replay():
         for a, b in zip(first, plan.cores(5)):
             assert torch.equal(a, b)
     rs = w.extra["ranks"]
-    sample = sorted(set([int(np.argmax(rs)), int(np.argmin(rs)), 0, 1, 100, 255, 511]))
-    worst = 0.0
-    for i in sample:
-        worst = max(worst, check_instance(plan, i, w.a[i], w.b[i], w.rel_tol, 0, 1e-5))
-    log(f"hadamard_batch sampled worst rel err {worst:.2e}")
-    # every problem: rank bounds and right-orthonormal cores
+    # every problem against the oracle: identical ranks, the rounded tensor to
+    # 1e-6 (bf16x6 products with FP32 accumulation per step), orthonormal cores
+    worst, worst_i = 0.0, -1
     for i in range(len(w.a)):
         assert ranks0[i][0] == 1 and ranks0[i][-1] == 1
         assert max(ranks0[i]) <= 2 * rs[i]
+        e = check_instance(plan, i, w.a[i], w.b[i], w.rel_tol, 0, 1e-6)
+        if e > worst:
+            worst, worst_i = e, i
+        if i % 64 == 63:
+            log(f"  {i + 1} problems checked, worst so far {worst:.2e}")
+    log(f"hadamard_batch: all {len(w.a)} problems within 1e-6 of the oracle, worst {worst:.2e} (problem {worst_i}, "
+        f"rank {rs[worst_i]})")
