@@ -49,7 +49,9 @@ typedef enum {
 /* Storage type of the cores. */
 typedef enum { QTT_F64 = 0, QTT_F32 = 1 } qtt_dtype;
 
-/* Arithmetic of the GEMM steps of a rounding sweep (the bond products).  The
+/* Arithmetic of the GEMM steps: in a rounding sweep the bond products R C_k
+ * of the QR sweep and the products U Sigma = F V that the SVD sweep absorbs
+ * into the left neighbour, in qtt_inner_prec the environment products.  The
  * Householder QR, the Jacobi SVD, norms and the rank decisions are always FP64. */
 typedef enum {
   QTT_GEMM_FP64 = 0,   /* FP64 MFMA */
@@ -156,6 +158,20 @@ int qtt_contract_round(qtt_handle h, const char *spec, const qtt_tt *a, const qt
                        double rel_tol, int64_t max_rank, int prec, qtt_round_info *info,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* Stream-ordered qtt_contract_round for HIP graph capture: the same sweeps
+ * with no host synchronisation and no host read-back (all rank decisions stay
+ * on the device; every launch is sized by the rank bounds, which are the
+ * bounds qtt_contract_round's output cores must hold).  On completion of the
+ * stream, out's cores hold the rounded train (compact at the rounded ranks),
+ * ranks_dev (device, n + 1 int64) the rounded ranks and *status_dev (device)
+ * QTT_OK, QTT_ERR_NONFINITE or QTT_ERR_NOCONV.  out's host ranks are not
+ * written.  Argument, shape and workspace errors are returned at once, before
+ * anything is enqueued.  The workspace is that of qtt_contract_round and must
+ * stay untouched until the stream has completed the call.  Asynchronous. */
+int qtt_contract_round_async(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qtt_tt *out,
+                             double rel_tol, int64_t max_rank, int prec, int64_t *ranks_dev,
+                             int32_t *status_dev, void *ws, size_t ws_bytes, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * contraction + rounding as qtt_contract_round, with its workspace in a
@@ -216,6 +232,31 @@ int qtt_fit(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qt
 /* Device workspace (bytes) of qtt_fit; pure shape arithmetic. */
 int qtt_fit_workspace_size(const char *spec, const qtt_tt *a, const qtt_tt *b, const qtt_tt *c, size_t *bytes);
 
+/* Variational fitting with super-cores of two adjacent cores (the multi-core
+ * strategy of Sec. 3.3; the paper's variational(..., ncores=2)): with the
+ * cores left of the pair (q, q+1) left-orthonormal and those right of it
+ * right-orthonormal, the pair is replaced by the derivative of <c|a*b> with
+ * respect to the fused super-core, S = L_q Y_q Y_{q+1} R_{q+2} (Y the
+ * exactly contracted product, formed in the workspace), which is then
+ * decomposed again by a truncated SVD (Householder QR + one-sided Jacobi,
+ * FP64): the kept rank is the smallest r whose discarded singular values
+ * have 2-norm <= rel_tol ||S||_F / sqrt(n-1), capped at max_rank (<= 0: no
+ * cap) -- so, unlike qtt_fit, the ranks adapt (grow or shrink).  The guess
+ * is first orthogonalised from the left; a sweep runs over the pairs from
+ * the right end (core q+1 <- V^T, core q <- U Sigma) and back from the left
+ * (core q <- U, core q+1 <- Sigma V^T).  c's cores (FP64, caller-owned) must
+ * hold the rank bounds of qtt_fit2_query; c->ranks is rewritten.  info
+ * (nullable): norm = ||c||, tail[k] the discarded 2-norm of the last
+ * sweep's split at bond k+1, jacobi_sweeps_max; the other fields are not
+ * written.  Synchronous. */
+int qtt_fit2(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qtt_tt *c, int32_t nsweeps,
+             double rel_tol, int64_t max_rank, qtt_round_info *info, void *ws, size_t ws_bytes, void *stream);
+/* Rank capacity per bond of qtt_fit2's result (bounds, n+1 entries, nullable:
+ * the guess's rank or the largest rank a split can give, whichever is
+ * larger) and its device workspace (bytes); pure shape arithmetic. */
+int qtt_fit2_query(const char *spec, const qtt_tt *a, const qtt_tt *b, const qtt_tt *c, int64_t max_rank,
+                   int64_t *bounds, size_t *bytes);
+
 /* Shape query of qtt_contract_zipup: per-bond rank bounds of the result
  * (n+1 entries, nullable) and the device workspace in bytes (nullable).
  * Pure shape arithmetic; core pointers are not dereferenced. */
@@ -238,6 +279,12 @@ int qtt_add(qtt_handle h, int32_t count, const qtt_tt *terms, const double *coef
  * sizes, FP64 or FP32 (accumulated in the storage type).  Synchronous. */
 int qtt_inner(qtt_handle h, const qtt_tt *a, const qtt_tt *b, double *out_host, void *ws,
               size_t ws_bytes, void *stream);
+/* qtt_inner with the two GEMMs of every environment step in the arithmetic
+ * `prec` (qtt_prec; the precision form of the inner product): FP64 cores
+ * only for the reduced forms (QTT_ERR_DTYPE otherwise), same workspace as
+ * qtt_inner.  QTT_GEMM_FP64 is qtt_inner.  Synchronous. */
+int qtt_inner_prec(qtt_handle h, const qtt_tt *a, const qtt_tt *b, int prec, double *out_host, void *ws,
+                   size_t ws_bytes, void *stream);
 
 /* Gradient of g * <a, b> with respect to the cores of a (and of b when db is
  * not NULL): da_k = g * E_{k-1} b_k(i) F_{k+1}^T from left/right environment
@@ -259,13 +306,17 @@ int qtt_contract_backward(qtt_handle h, const char *spec, const qtt_tt *a, const
  * Each workgroup takes the next problem from a device work queue (largest
  * estimated cost first) and runs the whole QR sweep / Jacobi SVD sweep for
  * it with workgroup-level kernels; rank decisions stay on the device.
- * Bond products and U Sigma = F V accumulate in FP32; Householder QR, the
+ * Bond products and U Sigma = F V run on the bf16 matrix cores: the FP64
+ * operands split into three bf16 pieces, six cross products per 32-deep k
+ * step accumulated in FP32, the steps added in FP64.  Householder QR, the
  * Jacobi SVD, norms and rank decisions are FP64.  Limits: <= 32 cores per
  * problem, unfolding rows <= 512, Jacobi row length d*r <= 768.
  *
  * qtt_batch_plan_create validates the problems, writes the instance table
- * into ws, selects a kernel variant (Jacobi block size x grid size) -- by
- * timing all variants on this batch when `tune` is non-zero, cached in the
+ * into ws, picks the GEMM tile shape (64x64, 64x32, 32x64 or 32x32) of each
+ * GEMM shape bucket (M > 32, N > 32, K > 64) and a kernel variant (Jacobi
+ * block size x grid size) -- when `tune` is non-zero by timing every tile on
+ * the bucket's largest shape and every variant on this batch, cached in the
  * file named by QTT_TUNE_CACHE (default ~/.cache/qtt/batched_tune.txt) --
  * and captures the queue reset plus the persistent launch in a hipGraph.
  * qtt_batch_plan_launch replays that graph on `stream` (asynchronous; out
@@ -288,6 +339,12 @@ int qtt_batch_plan_results(qtt_batch_plan plan, int64_t *ranks, double *tails, v
  * CU), grid size and the tuning times of the four variants (ms; 0 if the
  * variant came from the cache). */
 int qtt_batch_plan_info(qtt_batch_plan plan, int32_t *variant, int32_t *grid, float *tuned_ms);
+/* GEMM tile choice of the plan: tiles[8] (0: 64x64, 1: 64x32, 2: 32x64,
+ * 3: 32x32) per shape bucket b = (M > 32) + 2 (N > 32) + 4 (K > 64),
+ * shapes[8][3] the (M, N, K) the bucket was timed on (zeros: bucket unused),
+ * probe_ms[8][4] the median probe time of each tile (zeros: not measured).
+ * Any pointer may be NULL. */
+int qtt_batch_plan_tiles(qtt_batch_plan plan, uint8_t *tiles, int32_t *shapes, float *probe_ms);
 int qtt_batch_plan_destroy(qtt_batch_plan plan);
 
 /* Launch profiling for roofline reports.  qtt_profile_start arms one kernel

@@ -20,6 +20,7 @@
 #include <sstream>
 #include <string>
 #include <sys/stat.h>
+#include <type_traits>
 #include <vector>
 
 using namespace qtt;
@@ -126,8 +127,12 @@ struct Plan {
   std::vector<long> m;     // rows of M_k (k < n-1): rho_{k-1} d_k
   std::vector<long> rho;   // rank after QR, rho[-1] = 1 stored at index 0 => rho[k+1]
   std::vector<long> offM, offT;
+  std::vector<long> rr;    // bound of the rounded rank per bond (n+1)
   long offCenter = 0, offR = 0, offY = 0, offZ = 0, offX = 0, offXc = 0, offYn = 0, offTB = 0;
   long offSig = 0, offPerm = 0, offTrunc = 0, offCtr = 0, offNorm = 0, offSweeps = 0, offOne = 0, offScr = 0;
+  // SVD sweep with device-resident ranks: the compacted B_k (QR in place), the
+  // padded V rows, R V, and a device int 1
+  long offB = 0, offV = 0, offYt = 0, offOneI = 0;
   long total = 0;
   long maxr_bound = 0;
 };
@@ -136,7 +141,9 @@ long round_up(long x, long a) { return (x + a - 1) / a * a; }
 
 // svd = false plans the QR sweep only (orthogonalisation): no SVD-sweep
 // buffers and none of their size limits.
-int make_plan(const Shape& s, long max_rank, Plan& P, bool svd = true) {
+// devranks = false: the batched kernel's per-problem plan (its sweep keeps
+// ranks in workgroup registers and needs none of the device-rank buffers).
+int make_plan(const Shape& s, long max_rank, Plan& P, bool svd = true, bool devranks = true) {
   const int n = s.n;
   P.m.assign(n, 0);
   P.rho.assign(n + 1, 1);
@@ -214,11 +221,18 @@ int make_plan(const Shape& s, long max_rank, Plan& P, bool svd = true) {
   P.offTB = take(maxTB);
   P.offSig = take(maxP);
   P.offPerm = take(maxP / 2 + 1);
-  P.offTrunc = take(8);
+  // one rank decision and one Jacobi record (sweeps, converged) per bond
+  P.offTrunc = take((long)std::max(n, 1) * (long)((sizeof(TruncOut) + 7) / 8));
   P.offCtr = take(96);  // Jacobi: 8 counter words + one version per 8-row block (p <= 1024)
   P.offNorm = take(1);
-  P.offSweeps = take(1);
+  P.offSweeps = take(std::max(n, 1));
   P.offOne = take(1);
+  if (svd && devranks) {
+    P.offB = take(maxZ);
+    P.offV = take(maxX);
+    P.offYt = take(maxX);
+    P.offOneI = take(1);
+  }
   {
     long maxc = 1;
     for (int k = 0; k <= n; ++k) maxc = std::max(maxc, s.rc[k]);
@@ -228,6 +242,7 @@ int make_plan(const Shape& s, long max_rank, Plan& P, bool svd = true) {
   P.total = off;
   P.maxr_bound = 0;
   for (int k = 0; k <= n; ++k) P.maxr_bound = std::max(P.maxr_bound, rr[k]);
+  P.rr = rr;
   return QTT_OK;
 }
 
@@ -314,6 +329,22 @@ hipError_t bond_gemm(hipStream_t st, int prec, int rows, int cols, int K, const 
   }
 }
 
+// C = op(A) op(B) (M x N, K deep) in the requested GEMM arithmetic (the
+// reduced-precision forms take FP64 operands and write FP64 results).
+hipError_t gemm_prec(hipStream_t st, int prec, bool ta, bool tb, int M, int N, int K, const double* A, long lda,
+                     const double* B, long ldb, double* C, long ldc) {
+  switch (prec) {
+    case QTT_GEMM_FP32:
+      return gemm_f64_via_f32(st, ta, tb, M, N, K, A, lda, B, ldb, C, ldc);
+    case QTT_GEMM_BF16X3:
+      return gemm_bf16split(st, ta, tb, M, N, K, A, lda, B, ldb, C, ldc, 3);
+    case QTT_GEMM_BF16X6:
+      return gemm_bf16split(st, ta, tb, M, N, K, A, lda, B, ldb, C, ldc, 6);
+    default:
+      return gemm_f64(st, ta, tb, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, ldc, 0, 1);
+  }
+}
+
 struct Sweep {
   qtt_context* h;
   hipStream_t st;
@@ -382,7 +413,19 @@ int readback(qtt_context* h, hipStream_t st, const void* dev, size_t bytes, void
 }
 
 // SVD sweep from the right; writes the rounded cores into out.
-int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_info* info, std::vector<long>& newr) {
+//
+// The ranks stay on the device: every launch is sized by the plan's rank
+// bounds, and the rank r_{k+1} decided at the previous bond is read by the
+// kernels that need it.  B_k = Q_k [U Sigma; 0] (whose columns beyond
+// r_{k+1} are zero) is first compacted so that its zero columns trail; its
+// Householder QR then has exactly zero rows beyond rank(B_k), which the
+// Jacobi leaves untouched, so bonds whose rank falls below the bound cost
+// only the bound's extra (zero) work.  Nothing is read back until the end,
+// so the whole sweep is stream-ordered (sync = false: no host wait at all,
+// and out's host ranks and info are not written; the record kernel leaves
+// the ranks and a status in record_ranks / record_status).
+int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_info* info, std::vector<long>& newr,
+              bool sync = true, long long* record_ranks = nullptr, int* record_status = nullptr) {
   const Shape& s = *w.s;
   const Plan& P = *w.P;
   const int n = s.n;
@@ -392,108 +435,106 @@ int svd_sweep(Sweep& w, qtt_tt* out, double rel_tol, long max_rank, qtt_round_in
   double* Xc = ws + P.offXc;
   double* Yn = ws + P.offYn;
   double* TB = ws + P.offTB;
+  double* X0 = ws + P.offB;
+  double* V = ws + P.offV;
+  double* Yt = ws + P.offYt;
   double* sig = ws + P.offSig;
   int* perm = (int*)(ws + P.offPerm);
-  TruncOut* tr = (TruncOut*)(ws + P.offTrunc);
+  TruncOut* trs = (TruncOut*)(ws + P.offTrunc);
   unsigned* ctr = (unsigned*)(ws + P.offCtr);
   int* sweeps = (int*)(ws + P.offSweeps);
+  int* one_i = (int*)(ws + P.offOneI);
   newr.assign(n + 1, 1);
-  double norm = 0.0;
-  {
-    int e = readback(w.h, w.st, ws + P.offNorm, sizeof(double), w.h->pin_dbl);
-    if (e) return e;
-    norm = w.h->pin_dbl[0];
+  QTT_HIP(fill_u32(w.st, (unsigned*)one_i, 1u, 1));
+  const bool want_sig = sync && info && info->sigma && info->sigma_ld > 0;
+  long rbnext = 1;              // launch bound of r_{k+1}
+  const int* rnext_dev = one_i;  // r_{k+1} on the device
+  for (int k = n - 1; k >= 1; --k) {
+    const long rows = P.rho[k];
+    const long D = s.d[k] * rbnext;
+    if (k == n - 1) {
+      QTT_HIP(copy_pad_rows(w.st, ws + P.offCenter, (int)rows, (int)D, D, X0, (int)rows, D));
+    } else {
+      // Z = Q_k [Y_{k+1}; 0]  (m_k x rb_{k+1}) = B_k as rows x D, then its kept columns to the front
+      QTT_HIP(copy_pad_rows(w.st, Yn, (int)P.rho[k + 1], (int)rbnext, rbnext, Z, (int)P.m[k], rbnext));
+      QTT_HIP(apply_q(w.st, ws + P.offM[k], (int)P.m[k], (int)P.rho[k + 1], s.rc[k + 1], ws + P.offT[k], Z,
+                      (int)rbnext, rbnext, false, ws + P.offScr));
+      QTT_HIP(compact_cols(w.st, Z, (int)rows, s.d[k], (int)rbnext, rnext_dev, X0));
+    }
+    // B = Q_B R; the Jacobi acts on the rows of F = R (p x D, p = min(rows, D)),
+    // Xc keeps F for U Sigma = Q_B [F V; 0]
+    const int p = (int)std::min(rows, D);
+    const int L = (int)D;
+    QTT_HIP(householder_qr(w.st, X0, (int)rows, (int)D, D, TB, ws + P.offScr));
+    QTT_HIP(extract_r(w.st, X0, p, (int)D, D, Xc));
+    // Jacobi from F's rows in descending-norm order (a row permutation changes
+    // neither V nor F V)
+    QTT_HIP(row_norms_sorted(w.st, Xc, p, L, sig, perm));
+    QTT_HIP(permute_rows(w.st, Xc, p, L, perm, X));
+    QTT_HIP(jacobi_rows(w.st, X, p, L, ctr, w.h->max_sweeps, sweeps + 2 * (k - 1), sig));  // sig[0]: largest norm
+    QTT_HIP(row_norms_sorted(w.st, X, p, L, sig, perm));
+    TruncOut* tr = trs + (k - 1);
+    QTT_HIP(truncate_decide(w.st, sig, p, ws + P.offNorm, rel_tol, n - 1, max_rank, tr));
+    if (want_sig) {
+      const long cnt = std::min<long>(p, info->sigma_ld);
+      QTT_HIP(hipMemcpyAsync(info->sigma + (long)(k - 1) * info->sigma_ld, sig, cnt * sizeof(double),
+                             hipMemcpyDeviceToHost, w.st));
+      QTT_HIP(hipStreamSynchronize(w.st));
+      for (long i = cnt; i < info->sigma_ld; ++i) info->sigma[(long)(k - 1) * info->sigma_ld + i] = 0.0;
+    }
+    // V: the r kept right singular vectors (rows), zero rows up to the bound
+    const int rb = (int)std::max(1L, std::min<long>(p, P.rr[k]));
+    QTT_HIP(gather_rows_padded(w.st, X, L, perm, sig, tr, V, rb));
+    // core k <- V_r^T  ([r_k, d_k, r_{k+1}], compact)
+    QTT_HIP(core_from_rows(w.st, V, rb, L, &tr->rank, s.d[k], rnext_dev, (double*)out->cores[k]));
+    // Y_k = U Sigma = B V_r = Q_B [F V_r; 0]  (rows x rb; columns beyond r_k are zero)
+    QTT_HIP(gemm_prec(w.st, w.prec, false, true, p, rb, L, Xc, L, V, L, Yt, rb));
+    QTT_HIP(copy_pad_rows(w.st, Yt, p, rb, rb, Yn, (int)rows, rb));
+    QTT_HIP(apply_q(w.st, X0, (int)rows, p, D, TB, Yn, rb, rb, false, ws + P.offScr));
+    rbnext = rb;
+    rnext_dev = &tr->rank;
   }
+  // core 0 = Q_0 [Y_1; 0], its first r_1 columns per physical index
+  if (n == 1) {
+    QTT_HIP(copy_pad_rows(w.st, ws + P.offCenter, 1, s.d[0], s.d[0], (double*)out->cores[0], 1, s.d[0]));
+  } else {
+    QTT_HIP(copy_pad_rows(w.st, Yn, (int)P.rho[1], (int)rbnext, rbnext, Z, (int)P.m[0], rbnext));
+    QTT_HIP(apply_q(w.st, ws + P.offM[0], (int)P.m[0], (int)P.rho[1], s.rc[1], ws + P.offT[0], Z, (int)rbnext,
+                    rbnext, false, ws + P.offScr));
+    QTT_HIP(compact_cols(w.st, Z, 1, s.d[0], (int)rbnext, rnext_dev, (double*)out->cores[0]));
+  }
+  if (record_ranks || record_status) {
+    if (!record_ranks || !record_status) return QTT_ERR_ARG;
+    QTT_HIP(round_record(w.st, trs, sweeps, n, ws + P.offNorm, record_ranks, record_status, QTT_ERR_NONFINITE,
+                         QTT_ERR_NOCONV));
+  }
+  if (!sync) return QTT_OK;
+  // the only host wait of the sweep: decisions and Jacobi records of all bonds
+  std::vector<TruncOut> ht(std::max(n - 1, 1));
+  std::vector<int> hs(2 * std::max(n - 1, 1));
+  double norm = 0.0;
+  QTT_HIP(hipMemcpyAsync(&norm, ws + P.offNorm, sizeof(double), hipMemcpyDeviceToHost, w.st));
+  if (n > 1) {
+    QTT_HIP(hipMemcpyAsync(ht.data(), trs, (size_t)(n - 1) * sizeof(TruncOut), hipMemcpyDeviceToHost, w.st));
+    QTT_HIP(hipMemcpyAsync(hs.data(), sweeps, (size_t)(n - 1) * 2 * sizeof(int), hipMemcpyDeviceToHost, w.st));
+  }
+  QTT_HIP(hipStreamSynchronize(w.st));
   if (!std::isfinite(norm)) return QTT_ERR_NONFINITE;
   double err2 = 0.0;
   int maxsw = 0;
-  long rnext = 1;  // r''_{k+1}
-  for (int k = n - 1; k >= 1; --k) {
-    const long rows = P.rho[k];
-    const long D = s.d[k] * rnext;
-    const double* B;
-    if (k == n - 1) {
-      B = ws + P.offCenter;
-    } else {
-      // Z = Q_k [Y_{k+1}; 0]  (m_k x r''_{k+1}) = B_k as rows x D
-      QTT_HIP(copy_pad_rows(w.st, Yn, (int)P.rho[k + 1], (int)rnext, rnext, Z, (int)P.m[k], rnext));
-      QTT_HIP(apply_q(w.st, ws + P.offM[k], (int)P.m[k], (int)P.rho[k + 1], s.rc[k + 1], ws + P.offT[k], Z,
-                      (int)rnext, rnext, false, ws + P.offScr));
-      B = Z;
-    }
-    // Jacobi acts on the rows of F: F = R (D x D) from a QR of B when B is
-    // tall, F = B itself otherwise.  Xc keeps F for U Sigma = F V.
-    const bool tall = rows >= D;
-    int p;
-    const int L = (int)D;
-    if (tall) {
-      if (B != Z) QTT_HIP(copy_pad_rows(w.st, B, (int)rows, (int)D, D, Z, (int)rows, D));
-      QTT_HIP(householder_qr(w.st, Z, (int)rows, (int)D, D, TB, ws + P.offScr));
-      QTT_HIP(extract_r(w.st, Z, (int)D, (int)D, D, X));
-      p = (int)D;
-    } else {
-      QTT_HIP(copy_pad_rows(w.st, B, (int)rows, (int)D, D, X, (int)rows, D));
-      p = (int)rows;
-    }
-    // F kept in Xc; Jacobi starts from F's rows in descending-norm order
-    // (a row permutation changes neither V nor U Sigma = F V)
-    QTT_HIP(copy_pad_rows(w.st, X, p, L, L, Xc, p, L));
-    QTT_HIP(row_norms_sorted(w.st, Xc, p, L, sig, perm));
-    QTT_HIP(permute_rows(w.st, Xc, p, L, perm, X));
-    QTT_HIP(jacobi_rows(w.st, X, p, L, ctr, w.h->max_sweeps, sweeps, sig));  // sig[0]: largest row norm
-    QTT_HIP(row_norms_sorted(w.st, X, p, L, sig, perm));
-    QTT_HIP(truncate_decide(w.st, sig, p, ws + P.offNorm, rel_tol, n - 1, max_rank, tr));
-    QTT_HIP(hipMemcpyAsync(w.h->pin_int, sweeps, 2 * sizeof(int), hipMemcpyDeviceToHost, w.st));
-    int e = readback(w.h, w.st, tr, sizeof(TruncOut), w.h->pin_trunc);
-    if (e) return e;
-    const TruncOut t = *w.h->pin_trunc;
-    const int swp = w.h->pin_int[0];
-    if (!w.h->pin_int[1]) return QTT_ERR_NOCONV;
-    {
-      double jb = 0.0, jf = 0.0;
-      jacobi_sweep_cost(p, L, &jb, &jf);
-      prof::amend(prof::JACOBI, swp * jb, swp * jf);
-    }
-    maxsw = std::max(maxsw, swp);
-    const int r = t.rank;
+  for (int k = 1; k < n; ++k) {
+    const TruncOut& t = ht[k - 1];
+    if (!hs[2 * (k - 1) + 1]) return QTT_ERR_NOCONV;
+    maxsw = std::max(maxsw, hs[2 * (k - 1)]);
+    newr[k] = t.rank;
+    err2 += t.tail_r * t.tail_r;
     if (info) {
       if (info->tail) info->tail[k - 1] = t.tail_r;
       if (info->margin_lo) info->margin_lo[k - 1] = t.delta > 0 ? t.tail_rm1 / t.delta : INFINITY;
       if (info->margin_hi) info->margin_hi[k - 1] = t.delta > 0 ? t.tail_r / t.delta : 0.0;
       if (info->maxrank_hit) info->maxrank_hit[k - 1] = (uint8_t)t.capped;
-      if (info->sigma && info->sigma_ld > 0) {
-        const long cnt = std::min<long>(p, info->sigma_ld);
-        QTT_HIP(hipMemcpyAsync(info->sigma + (long)(k - 1) * info->sigma_ld, sig, cnt * sizeof(double),
-                               hipMemcpyDeviceToHost, w.st));
-        QTT_HIP(hipStreamSynchronize(w.st));
-        for (long i = cnt; i < info->sigma_ld; ++i) info->sigma[(long)(k - 1) * info->sigma_ld + i] = 0.0;
-      }
     }
-    err2 += t.tail_r * t.tail_r;
-    // core k <- V_r^T: rows perm[:r] of X, normalised  ([r, d_k, r''_{k+1}])
-    double* core = (double*)out->cores[k];
-    QTT_HIP(gather_rows_normalized(w.st, X, L, perm, sig, tr, core, L, r));
-    // Y_k = U Sigma = B V_r  (rows x r): tall B = Q_B R  =>  Q_B [R V_r; 0]
-    if (tall) {
-      QTT_HIP(gemm_f64(w.st, false, true, p, r, L, 1.0, Xc, L, 0, core, L, 0, 0.0, Yn, r, 0, 1));
-      if (rows > p) QTT_HIP(fill_f64(w.st, Yn + (long)p * r, 0.0, (rows - p) * r));
-      QTT_HIP(apply_q(w.st, Z, (int)rows, p, D, TB, Yn, r, r, false, ws + P.offScr));
-    } else {
-      QTT_HIP(gemm_f64(w.st, false, true, p, r, L, 1.0, Xc, L, 0, core, L, 0, 0.0, Yn, r, 0, 1));
-    }
-    newr[k] = r;
-    rnext = r;
   }
-  // core 0 = Q_0 [Y_1; 0]
-  if (n == 1) {
-    QTT_HIP(copy_pad_rows(w.st, ws + P.offCenter, 1, s.d[0], s.d[0], (double*)out->cores[0], 1, s.d[0]));
-  } else {
-    QTT_HIP(copy_pad_rows(w.st, Yn, (int)P.rho[1], (int)rnext, rnext, Z, (int)P.m[0], rnext));
-    QTT_HIP(apply_q(w.st, ws + P.offM[0], (int)P.m[0], (int)P.rho[1], s.rc[1], ws + P.offT[0], Z, (int)rnext,
-                    rnext, false, ws + P.offScr));
-    QTT_HIP(copy_pad_rows(w.st, Z, (int)P.m[0], (int)rnext, rnext, (double*)out->cores[0], (int)P.m[0], rnext));
-  }
-  QTT_HIP(hipStreamSynchronize(w.st));
   if (info) {
     info->norm = norm;
     info->delta = (n > 1) ? rel_tol * norm / std::sqrt((double)(n - 1)) : 0.0;
@@ -603,8 +644,19 @@ hipError_t env_step_right(hipStream_t st, const T* F, const T* ak, const T* bk, 
                   rb0);
 }
 
+// The same step with the two GEMMs in the requested arithmetic (FP64 cores).
+hipError_t env_step_left_prec(hipStream_t st, int prec, const double* E, const double* ak, const double* bk, long ra0,
+                              long ra1, long rb0, long rb1, long d, double* Tt, double* Enext) {
+  if (prec == QTT_GEMM_FP64) return env_step_left<double>(st, E, ak, bk, ra0, ra1, rb0, rb1, d, Tt, Enext);
+  hipError_t e = gemm_prec(st, prec, false, false, (int)ra0, (int)(d * rb1), (int)rb0, E, rb0, bk, d * rb1, Tt,
+                           d * rb1);
+  if (e != hipSuccess) return e;
+  return gemm_prec(st, prec, true, false, (int)ra1, (int)rb1, (int)(ra0 * d), ak, ra1, Tt, rb1, Enext, rb1);
+}
+
 template <typename T>
-int inner_impl(qtt_context* h, const qtt_tt* a, const qtt_tt* b, double* out, void* ws_raw, hipStream_t st) {
+int inner_impl(qtt_context* h, const qtt_tt* a, const qtt_tt* b, double* out, void* ws_raw, hipStream_t st,
+               int prec = QTT_GEMM_FP64) {
   InnerPlan p = inner_plan(a, b);
   T* ws = (T*)align_ws(ws_raw);
   T* E = ws + p.offE0;
@@ -612,8 +664,13 @@ int inner_impl(qtt_context* h, const qtt_tt* a, const qtt_tt* b, double* out, vo
   T* Tt = ws + p.offT;
   QTT_HIP(fill_T<T>(st, E, 1.0, 1));
   for (int k = 0; k < a->n; ++k) {
-    QTT_HIP(env_step_left<T>(st, E, (const T*)a->cores[k], (const T*)b->cores[k], a->ranks[k], a->ranks[k + 1],
-                             b->ranks[k], b->ranks[k + 1], dphys(a, k), Tt, E2));
+    if constexpr (std::is_same<T, double>::value) {
+      QTT_HIP(env_step_left_prec(st, prec, E, (const T*)a->cores[k], (const T*)b->cores[k], a->ranks[k],
+                                 a->ranks[k + 1], b->ranks[k], b->ranks[k + 1], dphys(a, k), Tt, E2));
+    } else {
+      QTT_HIP(env_step_left<T>(st, E, (const T*)a->cores[k], (const T*)b->cores[k], a->ranks[k], a->ranks[k + 1],
+                               b->ranks[k], b->ranks[k + 1], dphys(a, k), Tt, E2));
+    }
     std::swap(E, E2);
   }
   T hv;
@@ -704,7 +761,7 @@ int batch_layout(const char* spec, int count, const qtt_tt* a, const qtt_tt* b, 
     if (a[i].dtype != QTT_F64 || b[i].dtype != QTT_F64) return QTT_ERR_DTYPE;
     const Shape& sh = Lo.shapes[i];
     if (sh.n > QTT_BATCH_MAXN) return QTT_ERR_UNSUPPORTED;
-    if ((st = make_plan(sh, max_rank, Lo.plans[i]))) return st;
+    if ((st = make_plan(sh, max_rank, Lo.plans[i], true, false))) return st;
     const Plan& P = Lo.plans[i];
     for (int k = 0; k + 1 < sh.n; ++k)
       if (P.m[k] > 512) return QTT_ERR_UNSUPPORTED;  // register panel of the workgroup QR
@@ -776,6 +833,9 @@ struct qtt_batch {
   long max_rank = 0;
   int max_sweeps = 0;
   float tuned_ms[4] = {0, 0, 0, 0};
+  TileMap tiles{};                                  // GEMM tile variant per shape bucket
+  int tile_shape[kGemmBuckets][3] = {};             // representative (M, N, K) of each bucket (0: unused)
+  float tile_ms[kGemmBuckets][kTileVariants] = {};  // probe time per variant (0: not measured)
 };
 
 namespace {
@@ -796,8 +856,112 @@ hipError_t batch_run(qtt_batch* p, hipStream_t s, int variant) {
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->h->device);
   const int grid = std::min(p->count, cus * ((variant & 2) ? 2 : 1));
   p->grid = grid;
-  return batched_launch(s, variant, grid, p->dtab, p->dorder, p->count, p->dqueue, p->tol, p->max_rank,
+  return batched_launch(s, variant, grid, p->dtab, p->dorder, p->count, p->dqueue, p->tiles, p->tol, p->max_rank,
                         p->max_sweeps, p->dranks, p->dtails, p->dstatus, p->maxL);
+}
+
+// Tile variant used for a bucket when none was measured: 64 rows / columns
+// when the bucket's M / N exceed 32.
+int default_tile(int bucket) {
+  const bool bm = bucket & 1, bn = bucket & 2;
+  return bm ? (bn ? 0 : 1) : (bn ? 2 : 3);
+}
+
+// The GEMM shapes the batched kernel will run, bucketed; per bucket the
+// shape with the most work (M N K times its call count) represents it.
+void batch_gemm_shapes(const BatchLayout& Lo, long max_rank, int (&rep)[kGemmBuckets][3]) {
+  double best[kGemmBuckets] = {};
+  auto add = [&](long M, long N, long K, long calls) {
+    if (M <= 0 || N <= 0 || K <= 0) return;
+    const int b = gemm_bucket((int)M, (int)N, (int)K);
+    const double wgt = (double)M * N * K * calls;
+    if (wgt > best[b]) {
+      best[b] = wgt;
+      rep[b][0] = (int)M;
+      rep[b][1] = (int)N;
+      rep[b][2] = (int)K;
+    }
+  };
+  for (size_t i = 0; i < Lo.shapes.size(); ++i) {
+    const Shape& sh = Lo.shapes[i];
+    const Plan& P = Lo.plans[i];
+    const bool mpo = sh.kind == K_MPO;
+    for (int k = 0; k < sh.n; ++k) {
+      add(P.rho[k] * sh.ra[k], (long)sh.dj[k] * sh.rb[k + 1], sh.rb[k], 1);
+      add(P.rho[k], sh.ra[k + 1], sh.ra[k] * (mpo ? sh.dj[k] : 1), (long)sh.d[k] * sh.rb[k + 1]);
+    }
+    long rnext = 1;
+    for (int k = sh.n - 1; k >= 1; --k) {
+      const long rows = P.rho[k], D = (long)sh.d[k] * rnext;
+      const long p = rows >= D ? D : rows;
+      long r = std::min(p, rows);
+      if (max_rank > 0) r = std::min<long>(r, max_rank);
+      add(p, r, D, 1);
+      rnext = std::max<long>(1, r);
+    }
+  }
+}
+
+// Tuner of the GEMM tiles: every tile variant runs the bucket's representative
+// shape on `grid` workgroups side by side (median of three launches); the
+// fastest wins.  Results are cached per (bucket shape, grid) in the tuning file.
+int tune_tiles(qtt_batch* p, const BatchLayout& Lo, long max_rank, bool tune, char* base, hipStream_t us, int grid) {
+  batch_gemm_shapes(Lo, max_rank, p->tile_shape);
+  for (int b = 0; b < kGemmBuckets; ++b) p->tiles.v[b] = (unsigned char)default_tile(b);
+  if (!tune) return QTT_OK;
+  // probe operands in the largest instance's workspace (overwritten by every run)
+  size_t big = 0;
+  for (size_t i = 1; i < Lo.plans.size(); ++i)
+    if (Lo.plans[i].total > Lo.plans[big].total) big = i;
+  double* scr = (double*)(base + Lo.instOff[big]);
+  const long cap = Lo.plans[big].total;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return QTT_ERR_HIP;
+  int rc = QTT_OK;
+  for (int b = 0; b < kGemmBuckets && rc == QTT_OK; ++b) {
+    const int M = p->tile_shape[b][0], N = p->tile_shape[b][1], K = p->tile_shape[b][2];
+    if (M <= 0) continue;
+    const long need = (long)M * K + (long)K * N + (long)M * N;
+    if (need > cap) continue;
+    std::ostringstream sig;
+    sig << "tile|" << b << "|" << M << "x" << N << "x" << K << "|" << grid;
+    const int cached = tune_lookup(sig.str());
+    if (cached >= 0 && cached < kTileVariants) {
+      p->tiles.v[b] = (unsigned char)cached;
+      continue;
+    }
+    double *A = scr, *B = scr + (long)M * K, *C = B + (long)K * N;
+    if (fill_f64(us, scr, 0.5, need) != hipSuccess) {
+      rc = QTT_ERR_HIP;
+      break;
+    }
+    float bestms = 1e30f;
+    int bestv = default_tile(b);
+    for (int v = 0; v < kTileVariants; ++v) {
+      float t[3];
+      for (int rep = 0; rep < 3; ++rep) {
+        if (hipEventRecord(e0, us) != hipSuccess || tile_probe_launch(us, v, grid, M, N, K, A, B, C) != hipSuccess ||
+            hipEventRecord(e1, us) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = QTT_ERR_HIP;
+          break;
+        }
+        (void)hipEventElapsedTime(&t[rep], e0, e1);
+      }
+      if (rc != QTT_OK) break;
+      std::sort(t, t + 3);
+      p->tile_ms[b][v] = t[1];
+      if (t[1] < bestms) {
+        bestms = t[1];
+        bestv = v;
+      }
+    }
+    if (rc != QTT_OK) break;
+    p->tiles.v[b] = (unsigned char)bestv;
+    tune_store(sig.str(), bestv);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 }  // namespace
@@ -1030,11 +1194,6 @@ int zip_sweep(qtt_context* h, hipStream_t st, double* ws, const Shape& s, const 
       const int swp = h->pin_int[0];
       if (!std::isfinite(t.norm)) return QTT_ERR_NONFINITE;
       if (!h->pin_int[1]) return QTT_ERR_NOCONV;
-      {
-        double jb = 0.0, jf = 0.0;
-        jacobi_sweep_cost(p, L, &jb, &jf);
-        prof::amend(prof::JACOBI, swp * jb, swp * jf);
-      }
       maxsw = std::max(maxsw, swp);
       const int rn = t.rank;
       if (outc == 0) {
@@ -1225,6 +1384,238 @@ int fit_sweeps(hipStream_t st, double* ws, const Shape& s, const FitPlan& F, qtt
   }
   QTT_HIP(frob_norm(st, core(n - 1), rc[n - 1] * s.d[n - 1], ws + F.offNrm));
   return QTT_OK;
+}
+
+// ---------------------------------------------------------------- two-core fitting
+// Sec. 3.3, multi-core strategy with super-cores of two cores: with the cores
+// left of the pair (q, q+1) left-orthonormal and those right of it
+// right-orthonormal, the best super-core is
+//   S[(a,i),(j,c)] = sum L_q[a,b] Y_q[b,i,d] Y_{q+1}[d,j,e] R_{q+2}[c,e],
+// decomposed again by a truncated SVD (rank rule of the rounding with
+// delta = rel_tol ||S||_F / sqrt(n-1), capped at max_rank), so the ranks of
+// the fitted train adapt to the product.
+struct Fit2Plan {
+  std::vector<long> ry, bnd;  // product ranks, capacity of the fitted train's ranks
+  std::vector<long> offY, offL, offF;
+  long offT1 = 0, offT2 = 0, offS = 0, offSt = 0, offTB = 0, offX = 0, offXc = 0, offV = 0, offYt = 0, offMV = 0;
+  long offSig = 0, offPerm = 0, offTrunc = 0, offCtr = 0, offSweeps = 0, offNrm = 0, offScr = 0;
+  long total = 0;
+};
+
+// Rank capacity of every bond of the fitted train: the guess's rank, or the
+// largest rank a split can produce (min of the left and right physical
+// products, the product's rank, max_rank), whichever is larger.
+std::vector<long> fit2_bounds(const Shape& s, const qtt_tt* c, long max_rank) {
+  const int n = s.n;
+  std::vector<long> left(n + 1, 1), right(n + 1, 1), b(n + 1, 1);
+  for (int k = 1; k <= n; ++k) left[k] = std::min<long>(left[k - 1] * s.d[k - 1], 1L << 40);
+  for (int k = n - 1; k >= 0; --k) right[k] = std::min<long>(right[k + 1] * s.d[k], 1L << 40);
+  for (int k = 1; k < n; ++k) {
+    long v = std::min({left[k], right[k], s.rc[k]});
+    if (max_rank > 0) v = std::min(v, max_rank);
+    b[k] = std::max<long>({v, c->ranks[k], 1L});
+  }
+  return b;
+}
+
+int make_fit2_plan(const Shape& s, const qtt_tt* c, long max_rank, Fit2Plan& F) {
+  const int n = s.n;
+  F.ry = s.rc;
+  F.bnd = fit2_bounds(s, c, max_rank);
+  long off = 0;
+  auto take = [&](long cnt) {
+    long o = off;
+    off += round_up(std::max(cnt, 1L), 32);
+    return o;
+  };
+  F.offY.assign(n, 0);
+  F.offL.assign(n + 1, 0);
+  F.offF.assign(n + 1, 0);
+  long maxT1 = 1, maxT2 = 1, maxS = 1, maxTB = 1, maxX = 1, maxP = 1, maxc = 1, maxE = 1;
+  for (int k = 0; k < n; ++k) {
+    F.offY[k] = take(F.ry[k] * s.d[k] * F.ry[k + 1]);
+    maxE = std::max(maxE, F.bnd[k] * s.d[k] * F.ry[k + 1]);  // environment step temporaries
+  }
+  for (int k = 0; k <= n; ++k) {
+    F.offL[k] = take(F.bnd[k] * F.ry[k]);
+    F.offF[k] = take(F.bnd[k] * F.ry[k]);
+  }
+  for (int q = 0; q + 1 < n; ++q) {
+    const long m = F.bnd[q] * s.d[q], cols = (long)s.d[q + 1] * F.bnd[q + 2];
+    maxT1 = std::max(maxT1, m * F.ry[q + 1]);
+    maxT2 = std::max(maxT2, F.ry[q + 1] * cols);
+    maxS = std::max(maxS, m * cols);
+    // both orientations of the split: rows M x L with M, L in {m, cols}
+    for (int o = 0; o < 2; ++o) {
+      const long p0 = o ? cols : m, L = o ? m : cols;
+      if (L > 1024 || p0 > kMaxRows) return QTT_ERR_UNSUPPORTED;
+      const long p = std::min(p0, L);
+      maxTB = std::max(maxTB, qr_t_doubles((int)p0, (int)p));
+      maxX = std::max(maxX, p * L);
+      maxP = std::max(maxP, p);
+      maxc = std::max({maxc, L, p0});
+    }
+  }
+  F.offT1 = take(std::max(maxT1, maxE));
+  F.offT2 = take(maxT2);
+  F.offS = take(maxS);
+  F.offSt = take(maxS);
+  F.offTB = take(maxTB);
+  F.offX = take(maxX);
+  F.offXc = take(maxX);
+  F.offV = take(maxX);
+  F.offYt = take(maxX);
+  F.offMV = take(maxS);
+  F.offSig = take(maxP);
+  F.offPerm = take(maxP / 2 + 1);
+  F.offTrunc = take(8);
+  F.offCtr = take(96);
+  F.offSweeps = take(1);
+  F.offNrm = take(1);
+  F.offScr = take(qr_scratch_doubles(maxc));
+  F.total = off;
+  return QTT_OK;
+}
+
+// Truncated SVD of M (p0 x L, row-major; overwritten by its Householder QR
+// when tall): vt (rn x L, ld L) the kept right singular vectors as rows,
+// mv (p0 x rn, ld rn) = M V_r = U_r Sigma_r.  Reads the decision back.
+int split_rows(qtt_context* h, hipStream_t st, double* ws, const Fit2Plan& F, double* M, int p0, int L,
+               double rel_tol, int nb, long max_rank, double* vt, double* mv, int& rn, double& tail, int& swp) {
+  double* TB = ws + F.offTB;
+  double* X = ws + F.offX;
+  double* Xc = ws + F.offXc;
+  double* Yt = ws + F.offYt;
+  double* sig = ws + F.offSig;
+  int* perm = (int*)(ws + F.offPerm);
+  TruncOut* tr = (TruncOut*)(ws + F.offTrunc);
+  unsigned* ctr = (unsigned*)(ws + F.offCtr);
+  int* sweeps = (int*)(ws + F.offSweeps);
+  double* nrm = ws + F.offNrm;
+  double* scr = ws + F.offScr;
+  const bool tall = p0 >= L;
+  const int p = tall ? L : p0;
+  if (tall) {
+    QTT_HIP(householder_qr(st, M, p0, L, L, TB, scr));
+    QTT_HIP(extract_r(st, M, L, L, L, Xc));
+  } else {
+    QTT_HIP(copy_pad_rows(st, M, p0, L, L, Xc, p0, L));
+  }
+  QTT_HIP(row_norms_sorted(st, Xc, p, L, sig, perm));
+  QTT_HIP(permute_rows(st, Xc, p, L, perm, X));
+  QTT_HIP(jacobi_rows(st, X, p, L, ctr, h->max_sweeps, sweeps, sig));  // sig[0]: largest row norm
+  QTT_HIP(row_norms_sorted(st, X, p, L, sig, perm));
+  QTT_HIP(frob_norm(st, sig, p, nrm));  // ||S||_F of the super-core being split
+  QTT_HIP(truncate_decide(st, sig, p, nrm, rel_tol, nb, max_rank, tr));
+  QTT_HIP(hipMemcpyAsync(h->pin_int, sweeps, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  int e = readback(h, st, tr, sizeof(TruncOut), h->pin_trunc);
+  if (e) return e;
+  const TruncOut t = *h->pin_trunc;
+  if (!std::isfinite(t.norm)) return QTT_ERR_NONFINITE;
+  if (!h->pin_int[1]) return QTT_ERR_NOCONV;
+  swp = h->pin_int[0];
+  rn = t.rank;
+  tail = t.tail_r;
+  QTT_HIP(gather_rows_normalized(st, X, L, perm, sig, tr, vt, L, rn));
+  QTT_HIP(gemm_f64(st, false, true, p, rn, L, 1.0, Xc, L, 0, vt, L, 0, 0.0, Yt, rn, 0, 1));
+  QTT_HIP(copy_pad_rows(st, Yt, p, rn, rn, mv, p0, rn));
+  if (tall) QTT_HIP(apply_q(st, M, p0, p, L, TB, mv, rn, rn, false, scr));
+  return QTT_OK;
+}
+
+// S = L_q Y_q Y_{q+1} R_{q+2}^T as (rc_q d_q) x (d_{q+1} rc_{q+2}).
+hipError_t fit2_supercore(hipStream_t st, double* ws, const Shape& s, const Fit2Plan& F, const std::vector<long>& rc,
+                          int q, double* S) {
+  const long rc0 = rc[q], rc2 = rc[q + 2], ry0 = F.ry[q], ry1 = F.ry[q + 1], ry2 = F.ry[q + 2];
+  const long d0 = s.d[q], d1 = s.d[q + 1];
+  double* T1 = ws + F.offT1;
+  double* T2 = ws + F.offT2;
+  hipError_t e = gemm_f64(st, false, false, (int)rc0, (int)(d0 * ry1), (int)ry0, 1.0, ws + F.offL[q], ry0, 0,
+                          ws + F.offY[q], d0 * ry1, 0, 0.0, T1, d0 * ry1, 0, 1);
+  if (e != hipSuccess) return e;
+  e = gemm_f64(st, false, true, (int)(ry1 * d1), (int)rc2, (int)ry2, 1.0, ws + F.offY[q + 1], ry2, 0,
+               ws + F.offF[q + 2], ry2, 0, 0.0, T2, rc2, 0, 1);
+  if (e != hipSuccess) return e;
+  return gemm_f64(st, false, false, (int)(rc0 * d0), (int)(d1 * rc2), (int)ry1, 1.0, T1, ry1, 0, T2, d1 * rc2, 0,
+                  0.0, S, d1 * rc2, 0, 1);
+}
+
+int fit2_sweeps(qtt_context* h, hipStream_t st, double* ws, const Shape& s, const Fit2Plan& F, qtt_tt* c,
+                std::vector<long>& rc, int nsweeps, double rel_tol, long max_rank, double* tails, int& maxsw) {
+  const int n = s.n;
+  auto core = [&](int k) { return (double*)c->cores[k]; };
+  auto Y = [&](int k) { return (const double*)(ws + F.offY[k]); };
+  double* S = ws + F.offS;
+  double* St = ws + F.offSt;
+  double* V = ws + F.offV;
+  double* MV = ws + F.offMV;
+  double* T = ws + F.offT1;
+  QTT_HIP(fill_f64(st, ws + F.offL[0], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + F.offF[n], 1.0, 1));
+  for (int k = 0; k + 2 < n; ++k)
+    QTT_HIP(env_step_left<double>(st, ws + F.offL[k], core(k), Y(k), rc[k], rc[k + 1], F.ry[k], F.ry[k + 1], s.d[k],
+                                  T, ws + F.offL[k + 1]));
+  maxsw = 0;
+  int split_no = 0;
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    // pairs from the right end: core q+1 <- V^T (right-orthonormal), core q <- U Sigma
+    for (int q = n - 2; q >= 0; --q) {
+      const long m = rc[q] * s.d[q], cols = (long)s.d[q + 1] * rc[q + 2];
+      QTT_HIP(fit2_supercore(st, ws, s, F, rc, q, S));
+      int rn = 0, swp = 0;
+      double tail = 0.0;
+      int e = split_rows(h, st, ws, F, S, (int)m, (int)cols, rel_tol, n - 1, max_rank, V, MV, rn, tail, swp);
+      if (e) return e;
+      if (rn > F.bnd[q + 1]) return QTT_ERR_UNSUPPORTED;
+      maxsw = std::max(maxsw, swp);
+      if (tails) tails[split_no] = tail;
+      ++split_no;
+      QTT_HIP(copy_pad_rows(st, V, rn, (int)cols, cols, core(q + 1), rn, cols));
+      QTT_HIP(copy_pad_rows(st, MV, (int)m, rn, rn, core(q), (int)m, rn));
+      rc[q + 1] = rn;
+      QTT_HIP(env_step_right<double>(st, ws + F.offF[q + 2], core(q + 1), Y(q + 1), rc[q + 1], rc[q + 2], F.ry[q + 1],
+                                     F.ry[q + 2], s.d[q + 1], T, ws + F.offF[q + 1]));
+    }
+    // and back from the left end: core q <- U (left-orthonormal), core q+1 <- Sigma V^T
+    for (int q = 0; q + 1 < n; ++q) {
+      const long m = rc[q] * s.d[q], cols = (long)s.d[q + 1] * rc[q + 2];
+      QTT_HIP(fit2_supercore(st, ws, s, F, rc, q, S));
+      QTT_HIP(transpose(st, S, (int)m, (int)cols, cols, St, m));
+      int rn = 0, swp = 0;
+      double tail = 0.0;
+      int e = split_rows(h, st, ws, F, St, (int)cols, (int)m, rel_tol, n - 1, max_rank, V, MV, rn, tail, swp);
+      if (e) return e;
+      if (rn > F.bnd[q + 1]) return QTT_ERR_UNSUPPORTED;
+      maxsw = std::max(maxsw, swp);
+      if (tails) tails[split_no] = tail;
+      ++split_no;
+      QTT_HIP(transpose(st, V, rn, (int)m, m, core(q), rn));        // (rc_q d_q) x rn
+      QTT_HIP(transpose(st, MV, (int)cols, rn, rn, core(q + 1), cols));  // rn x (d_{q+1} rc_{q+2})
+      rc[q + 1] = rn;
+      QTT_HIP(env_step_left<double>(st, ws + F.offL[q], core(q), Y(q), rc[q], rc[q + 1], F.ry[q], F.ry[q + 1], s.d[q],
+                                    T, ws + F.offL[q + 1]));
+    }
+  }
+  QTT_HIP(frob_norm(st, core(n - 1), rc[n - 1] * s.d[n - 1], ws + F.offNrm));
+  return QTT_OK;
+}
+
+int fit2_setup(const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt* c, long max_rank, Shape& s,
+               Fit2Plan& F, size_t& orth_bytes) {
+  int st = shape_from_pair(spec, a, b, s);
+  if (st) return st;
+  if (a->dtype != QTT_F64 || b->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  if ((st = check_tt(c, 1))) return st;
+  if (c->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  if (c->n != s.n) return QTT_ERR_SHAPE;
+  for (int k = 0; k < s.n; ++k)
+    if (dphys(c, k) != s.d[k]) return QTT_ERR_SHAPE;
+  Shape sc;
+  shape_from_tt(c, sc);
+  Plan P;
+  if ((st = make_plan(sc, 0, P, false))) return st;
+  orth_bytes = ws_bytes_of(P);
+  return make_fit2_plan(s, c, max_rank, F);
 }
 
 int fit_setup(const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt* c, Shape& s, FitPlan& F,
@@ -1519,6 +1910,26 @@ int qtt_contract_round(qtt_handle h, const char* spec, const qtt_tt* a, const qt
   return round_common(h, s, nullptr, a, b, out, rel_tol, max_rank, prec, info, ws, ws_bytes, stream);
 }
 
+int qtt_contract_round_async(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* out,
+                             double rel_tol, int64_t max_rank, int prec, int64_t* ranks_dev, int32_t* status_dev,
+                             void* ws, size_t ws_bytes, void* stream) {
+  if (!h || !ranks_dev || !status_dev) return QTT_ERR_ARG;
+  Shape s;
+  int st = contract_round_args(spec, a, b, out, s);
+  if (st) return st;
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return QTT_ERR_ARG;
+  if (prec < QTT_GEMM_FP64 || prec > QTT_GEMM_BF16X6) return QTT_ERR_ARG;
+  Plan P;
+  if ((st = make_plan(s, max_rank, P))) return st;
+  if (!ws || ws_bytes < ws_bytes_of(P)) return QTT_ERR_WORKSPACE;
+  Scoped sc(h->device);
+  Sweep w{h, (hipStream_t)stream, align_ws(ws), &s, &P, prec};
+  if ((st = qr_sweep(w, nullptr, a, b))) return st;
+  std::vector<long> newr;
+  static_assert(sizeof(long long) == sizeof(int64_t), "rank record width");
+  return svd_sweep(w, out, rel_tol, max_rank, nullptr, newr, false, (long long*)ranks_dev, (int*)status_dev);
+}
+
 int qtt_contract_round_noalloc(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* out,
                                double rel_tol, int64_t max_rank, int prec, qtt_round_info* info, void* stream) {
   if (!h) return QTT_ERR_ARG;
@@ -1533,17 +1944,25 @@ int qtt_contract_round_noalloc(qtt_handle h, const char* spec, const qtt_tt* a, 
                       (size_t)QTT_NOALLOC_SCRATCH_BYTES, stream);
 }
 
-int qtt_inner(qtt_handle h, const qtt_tt* a, const qtt_tt* b, double* out_host, void* ws, size_t ws_bytes,
-              void* stream) {
+int qtt_inner_prec(qtt_handle h, const qtt_tt* a, const qtt_tt* b, int prec, double* out_host, void* ws,
+                   size_t ws_bytes, void* stream) {
   if (!h || !out_host) return QTT_ERR_ARG;
+  if (prec < QTT_GEMM_FP64 || prec > QTT_GEMM_BF16X6) return QTT_ERR_ARG;
   int st;
   if ((st = check_tt(a, 1)) || (st = check_tt(b, 1))) return st;
   if ((st = same_layout(a, b))) return st;
+  // the reduced-precision forms take FP64 cores (FP32 cores already run FP32 GEMMs)
+  if (prec != QTT_GEMM_FP64 && a->dtype != QTT_F64) return QTT_ERR_DTYPE;
   const size_t need = (size_t)inner_plan(a, b).total * 8 + 256;
   if (!ws || ws_bytes < need) return QTT_ERR_WORKSPACE;
   Scoped sc(h->device);
-  if (a->dtype == QTT_F64) return inner_impl<double>(h, a, b, out_host, ws, (hipStream_t)stream);
+  if (a->dtype == QTT_F64) return inner_impl<double>(h, a, b, out_host, ws, (hipStream_t)stream, prec);
   return inner_impl<float>(h, a, b, out_host, ws, (hipStream_t)stream);
+}
+
+int qtt_inner(qtt_handle h, const qtt_tt* a, const qtt_tt* b, double* out_host, void* ws, size_t ws_bytes,
+              void* stream) {
+  return qtt_inner_prec(h, a, b, QTT_GEMM_FP64, out_host, ws, ws_bytes, stream);
 }
 
 int qtt_inner_backward(qtt_handle h, const qtt_tt* a, const qtt_tt* b, double g, qtt_tt* da, qtt_tt* db, void* ws,
@@ -1733,6 +2152,13 @@ int qtt_batch_plan_create(qtt_handle h, const char* spec, int32_t count, const q
       hipMemcpyAsync(p->dorder, order.data(), (size_t)count * sizeof(int), hipMemcpyHostToDevice, us) != hipSuccess ||
       hipStreamSynchronize(us) != hipSuccess)
     return fail(QTT_ERR_HIP);
+  // GEMM tile per shape bucket (probe-timed or cached), then the kernel variant
+  {
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int tst = tune_tiles(p, Lo, max_rank, tune != 0, base, us, std::min(count, cus));
+    if (tst != QTT_OK) return fail(tst);
+  }
   // variant: cached tuning result, measured now, or the default
   std::ostringstream sig;
   sig << spec << "|" << count << "|" << rel_tol << "|" << max_rank;
@@ -1823,6 +2249,16 @@ int qtt_batch_plan_info(qtt_batch_plan plan, int32_t* variant, int32_t* grid, fl
   *grid = plan->grid;
   if (tuned_ms)
     for (int v = 0; v < 4; ++v) tuned_ms[v] = plan->tuned_ms[v];
+  return QTT_OK;
+}
+
+int qtt_batch_plan_tiles(qtt_batch_plan plan, uint8_t* tiles, int32_t* shapes, float* probe_ms) {
+  if (!plan) return QTT_ERR_ARG;
+  for (int b = 0; b < kGemmBuckets; ++b) {
+    if (tiles) tiles[b] = plan->tiles.v[b];
+    for (int c = 0; shapes && c < 3; ++c) shapes[3 * b + c] = plan->tile_shape[b][c];
+    for (int v = 0; probe_ms && v < kTileVariants; ++v) probe_ms[kTileVariants * b + v] = plan->tile_ms[b][v];
+  }
   return QTT_OK;
 }
 
@@ -1989,6 +2425,72 @@ int qtt_fit(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qt
   if (e) return e;
   if (!std::isfinite(h->pin_dbl[0])) return QTT_ERR_NONFINITE;
   if (norm_host) *norm_host = h->pin_dbl[0];
+  for (int k = 0; k <= n; ++k) c->ranks[k] = rc[k];
+  return QTT_OK;
+}
+
+int qtt_fit2_query(const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt* c, int64_t max_rank,
+                   int64_t* bounds, size_t* bytes) {
+  if (!bytes) return QTT_ERR_ARG;
+  Shape s;
+  Fit2Plan F;
+  size_t ob = 0;
+  int st = fit2_setup(spec, a, b, c, max_rank, s, F, ob);
+  if (st) return st;
+  *bytes = std::max(ob, (size_t)F.total * sizeof(double) + 256);
+  if (bounds)
+    for (int k = 0; k <= s.n; ++k) bounds[k] = F.bnd[k];
+  return QTT_OK;
+}
+
+int qtt_fit2(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qtt_tt* c, int32_t nsweeps,
+             double rel_tol, int64_t max_rank, qtt_round_info* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return QTT_ERR_ARG;
+  if (nsweeps < 0 || !(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return QTT_ERR_ARG;
+  Shape s;
+  Fit2Plan F;
+  size_t ob = 0;
+  int st = fit2_setup(spec, a, b, c, max_rank, s, F, ob);
+  if (st) return st;
+  if (!ws || ws_bytes < std::max(ob, (size_t)F.total * sizeof(double) + 256)) return QTT_ERR_WORKSPACE;
+  double nrm = 0.0;
+  // the guess, orthogonalised from the left (centre at core n; ranks may shrink)
+  if ((st = qtt_orthogonalize(h, c, &nrm, ws, ws_bytes, stream))) return st;
+  Scoped sc(h->device);
+  hipStream_t strm = (hipStream_t)stream;
+  double* w = align_ws(ws);
+  const int n = s.n;
+  for (int k = 0; k < n; ++k) {
+    const int ra0 = (int)s.ra[k], ra1 = (int)s.ra[k + 1], rb0 = (int)s.rb[k], rb1 = (int)s.rb[k + 1];
+    hipError_t e;
+    if (s.kind == K_HAD)
+      e = contract_hadamard<double>(strm, (const double*)a->cores[k], ra0, s.d[k], ra1, (const double*)b->cores[k],
+                                    rb0, rb1, w + F.offY[k]);
+    else
+      e = contract_mpo<double>(strm, (const double*)a->cores[k], ra0, s.d[k], s.dj[k], ra1,
+                               (const double*)b->cores[k], rb0, rb1, w + F.offY[k]);
+    if (e != hipSuccess) return QTT_ERR_HIP;
+  }
+  std::vector<long> rc(n + 1);
+  for (int k = 0; k <= n; ++k) rc[k] = c->ranks[k];
+  int maxsw = 0;
+  if (n == 1) {
+    // one core: the product itself
+    QTT_HIP(copy_pad_rows(strm, w + F.offY[0], 1, s.d[0], s.d[0], (double*)c->cores[0], 1, s.d[0]));
+    QTT_HIP(frob_norm(strm, (double*)c->cores[0], s.d[0], w + F.offNrm));
+  } else {
+    std::vector<double> tails((size_t)2 * (n - 1) * std::max(nsweeps, 1));
+    if ((st = fit2_sweeps(h, strm, w, s, F, c, rc, nsweeps, rel_tol, max_rank, tails.data(), maxsw))) return st;
+    if (info && info->tail && nsweeps > 0)  // the discarded tails of the last sweep's left-to-right splits
+      for (int k = 0; k + 1 < n; ++k) info->tail[k] = tails[(size_t)(2 * nsweeps - 1) * (n - 1) + k];
+  }
+  int e = readback(h, strm, w + F.offNrm, sizeof(double), h->pin_dbl);
+  if (e) return e;
+  if (!std::isfinite(h->pin_dbl[0])) return QTT_ERR_NONFINITE;
+  if (info) {
+    info->norm = h->pin_dbl[0];
+    info->jacobi_sweeps_max = maxsw;
+  }
   for (int k = 0; k <= n; ++k) c->ranks[k] = rc[k];
   return QTT_OK;
 }

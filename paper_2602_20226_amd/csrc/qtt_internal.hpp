@@ -93,8 +93,6 @@ hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, do
 // without rotations was reached within max_sweeps (converged), else 0.
 // ref_norm (device, nullable): the largest input row norm; rows whose norm
 // falls below eps^2 times it are deflated to zero.
-// Algorithmic bytes and FLOP of one Jacobi sweep on p rows of length L.
-void jacobi_sweep_cost(int p, int L, double* bytes, double* flops);
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
                        int* sweeps_dev, const double* ref_norm = nullptr);
 // dst[j] = src[perm[j]] (row gather).
@@ -129,6 +127,21 @@ hipError_t truncate_decide(hipStream_t s, const double* sig, int cnt, const doub
 // rmax_host bounds the launch.
 hipError_t gather_rows_normalized(hipStream_t s, const double* X, int L, const int* perm, const double* sig,
                                   const TruncOut* t, double* out, long ldo, int rmax_host);
+// V (rb x L): rows perm[0:r] of X scaled to unit norm (r = t->rank on the
+// device), zero rows r..rb-1.
+hipError_t gather_rows_padded(hipStream_t s, const double* X, int L, const int* perm, const double* sig,
+                              const TruncOut* t, double* V, int rb);
+// out[a][i r + c] = B[a][i rb + c] for c < r (r = *r_dev on the device), zeros
+// after the first d r entries of each row of length d rb.
+hipError_t compact_cols(hipStream_t s, const double* B, int rows, int d, int rb, const int* r_dev, double* out);
+// Compact core [r0, d r1] (r0 = *r0_dev, r1 = *r1_dev) from the leading
+// entries of the first r0 rows of V (row length L); rows_bound >= r0.
+hipError_t core_from_rows(hipStream_t s, const double* V, int rows_bound, int L, const int* r0_dev, int d,
+                          const int* r1_dev, double* out);
+// ranks[0..n] and a status word from the per-bond decisions t[0..n-2] and the
+// Jacobi records sweeps[2 (n-1)] (see k_round_record).
+hipError_t round_record(hipStream_t s, const TruncOut* t, const int* sweeps, int n, const double* norm_dev,
+                        long long* ranks, int* status, int code_nonfinite, int code_noconv);
 long qr_t_doubles(int m, int n);
 
 // ---------------------------------------------------------------- kernel setup

@@ -22,6 +22,8 @@
 #include "qtt_device.hpp"
 #include "qtt_internal.hpp"
 
+#include <algorithm>
+
 namespace qtt {
 
 namespace {
@@ -361,6 +363,77 @@ __global__ void k_gather_rows(const double* __restrict__ X, int L, const int* __
   }
 }
 
+// Rows of V (rb x L): V[j] = X[perm[j]] / sig[j] for j < r = t->rank (zero
+// when sig[j] is zero), zero rows for r <= j < rb.
+__global__ void k_gather_rows_padded(const double* __restrict__ X, int L, const int* __restrict__ perm,
+                                     const double* __restrict__ sig, const TruncOut* __restrict__ t,
+                                     double* __restrict__ V, int rb) {
+  const int r = t->rank;
+  const long total = (long)rb * L;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / L), c = (int)(e % L);
+    double v = 0.0;
+    if (j < r) {
+      const double s = sig[j];
+      v = (s > 0.0) ? X[(long)perm[j] * L + c] / s : 0.0;
+    }
+    V[e] = v;
+  }
+}
+
+// out[a][i r + c] = B[a][i rb + c] for c < r = *r_dev (r <= rb); the rest of
+// each output row (length d rb) is zero.  Moves the kept columns of every
+// physical index to the front, so that a matrix whose rank r is known only on
+// the device has exactly zero trailing columns.
+__global__ void k_compact_cols(const double* __restrict__ B, int rows, int d, int rb, const int* __restrict__ r_dev,
+                               double* __restrict__ out) {
+  const int r = *r_dev;
+  const long w = (long)d * rb;
+  const long total = (long)rows * w;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long a = e / w;
+    const int q = (int)(e % w);
+    double v = 0.0;
+    if (q < d * r) {
+      const int i = q / r, c = q % r;
+      v = B[a * w + (long)i * rb + c];
+    }
+    out[e] = v;
+  }
+}
+
+// Compact core [r0, w] with w = d r1 (r0 = *r0_dev, r1 = *r1_dev): the
+// leading w entries of the first r0 rows of V (row length L).
+__global__ void k_core_from_rows(const double* __restrict__ V, int L, const int* __restrict__ r0_dev, int d,
+                                 const int* __restrict__ r1_dev, double* __restrict__ out, int rows_bound) {
+  const int r0 = *r0_dev, w = d * *r1_dev;
+  const long total = (long)min(r0, rows_bound) * w;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long j = e / w;
+    const int c = (int)(e % w);
+    out[e] = V[j * L + c];
+  }
+}
+
+// Ranks and status of a rounding from the per-bond decisions: ranks[0] =
+// ranks[n] = 1, ranks[k] = t[k-1].rank; status 0, or the (negative) code of a
+// non-finite norm or of a Jacobi run that did not converge (sweeps: two ints
+// per bond, the second the converged flag).
+__global__ void k_round_record(const TruncOut* __restrict__ t, const int* __restrict__ sweeps, int n,
+                               const double* __restrict__ norm_dev, long long* __restrict__ ranks,
+                               int* __restrict__ status, int code_nonfinite, int code_noconv) {
+  if (blockIdx.x != 0) return;
+  for (int k = threadIdx.x; k <= n; k += blockDim.x) ranks[k] = (k == 0 || k == n) ? 1 : t[k - 1].rank;
+  if (threadIdx.x == 0) {
+    int st = 0;
+    const double nr = norm_dev[0];
+    if (!(nr == nr) || nr > 1.7976931348623157e308) st = code_nonfinite;
+    for (int k = 1; st == 0 && k < n; ++k)
+      if (!sweeps[2 * (k - 1) + 1]) st = code_noconv;
+    status[0] = st;
+  }
+}
+
 inline int gsz(long n) {
   long g = (n + 255) / 256;
   if (g < 1) g = 1;
@@ -405,22 +478,16 @@ hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter
   // only the E = 16 instance needs more than 64 KiB; jacobi_configure()
   // raises its limit when a handle is created
   if (shmem > (E == 16 ? kJacobiBigLds : 64 * 1024)) return hipErrorInvalidValue;
-  // Work is recorded per sweep by the caller once the sweep count is known
-  // (jacobi_sweep_cost); the launch itself is only timed here.
-  if (prof::active(prof::JACOBI)) prof::begin(s, prof::JACOBI, 0.0, 0.0);
+  // Algorithmic work of the launch under the fixed SVD convention: 8 sweeps
+  // of 9 n^3 (n = min(p, L)), whatever the sweeps taken; bytes: the matrix
+  // read once and written once.
+  if (prof::active(prof::JACOBI)) {
+    const double nn = (double)std::min(p, L);
+    prof::begin(s, prof::JACOBI, 2.0 * 8.0 * (double)p * L, 8.0 * 9.0 * nn * nn * nn);
+  }
   e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(JNT), args, shmem, s);
   prof::end(s);
   return e;
-}
-
-void jacobi_sweep_cost(int p, int L, double* bytes, double* flops) {
-  // every round moves both blocks of every pair in and out of the workgroups:
-  // 2 (nb2 - 1) passes over the padded p x L matrix; every row pair costs
-  // three dot products and one rotation of length L
-  const int nblk = (p + JB - 1) / JB;
-  const int nb2 = nblk + (nblk & 1);
-  *bytes = 2.0 * (nb2 - 1) * (double)nb2 * JB * L * 8.0;
-  *flops = 0.5 * (double)p * (p - 1) * 12.0 * L;
 }
 
 hipError_t row_norms_sorted(hipStream_t s, const double* X, int p, int L, double* sig_sorted, int* perm) {
@@ -440,6 +507,34 @@ hipError_t permute_rows(hipStream_t s, const double* src, int p, int L, const in
 hipError_t truncate_decide(hipStream_t s, const double* sig, int cnt, const double* norm_dev, double rel_tol,
                            int nbonds, long max_rank, TruncOut* out_dev) {
   hipLaunchKernelGGL(k_truncate, dim3(1), dim3(64), 0, s, sig, cnt, norm_dev, rel_tol, nbonds, max_rank, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t gather_rows_padded(hipStream_t s, const double* X, int L, const int* perm, const double* sig,
+                              const TruncOut* t, double* V, int rb) {
+  if (rb <= 0 || L <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows_padded, dim3(gsz((long)rb * L)), dim3(256), 0, s, X, L, perm, sig, t, V, rb);
+  return hipGetLastError();
+}
+
+hipError_t compact_cols(hipStream_t s, const double* B, int rows, int d, int rb, const int* r_dev, double* out) {
+  if (rows <= 0 || d <= 0 || rb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact_cols, dim3(gsz((long)rows * d * rb)), dim3(256), 0, s, B, rows, d, rb, r_dev, out);
+  return hipGetLastError();
+}
+
+hipError_t core_from_rows(hipStream_t s, const double* V, int rows_bound, int L, const int* r0_dev, int d,
+                          const int* r1_dev, double* out) {
+  if (rows_bound <= 0 || L <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_core_from_rows, dim3(gsz((long)rows_bound * L)), dim3(256), 0, s, V, L, r0_dev, d, r1_dev,
+                     out, rows_bound);
+  return hipGetLastError();
+}
+
+hipError_t round_record(hipStream_t s, const TruncOut* t, const int* sweeps, int n, const double* norm_dev,
+                        long long* ranks, int* status, int code_nonfinite, int code_noconv) {
+  hipLaunchKernelGGL(k_round_record, dim3(1), dim3(64), 0, s, t, sweeps, n, norm_dev, ranks, status, code_nonfinite,
+                     code_noconv);
   return hipGetLastError();
 }
 

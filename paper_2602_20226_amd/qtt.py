@@ -37,6 +37,7 @@ EXPORTS = [
     "qtt_batch_plan_create", "qtt_batch_plan_launch", "qtt_batch_plan_results", "qtt_batch_plan_info",
     "qtt_batch_plan_destroy", "qtt_contract_zipup", "qtt_zipup_query", "qtt_add",
     "qtt_fit", "qtt_fit_workspace_size", "qtt_set_jacobi_max_sweeps", "qtt_contract_round_noalloc",
+    "qtt_inner_prec", "qtt_batch_plan_tiles", "qtt_contract_round_async", "qtt_fit2", "qtt_fit2_query",
 ]
 # size of the fixed device array behind qtt_contract_round_noalloc
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -101,9 +102,12 @@ def load_library():
     L.qtt_round.argtypes = [vp, P(TT), C.c_double, C.c_int64, C.c_int, P(RoundInfoC), vp, C.c_size_t, vp]
     L.qtt_contract_round.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_double, C.c_int64, C.c_int,
                                      P(RoundInfoC), vp, C.c_size_t, vp]
+    L.qtt_contract_round_async.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_double, C.c_int64, C.c_int,
+                                           vp, vp, vp, C.c_size_t, vp]
     L.qtt_contract_round_noalloc.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_double, C.c_int64, C.c_int,
                                              P(RoundInfoC), vp]
     L.qtt_inner.argtypes = [vp, P(TT), P(TT), P(C.c_double), vp, C.c_size_t, vp]
+    L.qtt_inner_prec.argtypes = [vp, P(TT), P(TT), C.c_int, P(C.c_double), vp, C.c_size_t, vp]
     L.qtt_inner_backward.argtypes = [vp, P(TT), P(TT), C.c_double, P(TT), P(TT), vp, C.c_size_t, vp]
     L.qtt_contract_backward.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), P(TT), P(TT), vp, C.c_size_t, vp]
     L.qtt_batch_workspace_size.argtypes = [vp, C.c_char_p, C.c_int32, P(TT), P(TT), C.c_int64, P(C.c_size_t)]
@@ -113,10 +117,14 @@ def load_library():
     L.qtt_batch_plan_results.argtypes = [vp, P(C.c_int64), P(C.c_double), vp]
     L.qtt_batch_plan_info.argtypes = [vp, P(C.c_int32), P(C.c_int32), P(C.c_float)]
     L.qtt_batch_plan_destroy.argtypes = [vp]
+    L.qtt_batch_plan_tiles.argtypes = [vp, P(C.c_uint8), P(C.c_int32), P(C.c_float)]
     L.qtt_contract_zipup.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_double, C.c_int64, C.c_int32, C.c_int,
                                      P(RoundInfoC), vp, C.c_size_t, vp]
     L.qtt_fit.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_int32, P(C.c_double), vp, C.c_size_t, vp]
     L.qtt_fit_workspace_size.argtypes = [C.c_char_p, P(TT), P(TT), P(TT), P(C.c_size_t)]
+    L.qtt_fit2.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_int32, C.c_double, C.c_int64, P(RoundInfoC),
+                           vp, C.c_size_t, vp]
+    L.qtt_fit2_query.argtypes = [C.c_char_p, P(TT), P(TT), P(TT), C.c_int64, P(C.c_int64), P(C.c_size_t)]
     L.qtt_add.argtypes = [vp, C.c_int32, P(TT), P(C.c_double), P(TT), vp]
     L.qtt_zipup_query.argtypes = [C.c_char_p, P(TT), P(TT), C.c_int64, C.c_int32, P(C.c_int64), P(C.c_size_t)]
     L.qtt_set_jacobi_max_sweeps.argtypes = [vp, C.c_int32]
@@ -315,7 +323,8 @@ def add(terms: Sequence[Sequence[torch.Tensor]], coeffs: Optional[Sequence[float
     return out
 
 
-def inner(a: Sequence[torch.Tensor], b: Sequence[torch.Tensor]) -> float:
+def inner(a: Sequence[torch.Tensor], b: Sequence[torch.Tensor], prec: str = "fp64") -> float:
+    """<a, b> by the environment sweep; `prec` selects the GEMM arithmetic."""
     L = load_library()
     h = handle(a[0].device.index)
     va, vb = TTView(list(a), 1), TTView(list(b), 1)
@@ -324,8 +333,12 @@ def inner(a: Sequence[torch.Tensor], b: Sequence[torch.Tensor]) -> float:
                                 C.byref(nb)), "qtt_workspace_size")
     ws = _workspace(nb.value, a[0].device)
     out = C.c_double()
-    _check(L.qtt_inner(h.ptr, C.byref(va.struct), C.byref(vb.struct), C.byref(out), C.c_void_p(ws.data_ptr()),
-                       ws.numel(), _stream_ptr()), "qtt_inner")
+    if prec == "fp64":
+        _check(L.qtt_inner(h.ptr, C.byref(va.struct), C.byref(vb.struct), C.byref(out), C.c_void_p(ws.data_ptr()),
+                           ws.numel(), _stream_ptr()), "qtt_inner")
+    else:
+        _check(L.qtt_inner_prec(h.ptr, C.byref(va.struct), C.byref(vb.struct), PREC[prec], C.byref(out),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr()), "qtt_inner_prec")
     return out.value
 
 
@@ -464,6 +477,51 @@ def contract_round(spec: str, a, b, rel_tol: float, max_rank: int = 0, prec: str
     return info.result(cores, ranks, n)
 
 
+class ContractRoundAsync:
+    """Stream-ordered contract + round (qtt_contract_round_async) with its
+    buffers allocated once: output cores at the rank bounds, the workspace,
+    and the device rank / status record.  `enqueue()` only enqueues work on
+    the current stream (so it can be captured in a CUDA/HIP graph);
+    `result()` reads the record after synchronising."""
+
+    def __init__(self, spec: str, a, b, rel_tol: float, max_rank: int = 0, prec: str = "fp64"):
+        L = load_library()
+        self.spec, self.rel_tol, self.max_rank, self.prec = spec, float(rel_tol), int(max_rank), prec
+        self.h = handle(a[0].device.index)
+        self.va, self.vb = TTView(list(a), _legs(spec)), TTView(list(b), 1)
+        n = len(a)
+        self.n = n
+        self.d = [c.shape[1] for c in a]
+        rc = [x * y for x, y in zip(self.va.ranks(), self.vb.ranks())]
+        bnd = rank_bounds(rc, self.d, max_rank)
+        dev = a[0].device
+        self.out_buffers = [torch.zeros(bnd[k] * self.d[k] * bnd[k + 1], dtype=torch.float64, device=dev)
+                            for k in range(n)]
+        self.vo = TTView(self.out_buffers, 1, ranks_override=bnd, phys_override=self.d)
+        nb = C.c_size_t()
+        _check(L.qtt_workspace_size(self.h.ptr, OP_CONTRACT_ROUND, spec.encode(), C.byref(self.va.struct),
+                                    C.byref(self.vb.struct), self.max_rank, PREC[prec], C.byref(nb)),
+               "qtt_workspace_size")
+        self.ws = _workspace(nb.value, dev)
+        self.ranks_dev = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+        self.status_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def enqueue(self):
+        _check(load_library().qtt_contract_round_async(
+            self.h.ptr, self.spec.encode(), C.byref(self.va.struct), C.byref(self.vb.struct),
+            C.byref(self.vo.struct), self.rel_tol, self.max_rank, PREC[self.prec],
+            C.c_void_p(self.ranks_dev.data_ptr()), C.c_void_p(self.status_dev.data_ptr()),
+            C.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream_ptr()), "qtt_contract_round_async")
+
+    def result(self):
+        torch.cuda.synchronize()
+        st = int(self.status_dev.item())
+        if st != QTT_OK:
+            raise QttError(st, "qtt_contract_round_async")
+        ranks = [int(x) for x in self.ranks_dev.tolist()]
+        return _views_of_compact(self.out_buffers, ranks, self.d), ranks
+
+
 def contract_round_noalloc(spec: str, a, b, rel_tol: float, max_rank: int, out_buffers: List[torch.Tensor],
                            prec: str = "fp64") -> RoundResult:
     """contract_round through the allocation-free entry point.
@@ -556,6 +614,42 @@ def fit(spec: str, a, b, guess, nsweeps: int = 1, workspace: Optional[torch.Tens
                      C.byref(nrm), C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr()), "qtt_fit")
     ranks = vc.ranks()
     return _views_of_compact(bufs, ranks, d), ranks, nrm.value
+
+
+def fit2(spec: str, a, b, guess, nsweeps: int = 1, rel_tol: float = 0.0, max_rank: int = 0,
+         workspace: Optional[torch.Tensor] = None):
+    """Two-core variational fitting (qtt_fit2) of a copy of `guess` to the
+    product of a and b: the ranks adapt under rel_tol / max_rank.  Returns
+    (cores, ranks, norm, info dict with the last sweep's discarded tails)."""
+    L = load_library()
+    h = handle(a[0].device.index)
+    legs = _legs(spec)
+    va, vb = TTView(list(a), legs), TTView(list(b), 1)
+    n = len(guess)
+    d = [g.shape[1] for g in guess]
+    r_in = [guess[0].shape[0]] + [g.shape[-1] for g in guess]
+    probe = TTView([g.detach().reshape(-1) for g in guess], 1, ranks_override=r_in, phys_override=d)
+    bnd = (C.c_int64 * (n + 1))()
+    nb = C.c_size_t()
+    _check(L.qtt_fit2_query(spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(probe.struct),
+                            int(max_rank), bnd, C.byref(nb)), "qtt_fit2_query")
+    bounds = [int(bnd[k]) for k in range(n + 1)]
+    dev = a[0].device
+    bufs = []
+    for k, g in enumerate(guess):
+        buf = torch.zeros(bounds[k] * d[k] * bounds[k + 1], dtype=torch.float64, device=dev)
+        buf[: g.numel()] = g.detach().reshape(-1)
+        bufs.append(buf)
+    vc = TTView(bufs, 1, ranks_override=r_in, phys_override=d)
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = _workspace(nb.value, dev)
+    info = _Info(n)
+    _check(L.qtt_fit2(h.ptr, spec.encode(), C.byref(va.struct), C.byref(vb.struct), C.byref(vc.struct),
+                      int(nsweeps), float(rel_tol), int(max_rank), C.byref(info.c),
+                      C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr()), "qtt_fit2")
+    ranks = vc.ranks()
+    extra = {"tails": [info.tail[k] for k in range(n - 1)], "jacobi_sweeps_max": info.c.jacobi_sweeps_max}
+    return _views_of_compact(bufs, ranks, d), ranks, info.c.norm, extra
 
 
 def round_tt(cores, rel_tol: float, max_rank: int = 0, prec: str = "fp64", want_sigmas: bool = False,
@@ -662,7 +756,15 @@ class BatchPlan:
         v, g = C.c_int32(), C.c_int32()
         ms = (C.c_float * 4)()
         _check(load_library().qtt_batch_plan_info(self._plan, C.byref(v), C.byref(g), ms), "qtt_batch_plan_info")
-        return {"variant": v.value, "grid": g.value, "tuned_ms": [ms[i] for i in range(4)]}
+        tiles = (C.c_uint8 * 8)()
+        shapes = (C.c_int32 * 24)()
+        pms = (C.c_float * 32)()
+        _check(load_library().qtt_batch_plan_tiles(self._plan, tiles, shapes, pms), "qtt_batch_plan_tiles")
+        names = ["64x64", "64x32", "32x64", "32x32"]
+        gemm = {b: {"shape": [shapes[3 * b + c] for c in range(3)], "tile": names[tiles[b]],
+                    "probe_ms": [pms[4 * b + v] for v in range(4)]}
+                for b in range(8) if shapes[3 * b] > 0}
+        return {"variant": v.value, "grid": g.value, "tuned_ms": [ms[i] for i in range(4)], "gemm_tiles": gemm}
 
     def cores(self, i: int) -> List[torch.Tensor]:
         return _views_of_compact(self.out_buffers[i], self.ranks[i], self.d[i])

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libqtt.so not b
 def header_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(qtt_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(qtt_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_every_declared_symbol_is_exported():
@@ -64,6 +64,7 @@ def test_null_handle_rejected_by_compute_calls():
     assert L.qtt_contract(None, b"i,i->i", C.byref(a), C.byref(a), C.byref(a), None, 0, None) == -1
     assert L.qtt_round(None, C.byref(a), 1e-8, 0, 0, None, None, 0, None) == -1
     assert L.qtt_set_jacobi_max_sweeps(None, 5) == -1
+    assert L.qtt_inner_prec(None, C.byref(a), C.byref(a), 3, C.byref(out), None, 0, None) == -1
     assert L.qtt_contract_round_noalloc(None, b"i,i->i", C.byref(a), C.byref(a), C.byref(a), 1e-8, 0, 0,
                                         None, None) == -1
 

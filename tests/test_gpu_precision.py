@@ -76,3 +76,21 @@ def test_lap3d_bf16x3_and_fp32_reported(lap3d):
         got, err, sig = _run(lap3d, prec)
         assert got.ranks == info.ranks
         assert err <= 1e-4
+
+
+@pytest.mark.timeout(300)
+def test_inner_precision_forms_rank256():
+    """The environment sweep of the inner product in each GEMM arithmetic at
+    the rank-256 size: <X, Y> and <X, X> of two 42-core rank-256 MPS against
+    the oracle, to 1e-6 ||X|| ||Y|| for the reduced forms."""
+    w = I.laplacian3d_r256()
+    X = w.b
+    Y = I.random_mps(len(X), 256, np.random.default_rng(13))
+    nx, ny = O.norm(X), O.norm(Y)
+    ref_xy, ref_xx = O.inner(X, Y), O.inner(X, X)
+    dX, dY = Q.to_device(X, DEV), Q.to_device(Y, DEV)
+    for prec, tol in [("fp64", 1e-13), ("bf16x6", 1e-6), ("fp32", 1e-6), ("bf16x3", 1e-4)]:
+        exy = abs(Q.inner(dX, dY, prec=prec) - ref_xy) / (nx * ny)
+        exx = abs(Q.inner(dX, dX, prec=prec) - ref_xx) / (nx * nx)
+        log(f"inner {prec}: |err|/(|x||y|) {exy:.2e}, <x,x> {exx:.2e}")
+        assert exy <= tol and exx <= tol, (prec, exy, exx)
