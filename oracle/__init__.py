@@ -25,6 +25,9 @@ numpy.linalg, written from the paper's definitions:
     the derivative of <C|Y> with every other core orthonormal, and the
     multi-core strategy with super-cores of two cores, decomposed again by a
     truncated SVD so that the ranks adapt;
+  * the DMRG-like linear solver of Sec. 5 for symmetric positive definite
+    operators: the energy <x, W x> - 2 <x, b> minimised over one core or a
+    super-core of two cores at a time (local dense solves);
   * sums of many trains (the block structure of Sec. 3.1, operators
     included) and the operator product 'ij,jk->ik';
   * general digit bases (factorised dimensions, Sec. 2): every function takes

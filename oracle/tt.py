@@ -23,6 +23,7 @@ __all__ = [
     "zipup",
     "fit",
     "fit_two_core",
+    "solve_energy",
     "RoundInfo",
     "truncation_rank",
     "cut_gaps",
@@ -567,6 +568,123 @@ def fit_two_core(spec: str, A, B, C0, rel_tol: float = 0.0, max_rank: int = 0, n
     if return_info:
         return C, {"ranks": ranks, "tails": tails}
     return C
+
+
+def solve_energy(W, b, x0, nsweeps: int = 1, ncores: int = 1, rel_tol: float = 0.0, max_rank: int = 0,
+                 return_info: bool = False):
+    """Solution of W x = b for a symmetric positive definite operator W (an
+    MPO) by the DMRG-like strategy of Sec. 5: the energy
+    J(x) = <x, W x> - 2 <x, b> is minimised core by core (ncores = 1, ranks
+    fixed) or over super-cores of two cores (ncores = 2, ranks adapt).
+
+    With every core outside the current block orthonormal (left of it
+    left-orthonormal, right of it right-orthonormal), J restricted to the
+    block is the quadratic form of the local matrix
+      A_loc[(a,i,c),(a',j,c')] = sum LW[a,al,a'] W[al,i,j,be] RW[c,be,c']
+    (LW, RW the three-layer environments of <x|W|x>; for two cores W is the
+    product of the two operator cores) and the local right-hand side
+      b_loc[a,i,c] = sum Lb[a,e] b[e,i,f] Rb[c,f]
+    (the environments of <x|b>); its minimiser solves A_loc x_loc = b_loc
+    (a dense solve here).  The guess is left-orthogonalised first; a sweep
+    runs from the right end to the left and back, as the variational
+    fitting does: one-core blocks move the centre by a QR of the solved core
+    (of its transpose on the way left), two-core blocks are split by the
+    truncated SVD of the fitting (delta = rel_tol ||S||_F / sqrt(n-1), capped
+    at max_rank).  Returns the cores (and, with return_info, the ranks and
+    the energy after every local solve)."""
+    if ncores not in (1, 2):
+        raise ValueError("ncores must be 1 or 2")
+    Wm = [np.asarray(w, dtype=np.float64) for w in W]
+    Bm = [_mat(c) for c in b]
+    x, _ = orthogonalize(x0)
+    X = [_mat(c).copy() for c in x]
+    n = len(X)
+    energies = []
+    one3 = np.ones((1, 1, 1))
+    one2 = np.ones((1, 1))
+
+    def lw_next(LW, q):
+        return np.einsum("aAx,aic,AijB,xjy->cBy", LW, X[q], Wm[q], X[q], optimize=True)
+
+    def rw_prev(RW, q):
+        return np.einsum("aic,AijB,xjy,cBy->aAx", X[q], Wm[q], X[q], RW, optimize=True)
+
+    def lb_next(Lb, q):
+        return np.einsum("ae,aic,eif->cf", Lb, X[q], Bm[q], optimize=True)
+
+    def rb_prev(Rb, q):
+        return np.einsum("aic,eif,cf->ae", X[q], Bm[q], Rb, optimize=True)
+
+    def local_solve(q, LW, RW, Lb, Rb):
+        if ncores == 1:
+            A = np.einsum("aAx,AijB,cBy->aicxjy", LW, Wm[q], RW, optimize=True)
+            rhs = np.einsum("ae,eif,cf->aic", Lb, Bm[q], Rb, optimize=True)
+        else:
+            A = np.einsum("aAx,AikB,BjlC,cCy->aijcxkly", LW, Wm[q], Wm[q + 1], RW, optimize=True)
+            rhs = np.einsum("ae,eif,fjg,cg->aijc", Lb, Bm[q], Bm[q + 1], Rb, optimize=True)
+        shp = rhs.shape
+        N = rhs.size
+        sol = np.linalg.solve(A.reshape(N, N), rhs.reshape(N))
+        energies.append(-float(sol @ rhs.reshape(N)))
+        return sol.reshape(shp)
+
+    def split(S, q, left_orthonormal):
+        a, i, j, c = S.shape
+        U, sg, Vt = np.linalg.svd(S.reshape(a * i, j * c), full_matrices=False)
+        delta = rel_tol * float(np.linalg.norm(sg)) / math.sqrt(max(n - 1, 1))
+        r, _, _, _ = truncation_rank(sg, delta, max_rank)
+        if left_orthonormal:
+            X[q] = U[:, :r].reshape(a, i, r)
+            X[q + 1] = (sg[:r, None] * Vt[:r]).reshape(r, j, c)
+        else:
+            X[q] = (U[:, :r] * sg[None, :r]).reshape(a, i, r)
+            X[q + 1] = Vt[:r].reshape(r, j, c)
+
+    for _ in range(nsweeps):
+        LW, Lb = [one3], [one2]
+        for q in range(n - 1):
+            LW.append(lw_next(LW[q], q))
+            Lb.append(lb_next(Lb[q], q))
+        RW, Rb = [None] * (n + 1), [None] * (n + 1)
+        RW[n], Rb[n] = one3, one2
+        if ncores == 1 or n == 1:
+            for q in range(n - 1, -1, -1):  # right to left
+                sol = local_solve(q, LW[q], RW[q + 1], Lb[q], Rb[q + 1])
+                r0, d, r1 = sol.shape
+                if q > 0:
+                    Qm, Rr = _qr_pos(sol.reshape(r0, d * r1).T)
+                    X[q] = Qm.T.reshape(Qm.shape[1], d, r1)
+                    X[q - 1] = np.einsum("aib,bc->aic", X[q - 1], Rr.T)
+                else:
+                    X[q] = sol
+                RW[q] = rw_prev(RW[q + 1], q)
+                Rb[q] = rb_prev(Rb[q + 1], q)
+            LW, Lb = [one3], [one2]
+            for q in range(n):  # and back
+                sol = local_solve(q, LW[q], RW[q + 1], Lb[q], Rb[q + 1])
+                r0, d, r1 = sol.shape
+                if q < n - 1:
+                    Qm, Rr = _qr_pos(sol.reshape(r0 * d, r1))
+                    X[q] = Qm.reshape(r0, d, Qm.shape[1])
+                    X[q + 1] = np.einsum("ab,bic->aic", Rr, X[q + 1])
+                else:
+                    X[q] = sol
+                LW.append(lw_next(LW[q], q))
+                Lb.append(lb_next(Lb[q], q))
+        else:
+            for q in range(n - 2, -1, -1):  # pairs from the right end
+                split(local_solve(q, LW[q], RW[q + 2], Lb[q], Rb[q + 2]), q, left_orthonormal=False)
+                RW[q + 1] = rw_prev(RW[q + 2], q + 1)
+                Rb[q + 1] = rb_prev(Rb[q + 2], q + 1)
+            LW, Lb = [one3], [one2]
+            for q in range(n - 1):  # and back from the left end
+                split(local_solve(q, LW[q], RW[q + 2], Lb[q], Rb[q + 2]), q, left_orthonormal=True)
+                LW.append(lw_next(LW[q], q))
+                Lb.append(lb_next(Lb[q], q))
+    ranks = [1] + [c.shape[-1] for c in X]
+    if return_info:
+        return X, {"ranks": ranks, "energies": energies}
+    return X
 
 
 def bond_singular_values(X):

@@ -211,8 +211,11 @@ def poly_qtt(n: int, coeffs: Sequence[float], a: float = 0.0, b: float = 1.0,
 # --------------------------------------------------------------------------
 # finite-difference Laplacian as an MPO
 # --------------------------------------------------------------------------
-def laplacian_mpo(m: int, D: int = 1):
-    """Unscaled Dirichlet Laplacian sum_a (2 I - S_a - S_a^T) on a (2^m)^D grid.
+def laplacian_mpo(m: int, D: int = 1, diag: float = 2.0):
+    """Unscaled Dirichlet Laplacian sum_a (2 I - S_a - S_a^T) on a (2^m)^D grid
+    (with diag != 2: sum_a (diag I - S_a - S_a^T), the Laplacian shifted by
+    D (diag - 2) I, e.g. the operator of an implicit heat step scaled by the
+    inverse time step).
 
     S is the shift Q^N_1 of Sec. 4.2 (S(i, j) = 1 iff i - j = 1), values
     outside the grid are zero (no wrap-around).  Cores are interleaved: core
@@ -271,7 +274,7 @@ def laplacian_mpo(m: int, D: int = 1):
             elif sr == ("N",):
                 put(("N",), sr, I2)  # still not started (if other axes remain)
                 if k == lsb_core(alpha):
-                    put(("A",), sr, 2.0 * I2 - E10 - E01)
+                    put(("A",), sr, diag * I2 - E10 - E01)
                     put(("Q", alpha), sr, -E01)
                     put(("P", alpha), sr, -E10)
             else:
