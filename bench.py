@@ -179,7 +179,15 @@ def main():
                          "laplacian3d_n42_r256_zipup: the same product by the decomposition (zip-up) algorithm")
     ap.add_argument("--ncores", type=int, default=2, choices=[1, 2],
                     help="zip-up super-core size (exact product cores per split)")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_k_jacobi.json from the counter CSVs of two rocprofv3 --pmc passes "
+                         "(FETCH_SIZE, WRITE_SIZE) over this workload's step run with --calib-copy-mb; no GPU work")
+    ap.add_argument("--traffic-command", action="append", default=[],
+                    help="with --traffic-record: the profiling commands, stored in the record")
     args = ap.parse_args()
+    if args.traffic_record:
+        return traffic_record("k_jacobi", args.workload, args.traffic_record[0], args.traffic_record[1],
+                              args.calib_copy_mb, args.traffic_command)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the single-chain rounding "
               f"sweep carries a core-to-core dependency and is not sharded across GPUs", file=sys.stderr)
@@ -345,9 +353,10 @@ def bench_batch(args, I, Q, torch, dev):
         "metric": "QTT batched contract+round TFLOP/s (512 uneven 1D Hadamard products, L=24, one graph launch)",
         "value": total / sec / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
+        "dtype": "bf16x6+f64", "data": "synthetic",
         "config": {"workload": w.name, "problems": len(w.a), "cores": 24, "rank_a": "U{8..128}", "rank_b": 2,
-                   "rel_tol": w.rel_tol, "gemm": "fp32", "factorisations": "fp64"},
+                   "rel_tol": w.rel_tol, "gemm": "bf16x6 split, FP32 accumulation per 32-deep step",
+                   "factorisations": "fp64"},
         "algorithmic_gflop_per_step": total / 1e9,
         "plan": plan.info(),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6,
@@ -589,7 +598,7 @@ def add_roofline(out, kernels, sec):
     out["roofline"] = {
         "bound": k["bound"], "achieved": k["achieved"] * scale, "peak": k["peak"] * scale,
         "unit": "TFLOP/s" if k["unit"] == "GFLOP/s" else "GB/s", "frac": k["frac"],
-        "traffic": measured_traffic(k["kernel"], k["alg_bytes_per_launch"]),
+        "traffic": measured_traffic(k["kernel"], out["config"]["workload"]),
         "kernel": k["kernel"], "launches": k["launches"], "avg_us": k["avg_us"],
         "share_of_step": k["ms_per_step"] / (sec * 1e3),
         "alg_bytes_per_launch": k["alg_bytes_per_launch"], "alg_flop_per_launch": k["alg_flop_per_launch"],
@@ -598,27 +607,82 @@ def add_roofline(out, kernels, sec):
                                                    "unit", "frac")} for c, v in kernels.items()}
 
 
-def measured_traffic(kernel, alg_bytes_per_launch):
-    """HBM bytes per launch from the committed hardware-counter summary of this
-    kernel (FETCH_SIZE + WRITE_SIZE of one launch, each scaled by the counter's
-    reading for a plain copy of known size), applied as the measured/algorithmic
-    ratio to this run's algorithmic bytes per launch; None unless the summary was
-    taken on the current source of the kernel."""
+TRAFFIC_SOURCES = {"k_jacobi": ["paper_2602_20226_amd/csrc/svd.hip", "paper_2602_20226_amd/csrc/qtt_device.hpp"]}
+
+
+def _sources_sha(names):
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel.split('+')[0]}.json")
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """Measured HBM bytes per launch of `kernel` on `workload`: the committed
+    hardware-counter record (FETCH_SIZE + WRITE_SIZE of every launch of the
+    kernel in one bench.py step, each scaled by the counter's reading for a
+    plain copy of known size, averaged over the launches); None unless the
+    record was taken on this workload and on the current source of the kernel."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
     try:
         with open(path) as f:
             rec = json.load(f)
-        h = hashlib.sha256()
-        for name in rec.get("sources", []):
-            with open(os.path.join(ROOT, name), "rb") as f:
-                h.update(f.read())
-        sha = h.hexdigest()
+        sha = _sources_sha(rec.get("sources", []))
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != sha or not rec.get("ratio"):
+    if rec.get("source_sha256") != sha or rec.get("workload") != workload:
         return None
-    return rec["ratio"] * alg_bytes_per_launch
+    return rec.get("measured_bytes_per_launch")
+
+
+def traffic_record(kernel, workload, fetch_csv, write_csv, copy_mib, commands, path=None):
+    """Builds profiles/traffic_<kernel>.json from the counter CSVs of two
+    rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) over
+    one bench.py step of `workload` that ends with a plain copy of copy_mib
+    MiB (--calib-copy-mb): the copy's readings give the scale factors."""
+    import csv
+
+    def read(path, counter):
+        per = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = (int(row["Dispatch_Id"]), row["Kernel_Name"])
+                per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+        return per
+
+    fetch, write = read(fetch_csv, "FETCH_SIZE"), read(write_csv, "WRITE_SIZE")
+    expect_kib = copy_mib * 1024.0
+
+    def split(per):
+        kern = [v for (i, n), v in sorted(per.items()) if kernel in n]
+        copy = [v for (i, n), v in sorted(per.items()) if kernel not in n and v > 0.25 * expect_kib]
+        return kern, copy
+
+    kf, cf = split(fetch)
+    kw, cw = split(write)
+    if not kf or len(kf) != len(kw) or not cf or not cw:
+        raise SystemExit(f"counter files do not hold matching {kernel} launches and a copy of {copy_mib} MiB")
+    ff, fw = expect_kib / cf[-1], expect_kib / cw[-1]
+    fetch_b = sum(kf) / len(kf) * ff * 1024.0
+    write_b = sum(kw) / len(kw) * fw * 1024.0
+    rec = {
+        "kernel": kernel, "workload": workload, "sources": TRAFFIC_SOURCES[kernel],
+        "source_sha256": _sources_sha(TRAFFIC_SOURCES[kernel]), "launches": len(kf),
+        "fetch_kib_per_launch": sum(kf) / len(kf), "write_kib_per_launch": sum(kw) / len(kw),
+        "calibration": {"kernel": f"plain elementwise copy of {copy_mib} MiB", "fetch_kib": cf[-1],
+                        "write_kib": cw[-1], "fetch_factor": ff, "write_factor": fw},
+        "measured_bytes_per_launch": fetch_b + write_b,
+        "commands": commands,
+    }
+    path = path or os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec))
 
 
 def _blas_threads():

@@ -18,20 +18,42 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr
 
 
-def test_traffic_record_matches_the_current_kernel_sources():
-    """The committed byte-counter record is only applied while the Jacobi
-    sources hash to the recorded value; its measured/algorithmic ratio must
-    describe a kernel that moves its algorithmic bytes once."""
-    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_k_jacobi.json")))
-    got = bench.measured_traffic("k_jacobi", 1.0)
+def _counter_csv(path, counter, rows):
+    with open(path, "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for did, name, v in rows:
+            f.write(f'{did},"{name}",{counter},{v}\n')
+
+
+def test_traffic_record_from_counter_files(tmp_path):
+    """The byte-counter record: per-launch averages of the kernel's FETCH_SIZE
+    and WRITE_SIZE (KiB), each scaled by what the counter reads for the plain
+    copy of known size, and applied only for the same workload and kernel
+    sources."""
+    k = "void qtt::(anonymous namespace)::k_jacobi<8>(double*, int)"
+    cp = "at::elementwise_kernel<mul>"
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE", [(1, k, 100.0), (2, k, 300.0), (3, cp, 131072.0)])
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", [(1, k, 50.0), (2, k, 150.0), (3, cp, 262144.0)])
+    out = tmp_path / "rec.json"
+    bench.traffic_record("k_jacobi", "wl", str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 256, ["cmd"], str(out))
+    rec = json.load(open(out))
+    assert rec["launches"] == 2
+    assert rec["calibration"]["fetch_factor"] == 2.0 and rec["calibration"]["write_factor"] == 1.0
+    # (200 KiB * 2 + 100 KiB * 1) per launch
+    assert abs(rec["measured_bytes_per_launch"] - 500.0 * 1024) < 1e-9
+    assert rec["source_sha256"] == bench._sources_sha(bench.TRAFFIC_SOURCES["k_jacobi"])
+
+
+def test_committed_traffic_record_applies_only_to_its_workload_and_sources():
+    path = os.path.join(ROOT, "profiles", "traffic_k_jacobi.json")
+    if not os.path.exists(path):
+        pytest.skip("no byte-counter record committed")
+    rec = json.load(open(path))
+    assert bench.measured_traffic("k_jacobi", rec["workload"] + "_other") is None
+    got = bench.measured_traffic("k_jacobi", rec["workload"])
     if got is None:
         pytest.skip("the record was taken on other kernel sources: bench.py reports traffic null until re-measured")
-    assert abs(got - rec["ratio"]) < 1e-12
-    assert 0.95 < rec["ratio"] < 1.2
-    # the ratio is the counters (scaled by the copy calibration) over the algorithmic bytes
-    meas = rec["fetch_kib"] * 1024 * rec["calibration"]["fetch_factor"] + \
-        rec["write_kib"] * 1024 * rec["calibration"]["write_factor"]
-    assert abs(meas / rec["algorithmic_bytes"] - rec["ratio"]) < 1e-9
+    assert got == rec["measured_bytes_per_launch"]
 
 
 def test_flop_model_reduces_to_textbook_counts():
