@@ -251,6 +251,30 @@ int qtt_fit_workspace_size(const char *spec, const qtt_tt *a, const qtt_tt *b, c
  * written.  Synchronous. */
 int qtt_fit2(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, qtt_tt *c, int32_t nsweeps,
              double rel_tol, int64_t max_rank, qtt_round_info *info, void *ws, size_t ws_bytes, void *stream);
+/* Linear system W x = b for a symmetric positive definite operator W (FP64
+ * MPO with equal input and output sizes; b and the guess x FP64 MPS): the
+ * DMRG-like solver of Sec. 5, which minimises the energy
+ * J(x) = <x, W x> - 2 <x, b> over one core at a time (ncores = 1, ranks of
+ * the guess kept) or over super-cores of two adjacent cores (ncores = 2,
+ * the super-core split again by the truncated SVD of qtt_fit2: rel_tol,
+ * max_rank, so the ranks adapt).  With the cores outside the block
+ * orthonormal the block's minimiser solves the local system
+ * A_loc x = b_loc (A_loc from the three-layer environments of <x|W|x>,
+ * b_loc from those of <x|b>), solved by Householder QR and a triangular
+ * solve (FP64).  The guess is orthogonalised from the left first; each of
+ * nsweeps sweeps runs from the right end to the left and back.  x's cores
+ * are caller-owned with the capacity of qtt_solve_query's bounds (for
+ * ncores = 2 a max_rank keeps them small); x->ranks is rewritten.  Limits:
+ * local systems of at most 4096 unknowns (rank^2 d^ncores), split rows of
+ * at most 1024.  info (nullable): norm = ||x||, jacobi_sweeps_max.
+ * Synchronous. */
+int qtt_solve(qtt_handle h, const qtt_tt *w, const qtt_tt *b, qtt_tt *x, int32_t nsweeps, int32_t ncores,
+              double rel_tol, int64_t max_rank, qtt_round_info *info, void *ws, size_t ws_bytes, void *stream);
+/* Rank capacity (bounds, n+1, nullable) and workspace (bytes) of qtt_solve;
+ * pure shape arithmetic. */
+int qtt_solve_query(const qtt_tt *w, const qtt_tt *b, const qtt_tt *x, int32_t ncores, int64_t max_rank,
+                    int64_t *bounds, size_t *bytes);
+
 /* Rank capacity per bond of qtt_fit2's result (bounds, n+1 entries, nullable:
  * the guess's rank or the largest rank a split can give, whichever is
  * larger) and its device workspace (bytes); pure shape arithmetic. */

@@ -1480,19 +1480,44 @@ int make_fit2_plan(const Shape& s, const qtt_tt* c, long max_rank, Fit2Plan& F) 
 // Truncated SVD of M (p0 x L, row-major; overwritten by its Householder QR
 // when tall): vt (rn x L, ld L) the kept right singular vectors as rows,
 // mv (p0 x rn, ld rn) = M V_r = U_r Sigma_r.  Reads the decision back.
-int split_rows(qtt_context* h, hipStream_t st, double* ws, const Fit2Plan& F, double* M, int p0, int L,
-               double rel_tol, int nb, long max_rank, double* vt, double* mv, int& rn, double& tail, int& swp) {
-  double* TB = ws + F.offTB;
-  double* X = ws + F.offX;
-  double* Xc = ws + F.offXc;
-  double* Yt = ws + F.offYt;
-  double* sig = ws + F.offSig;
-  int* perm = (int*)(ws + F.offPerm);
-  TruncOut* tr = (TruncOut*)(ws + F.offTrunc);
-  unsigned* ctr = (unsigned*)(ws + F.offCtr);
-  int* sweeps = (int*)(ws + F.offSweeps);
-  double* nrm = ws + F.offNrm;
-  double* scr = ws + F.offScr;
+// Device buffers of a truncated split (see split_rows).
+struct SplitBufs {
+  double *TB, *X, *Xc, *Yt, *sig, *nrm, *scr;
+  int* perm;
+  TruncOut* tr;
+  unsigned* ctr;
+  int* sweeps;
+};
+
+SplitBufs fit2_bufs(double* ws, const Fit2Plan& F) {
+  SplitBufs b;
+  b.TB = ws + F.offTB;
+  b.X = ws + F.offX;
+  b.Xc = ws + F.offXc;
+  b.Yt = ws + F.offYt;
+  b.sig = ws + F.offSig;
+  b.perm = (int*)(ws + F.offPerm);
+  b.tr = (TruncOut*)(ws + F.offTrunc);
+  b.ctr = (unsigned*)(ws + F.offCtr);
+  b.sweeps = (int*)(ws + F.offSweeps);
+  b.nrm = ws + F.offNrm;
+  b.scr = ws + F.offScr;
+  return b;
+}
+
+int split_rows(qtt_context* h, hipStream_t st, const SplitBufs& bf, double* M, int p0, int L, double rel_tol, int nb,
+               long max_rank, double* vt, double* mv, int& rn, double& tail, int& swp) {
+  double* TB = bf.TB;
+  double* X = bf.X;
+  double* Xc = bf.Xc;
+  double* Yt = bf.Yt;
+  double* sig = bf.sig;
+  int* perm = bf.perm;
+  TruncOut* tr = bf.tr;
+  unsigned* ctr = bf.ctr;
+  int* sweeps = bf.sweeps;
+  double* nrm = bf.nrm;
+  double* scr = bf.scr;
   const bool tall = p0 >= L;
   const int p = tall ? L : p0;
   if (tall) {
@@ -1564,7 +1589,8 @@ int fit2_sweeps(qtt_context* h, hipStream_t st, double* ws, const Shape& s, cons
       QTT_HIP(fit2_supercore(st, ws, s, F, rc, q, S));
       int rn = 0, swp = 0;
       double tail = 0.0;
-      int e = split_rows(h, st, ws, F, S, (int)m, (int)cols, rel_tol, n - 1, max_rank, V, MV, rn, tail, swp);
+      int e = split_rows(h, st, fit2_bufs(ws, F), S, (int)m, (int)cols, rel_tol, n - 1, max_rank, V, MV, rn, tail,
+                         swp);
       if (e) return e;
       if (rn > F.bnd[q + 1]) return QTT_ERR_UNSUPPORTED;
       maxsw = std::max(maxsw, swp);
@@ -1583,7 +1609,8 @@ int fit2_sweeps(qtt_context* h, hipStream_t st, double* ws, const Shape& s, cons
       QTT_HIP(transpose(st, S, (int)m, (int)cols, cols, St, m));
       int rn = 0, swp = 0;
       double tail = 0.0;
-      int e = split_rows(h, st, ws, F, St, (int)cols, (int)m, rel_tol, n - 1, max_rank, V, MV, rn, tail, swp);
+      int e = split_rows(h, st, fit2_bufs(ws, F), St, (int)cols, (int)m, rel_tol, n - 1, max_rank, V, MV, rn, tail,
+                         swp);
       if (e) return e;
       if (rn > F.bnd[q + 1]) return QTT_ERR_UNSUPPORTED;
       maxsw = std::max(maxsw, swp);
@@ -1616,6 +1643,327 @@ int fit2_setup(const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt*
   if ((st = make_plan(sc, 0, P, false))) return st;
   orth_bytes = ws_bytes_of(P);
   return make_fit2_plan(s, c, max_rank, F);
+}
+
+// ---------------------------------------------------------------- linear solver
+// Sec. 5, DMRG-like strategy for W x = b with W symmetric positive definite:
+// the energy J(x) = <x, W x> - 2 <x, b> is minimised over one core (ranks
+// fixed) or a super-core of two cores (ranks adapt through the truncated
+// split of the fitting).  With the cores outside the block orthonormal the
+// block's minimiser solves A_loc x = b_loc, A_loc the block's local matrix
+// (three-layer environments of <x|W|x> and the block's operator cores),
+// b_loc = Lb b_block Rb^T; the local system is solved by Householder QR
+// (backward stable) and an upper-triangular solve.
+struct SolvePlan {
+  int nc = 1;
+  std::vector<long> bnd, rw, rb;
+  std::vector<long> offLW, offRW, offLb, offRb;
+  long offA = 0, offRhs = 0, offT = 0, offE1 = 0, offE2 = 0, offG = 0, offBp = 0, offGt = 0, offTq = 0, offQe = 0;
+  long offS = 0, offSt = 0, offV = 0, offMV = 0, offLTB = 0, offLScr = 0;
+  long offTB = 0, offX = 0, offXc = 0, offYt = 0, offSig = 0, offPerm = 0, offTrunc = 0, offCtr = 0, offSweeps = 0,
+       offNrm = 0, offScr = 0;
+  long total = 0;
+};
+
+SplitBufs solve_bufs(double* ws, const SolvePlan& F) {
+  SplitBufs b;
+  b.TB = ws + F.offTB;
+  b.X = ws + F.offX;
+  b.Xc = ws + F.offXc;
+  b.Yt = ws + F.offYt;
+  b.sig = ws + F.offSig;
+  b.perm = (int*)(ws + F.offPerm);
+  b.tr = (TruncOut*)(ws + F.offTrunc);
+  b.ctr = (unsigned*)(ws + F.offCtr);
+  b.sweeps = (int*)(ws + F.offSweeps);
+  b.nrm = ws + F.offNrm;
+  b.scr = ws + F.offScr;
+  return b;
+}
+
+int solve_check(const qtt_tt* w, const qtt_tt* b, const qtt_tt* x) {
+  int st;
+  if ((st = check_tt(w, 2)) || (st = check_tt(b, 1)) || (st = check_tt(x, 1))) return st;
+  if (w->dtype != QTT_F64 || b->dtype != QTT_F64 || x->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  if (w->n != b->n || x->n != b->n) return QTT_ERR_SHAPE;
+  for (int k = 0; k < w->n; ++k)
+    if (dphys(w, k) != dphys_in(w, k) || dphys(b, k) != dphys(w, k) || dphys(x, k) != dphys(w, k))
+      return QTT_ERR_SHAPE;
+  return QTT_OK;
+}
+
+int make_solve_plan(const qtt_tt* w, const qtt_tt* b, const qtt_tt* x, int ncores, long max_rank, SolvePlan& F) {
+  const int n = x->n;
+  F.nc = ncores;
+  F.bnd.assign(n + 1, 1);
+  F.rw.assign(n + 1, 1);
+  F.rb.assign(n + 1, 1);
+  std::vector<long> left(n + 1, 1), right(n + 1, 1);
+  std::vector<int> d(n);
+  for (int k = 0; k < n; ++k) d[k] = dphys(x, k);
+  for (int k = 1; k <= n; ++k) left[k] = std::min<long>(left[k - 1] * d[k - 1], 1L << 40);
+  for (int k = n - 1; k >= 0; --k) right[k] = std::min<long>(right[k + 1] * d[k], 1L << 40);
+  for (int k = 0; k <= n; ++k) {
+    F.rw[k] = w->ranks[k];
+    F.rb[k] = b->ranks[k];
+    // after the left orthogonalisation of the guess its ranks are at most min(left, guess)
+    long v = std::min<long>(left[k], x->ranks[k]);
+    if (ncores == 2 && k > 0 && k < n) {
+      long grow = std::min(left[k], right[k]);
+      if (max_rank > 0) grow = std::min(grow, max_rank);
+      v = std::max(v, grow);
+    }
+    F.bnd[k] = std::max(v, 1L);
+  }
+  long off = 0;
+  auto take = [&](long cnt) {
+    long o = off;
+    off += round_up(std::max(cnt, 1L), 32);
+    return o;
+  };
+  F.offLW.assign(n + 1, 0);
+  F.offRW.assign(n + 1, 0);
+  F.offLb.assign(n + 1, 0);
+  F.offRb.assign(n + 1, 0);
+  for (int k = 0; k <= n; ++k) {
+    F.offLW[k] = take(F.bnd[k] * F.rw[k] * F.bnd[k]);
+    F.offRW[k] = take(F.bnd[k] * F.rw[k] * F.bnd[k]);
+    F.offLb[k] = take(F.bnd[k] * F.rb[k]);
+    F.offRb[k] = take(F.bnd[k] * F.rb[k]);
+  }
+  long maxN = 1, maxT = 1, maxE = 1, maxG = 1, maxBp = 1, maxGt = 1, maxTq = 1, maxQe = 1, maxSplit = 1;
+  long maxTB = 1, maxX = 1, maxP = 1, maxc = 1;
+  for (int k = 0; k < n; ++k) {
+    const long r0 = F.bnd[k], r1 = F.bnd[k + 1], w0 = F.rw[k], w1 = F.rw[k + 1];
+    maxE = std::max({maxE, r0 * w0 * d[k] * r1, r0 * d[k] * w1 * r1, d[k] * r1 * w0 * r0});
+    if (ncores == 1) {
+      const long N = r0 * d[k] * r1;
+      maxN = std::max(maxN, N);
+      maxT = std::max(maxT, r0 * d[k] * F.rb[k + 1]);
+      // QR moves: the solved core (r0 d) x r1 or its transpose (d r1) x r0
+      const long m1 = d[k] * r1, m2 = r0 * d[k];
+      if (m1 > kMaxRows || m2 > kMaxRows) return QTT_ERR_UNSUPPORTED;
+      maxGt = std::max(maxGt, m1 * r0);
+      maxTq = std::max({maxTq, qr_t_doubles((int)m1, (int)r0), qr_t_doubles((int)m2, (int)r1)});
+      maxQe = std::max({maxQe, m1 * std::min(m1, r0), m2 * std::min(m2, r1)});
+      maxc = std::max({maxc, r0, r1});
+    } else if (k + 1 < n) {
+      const long r2 = F.bnd[k + 2], P = (long)d[k] * d[k + 1];
+      const long N = r0 * P * r2;
+      maxN = std::max(maxN, N);
+      maxT = std::max(maxT, r0 * P * F.rb[k + 2]);
+      maxG = std::max(maxG, w0 * P * P * F.rw[k + 2]);
+      maxBp = std::max(maxBp, F.rb[k] * P * F.rb[k + 2]);
+      const long m = r0 * d[k], cols = (long)d[k + 1] * r2;
+      maxSplit = std::max(maxSplit, m * cols);
+      for (int o = 0; o < 2; ++o) {
+        const long p0 = o ? cols : m, L = o ? m : cols;
+        if (L > 1024 || p0 > kMaxRows) return QTT_ERR_UNSUPPORTED;
+        const long p = std::min(p0, L);
+        maxTB = std::max(maxTB, qr_t_doubles((int)p0, (int)p));
+        maxX = std::max(maxX, p * L);
+        maxP = std::max(maxP, p);
+        maxc = std::max({maxc, L, p0});
+      }
+    }
+  }
+  if (maxN > kMaxRows) return QTT_ERR_UNSUPPORTED;  // the local QR solve
+  F.offA = take(maxN * maxN);
+  F.offRhs = take(maxN);
+  F.offT = take(maxT);
+  F.offE1 = take(maxE);
+  F.offE2 = take(maxE);
+  F.offG = take(maxG);
+  F.offBp = take(maxBp);
+  F.offGt = take(maxGt);
+  F.offTq = take(maxTq);
+  F.offQe = take(maxQe);
+  F.offS = take(maxSplit);
+  F.offSt = take(maxSplit);
+  F.offV = take(maxX);
+  F.offMV = take(maxSplit);
+  F.offLTB = take(qr_t_doubles((int)maxN, (int)maxN));
+  F.offLScr = take(qr_scratch_doubles(maxN));
+  F.offTB = take(maxTB);
+  F.offX = take(maxX);
+  F.offXc = take(maxX);
+  F.offYt = take(maxX);
+  F.offSig = take(maxP);
+  F.offPerm = take(maxP / 2 + 1);
+  F.offTrunc = take(8);
+  F.offCtr = take(96);
+  F.offSweeps = take(1);
+  F.offNrm = take(1);
+  F.offScr = take(qr_scratch_doubles(maxc));
+  F.total = off;
+  return QTT_OK;
+}
+
+// LW' = sum x^T LW W x (three-layer step to the right of core x: r0 -> r1)
+hipError_t env3_left(hipStream_t st, const double* LW, const double* x, const double* W, long r0, long d, long r1,
+                     long w0, long w1, double* T1, double* T2, double* out) {
+  hipError_t e = gemm_f64(st, false, false, (int)(r0 * w0), (int)(d * r1), (int)r0, 1.0, LW, r0, 0, x, d * r1, 0,
+                          0.0, T1, d * r1, 0, 1);
+  if (e != hipSuccess) return e;
+  if ((e = env3_left_mid(st, T1, W, (int)r0, (int)w0, (int)d, (int)w1, (int)r1, T2)) != hipSuccess) return e;
+  return gemm_f64(st, true, false, (int)r1, (int)(w1 * r1), (int)(r0 * d), 1.0, x, r1, 0, T2, w1 * r1, 0, 0.0, out,
+                  w1 * r1, 0, 1);
+}
+
+// RW = sum x W x RW' (three-layer step to the left of core x: r1 -> r0)
+hipError_t env3_right(hipStream_t st, const double* RW, const double* x, const double* W, long r0, long d, long r1,
+                      long w0, long w1, double* U1, double* U2, double* out) {
+  hipError_t e = gemm_f64(st, false, true, (int)(r0 * d), (int)(r1 * w1), (int)r1, 1.0, x, r1, 0, RW, r1, 0, 0.0, U1,
+                          r1 * w1, 0, 1);
+  if (e != hipSuccess) return e;
+  if ((e = env3_right_mid(st, U1, W, (int)r0, (int)w0, (int)d, (int)w1, (int)r1, U2)) != hipSuccess) return e;
+  return gemm_f64(st, false, false, (int)r0, (int)(w0 * r0), (int)(d * r1), 1.0, x, d * r1, 0, U2, w0 * r0, 0, 0.0,
+                  out, w0 * r0, 0, 1);
+}
+
+// Local solve over the block starting at core q (ncores 1 or 2): writes the
+// block's minimiser into F.offRhs (layout [r0][P][r_end]).
+int solve_local(hipStream_t st, double* ws, const SolvePlan& F, const qtt_tt* w, const qtt_tt* b,
+                const std::vector<long>& rc, const std::vector<int>& d, int q) {
+  const int nc = F.nc;
+  const long r0 = rc[q], r1 = rc[q + nc];
+  const long w0 = F.rw[q], w1 = F.rw[q + nc];
+  const long P = nc == 1 ? d[q] : (long)d[q] * d[q + 1];
+  const long N = r0 * P * r1;
+  double* A = ws + F.offA;
+  double* rhs = ws + F.offRhs;
+  const double* Wl = (const double*)w->cores[q];
+  const double* bl = (const double*)b->cores[q];
+  long rbl0 = F.rb[q], rbl1 = F.rb[q + nc];
+  if (nc == 2) {
+    QTT_HIP(mpo_pair(st, (const double*)w->cores[q], (const double*)w->cores[q + 1], (int)w0, d[q], (int)F.rw[q + 1],
+                     d[q + 1], (int)w1, ws + F.offG));
+    Wl = ws + F.offG;
+    const long rbm = F.rb[q + 1];
+    QTT_HIP(gemm_f64(st, false, false, (int)(rbl0 * d[q]), (int)(d[q + 1] * rbl1), (int)rbm, 1.0,
+                     (const double*)b->cores[q], rbm, 0, (const double*)b->cores[q + 1], d[q + 1] * rbl1, 0, 0.0,
+                     ws + F.offBp, d[q + 1] * rbl1, 0, 1));
+    bl = ws + F.offBp;
+  }
+  QTT_HIP(local_matrix(st, ws + F.offLW[q], Wl, ws + F.offRW[q + nc], (int)r0, (int)P, (int)r1, (int)w0, (int)w1, A));
+  QTT_HIP(fit_project(st, ws + F.offLb[q], bl, ws + F.offRb[q + nc], r0, r1, rbl0, rbl1, P, ws + F.offT, rhs));
+  QTT_HIP(householder_qr(st, A, (int)N, (int)N, N, ws + F.offLTB, ws + F.offLScr));
+  QTT_HIP(apply_q(st, A, (int)N, (int)N, N, ws + F.offLTB, rhs, 1, 1, true, ws + F.offLScr));
+  QTT_HIP(trsv_upper(st, A, (int)N, N, rhs));
+  return QTT_OK;
+}
+
+int solve_sweeps(qtt_context* h, hipStream_t st, double* ws, const SolvePlan& F, const qtt_tt* w, const qtt_tt* b,
+                 qtt_tt* x, std::vector<long>& rc, int nsweeps, double rel_tol, long max_rank, int& maxsw) {
+  const int n = x->n;
+  std::vector<int> d(n);
+  for (int k = 0; k < n; ++k) d[k] = dphys(x, k);
+  auto core = [&](int k) { return (double*)x->cores[k]; };
+  auto W = [&](int k) { return (const double*)w->cores[k]; };
+  auto B = [&](int k) { return (const double*)b->cores[k]; };
+  double* E1 = ws + F.offE1;
+  double* E2 = ws + F.offE2;
+  double* T = ws + F.offT;
+  double* sol = ws + F.offRhs;
+  auto lw_step = [&](int k) -> int {
+    QTT_HIP(env3_left(st, ws + F.offLW[k], core(k), W(k), rc[k], d[k], rc[k + 1], F.rw[k], F.rw[k + 1], E1, E2,
+                      ws + F.offLW[k + 1]));
+    QTT_HIP(env_step_left<double>(st, ws + F.offLb[k], core(k), B(k), rc[k], rc[k + 1], F.rb[k], F.rb[k + 1], d[k],
+                                  T, ws + F.offLb[k + 1]));
+    return QTT_OK;
+  };
+  auto rw_step = [&](int k) -> int {
+    QTT_HIP(env3_right(st, ws + F.offRW[k + 1], core(k), W(k), rc[k], d[k], rc[k + 1], F.rw[k], F.rw[k + 1], E1, E2,
+                       ws + F.offRW[k]));
+    QTT_HIP(env_step_right<double>(st, ws + F.offRb[k + 1], core(k), B(k), rc[k], rc[k + 1], F.rb[k], F.rb[k + 1],
+                                   d[k], T, ws + F.offRb[k]));
+    return QTT_OK;
+  };
+  QTT_HIP(fill_f64(st, ws + F.offLW[0], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + F.offLb[0], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + F.offRW[n], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + F.offRb[n], 1.0, 1));
+  int e;
+  for (int k = 0; k + F.nc < n; ++k)
+    if ((e = lw_step(k))) return e;
+  maxsw = 0;
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    if (F.nc == 1) {
+      // right to left: solve, then the solved core's transpose QR gives a right-orthonormal core
+      for (int q = n - 1; q >= 0; --q) {
+        if ((e = solve_local(st, ws, F, w, b, rc, d, q))) return e;
+        if (q > 0) {
+          const int m = (int)(d[q] * rc[q + 1]), nn = (int)rc[q], qq = std::min(m, nn);
+          double* G = ws + F.offGt;
+          double* Qe = ws + F.offQe;
+          QTT_HIP(transpose(st, sol, nn, m, m, G, nn));
+          QTT_HIP(householder_qr(st, G, m, nn, nn, ws + F.offTq, ws + F.offScr));
+          QTT_HIP(set_eye_rect(st, Qe, m, qq));
+          QTT_HIP(apply_q(st, G, m, qq, nn, ws + F.offTq, Qe, qq, qq, false, ws + F.offScr));
+          QTT_HIP(transpose(st, Qe, m, qq, qq, core(q), m));
+          rc[q] = qq;
+          if ((e = rw_step(q))) return e;
+        } else {
+          QTT_HIP(copy_pad_rows(st, sol, (int)(d[0] * rc[1]), 1, 1, core(0), (int)(d[0] * rc[1]), 1));
+          if ((e = rw_step(0))) return e;
+        }
+      }
+      // left to right: solve, then a QR of the solved core gives a left-orthonormal core
+      for (int q = 0; q < n; ++q) {
+        if ((e = solve_local(st, ws, F, w, b, rc, d, q))) return e;
+        if (q < n - 1) {
+          const int m = (int)(rc[q] * d[q]), nn = (int)rc[q + 1], qq = std::min(m, nn);
+          double* Qe = ws + F.offQe;
+          QTT_HIP(householder_qr(st, sol, m, nn, nn, ws + F.offTq, ws + F.offScr));
+          QTT_HIP(set_eye_rect(st, Qe, m, qq));
+          QTT_HIP(apply_q(st, sol, m, qq, nn, ws + F.offTq, Qe, qq, qq, false, ws + F.offScr));
+          QTT_HIP(copy_pad_rows(st, Qe, m, qq, qq, core(q), m, qq));
+          rc[q + 1] = qq;
+          if ((e = lw_step(q))) return e;
+        } else {
+          QTT_HIP(copy_pad_rows(st, sol, (int)(rc[q] * d[q]), 1, 1, core(q), (int)(rc[q] * d[q]), 1));
+        }
+      }
+    } else {
+      double* S = ws + F.offS;
+      double* St = ws + F.offSt;
+      double* V = ws + F.offV;
+      double* MV = ws + F.offMV;
+      const SplitBufs bf = solve_bufs(ws, F);
+      for (int q = n - 2; q >= 0; --q) {  // pairs from the right end: core q+1 <- V^T, core q <- U Sigma
+        if ((e = solve_local(st, ws, F, w, b, rc, d, q))) return e;
+        const long m = rc[q] * d[q], cols = (long)d[q + 1] * rc[q + 2];
+        QTT_HIP(copy_pad_rows(st, sol, (int)m, (int)cols, cols, S, (int)m, cols));
+        int rn = 0, swp = 0;
+        double tail = 0.0;
+        if ((e = split_rows(h, st, bf, S, (int)m, (int)cols, rel_tol, n - 1, max_rank, V, MV, rn, tail, swp)))
+          return e;
+        if (rn > F.bnd[q + 1]) return QTT_ERR_UNSUPPORTED;
+        maxsw = std::max(maxsw, swp);
+        QTT_HIP(copy_pad_rows(st, V, rn, (int)cols, cols, core(q + 1), rn, cols));
+        QTT_HIP(copy_pad_rows(st, MV, (int)m, rn, rn, core(q), (int)m, rn));
+        rc[q + 1] = rn;
+        if ((e = rw_step(q + 1))) return e;
+      }
+      for (int q = 0; q + 1 < n; ++q) {  // and back: core q <- U, core q+1 <- Sigma V^T
+        if ((e = solve_local(st, ws, F, w, b, rc, d, q))) return e;
+        const long m = rc[q] * d[q], cols = (long)d[q + 1] * rc[q + 2];
+        QTT_HIP(transpose(st, sol, (int)m, (int)cols, cols, St, m));
+        int rn = 0, swp = 0;
+        double tail = 0.0;
+        if ((e = split_rows(h, st, bf, St, (int)cols, (int)m, rel_tol, n - 1, max_rank, V, MV, rn, tail, swp)))
+          return e;
+        if (rn > F.bnd[q + 1]) return QTT_ERR_UNSUPPORTED;
+        maxsw = std::max(maxsw, swp);
+        QTT_HIP(transpose(st, V, rn, (int)m, m, core(q), rn));
+        QTT_HIP(transpose(st, MV, (int)cols, rn, rn, core(q + 1), cols));
+        rc[q + 1] = rn;
+        if ((e = lw_step(q))) return e;
+      }
+    }
+  }
+  QTT_HIP(frob_norm(st, core(n - 1), rc[n - 1] * d[n - 1], ws + F.offNrm));
+  return QTT_OK;
 }
 
 int fit_setup(const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt* c, Shape& s, FitPlan& F,
@@ -2426,6 +2774,56 @@ int qtt_fit(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, qt
   if (!std::isfinite(h->pin_dbl[0])) return QTT_ERR_NONFINITE;
   if (norm_host) *norm_host = h->pin_dbl[0];
   for (int k = 0; k <= n; ++k) c->ranks[k] = rc[k];
+  return QTT_OK;
+}
+
+int qtt_solve_query(const qtt_tt* w, const qtt_tt* b, const qtt_tt* x, int32_t ncores, int64_t max_rank,
+                    int64_t* bounds, size_t* bytes) {
+  if (!bytes || (ncores != 1 && ncores != 2)) return QTT_ERR_ARG;
+  int st = solve_check(w, b, x);
+  if (st) return st;
+  if (ncores == 2 && x->n < 2) return QTT_ERR_ARG;
+  SolvePlan F;
+  if ((st = make_solve_plan(w, b, x, ncores, max_rank, F))) return st;
+  Shape sx;
+  shape_from_tt(x, sx);
+  Plan P;
+  if ((st = make_plan(sx, 0, P, false))) return st;
+  *bytes = std::max(ws_bytes_of(P), (size_t)F.total * sizeof(double) + 256);
+  if (bounds)
+    for (int k = 0; k <= x->n; ++k) bounds[k] = F.bnd[k];
+  return QTT_OK;
+}
+
+int qtt_solve(qtt_handle h, const qtt_tt* w, const qtt_tt* b, qtt_tt* x, int32_t nsweeps, int32_t ncores,
+              double rel_tol, int64_t max_rank, qtt_round_info* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return QTT_ERR_ARG;
+  if (nsweeps < 0 || !(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return QTT_ERR_ARG;
+  size_t need = 0;
+  int st = qtt_solve_query(w, b, x, ncores, max_rank, nullptr, &need);
+  if (st) return st;
+  if (!ws || ws_bytes < need) return QTT_ERR_WORKSPACE;
+  SolvePlan F;
+  if ((st = make_solve_plan(w, b, x, ncores, max_rank, F))) return st;
+  double nrm = 0.0;
+  // the guess, orthogonalised from the left (centre at core n; ranks may shrink)
+  if ((st = qtt_orthogonalize(h, x, &nrm, ws, ws_bytes, stream))) return st;
+  Scoped sc(h->device);
+  hipStream_t strm = (hipStream_t)stream;
+  double* wsa = align_ws(ws);
+  const int n = x->n;
+  std::vector<long> rc(n + 1);
+  for (int k = 0; k <= n; ++k) rc[k] = x->ranks[k];
+  int maxsw = 0;
+  if ((st = solve_sweeps(h, strm, wsa, F, w, b, x, rc, nsweeps, rel_tol, max_rank, maxsw))) return st;
+  int e = readback(h, strm, wsa + F.offNrm, sizeof(double), h->pin_dbl);
+  if (e) return e;
+  if (!std::isfinite(h->pin_dbl[0])) return QTT_ERR_NONFINITE;
+  if (info) {
+    info->norm = h->pin_dbl[0];
+    info->jacobi_sweeps_max = maxsw;
+  }
+  for (int k = 0; k <= n; ++k) x->ranks[k] = rc[k];
   return QTT_OK;
 }
 

@@ -144,6 +144,24 @@ hipError_t round_record(hipStream_t s, const TruncOut* t, const int* sweeps, int
                         long long* ranks, int* status, int code_nonfinite, int code_noconv);
 long qr_t_doubles(int m, int n);
 
+// ---------------------------------------------------------------- linear solver (solve.hip)
+// Local matrix of the energy over a block of P physical values:
+// A[(a,i,c),(x,j,y)] = sum LW[a,al,x] Wl[al,i,j,be] RW[c,be,y]  (N = r0 P r1,
+// A is N x N row-major; LW [r0][w0][r0], Wl [w0][P][P][w1], RW [r1][w1][r1]).
+hipError_t local_matrix(hipStream_t s, const double* LW, const double* Wl, const double* RW, int r0, int P, int r1,
+                        int w0, int w1, double* A);
+// T2[a][i][be][y] = sum_{al,j} T1[a][al][j][y] W[al][i][j][be]
+hipError_t env3_left_mid(hipStream_t s, const double* T1, const double* W, int r0, int w0, int d, int w1, int r1,
+                         double* T2);
+// U2[i][c][al][x] = sum_{j,be} W[al][i][j][be] U1[x][j][c][be]
+hipError_t env3_right_mid(hipStream_t s, const double* U1, const double* W, int r0, int w0, int d, int w1, int r1,
+                          double* U2);
+// G[al][(i1,i2)][(j1,j2)][ga] = sum_be W1[al][i1][j1][be] W2[be][i2][j2][ga]
+hipError_t mpo_pair(hipStream_t s, const double* W1, const double* W2, int w0, int d1, int w1, int d2, int w2,
+                    double* G);
+// x <- R^{-1} x, R the upper triangle of A (N x N, leading dimension lda).
+hipError_t trsv_upper(hipStream_t s, const double* A, int N, long lda, double* x);
+
 // ---------------------------------------------------------------- kernel setup
 // Raise the dynamic-LDS limit of the kernels that stage more than 64 KiB
 // (on the current device); called once per handle before any launch.

@@ -38,6 +38,7 @@ EXPORTS = [
     "qtt_batch_plan_destroy", "qtt_contract_zipup", "qtt_zipup_query", "qtt_add",
     "qtt_fit", "qtt_fit_workspace_size", "qtt_set_jacobi_max_sweeps", "qtt_contract_round_noalloc",
     "qtt_inner_prec", "qtt_batch_plan_tiles", "qtt_contract_round_async", "qtt_fit2", "qtt_fit2_query",
+    "qtt_solve", "qtt_solve_query",
 ]
 # size of the fixed device array behind qtt_contract_round_noalloc
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -124,6 +125,9 @@ def load_library():
     L.qtt_fit_workspace_size.argtypes = [C.c_char_p, P(TT), P(TT), P(TT), P(C.c_size_t)]
     L.qtt_fit2.argtypes = [vp, C.c_char_p, P(TT), P(TT), P(TT), C.c_int32, C.c_double, C.c_int64, P(RoundInfoC),
                            vp, C.c_size_t, vp]
+    L.qtt_solve.argtypes = [vp, P(TT), P(TT), P(TT), C.c_int32, C.c_int32, C.c_double, C.c_int64, P(RoundInfoC),
+                            vp, C.c_size_t, vp]
+    L.qtt_solve_query.argtypes = [P(TT), P(TT), P(TT), C.c_int32, C.c_int64, P(C.c_int64), P(C.c_size_t)]
     L.qtt_fit2_query.argtypes = [C.c_char_p, P(TT), P(TT), P(TT), C.c_int64, P(C.c_int64), P(C.c_size_t)]
     L.qtt_add.argtypes = [vp, C.c_int32, P(TT), P(C.c_double), P(TT), vp]
     L.qtt_zipup_query.argtypes = [C.c_char_p, P(TT), P(TT), C.c_int64, C.c_int32, P(C.c_int64), P(C.c_size_t)]
@@ -650,6 +654,39 @@ def fit2(spec: str, a, b, guess, nsweeps: int = 1, rel_tol: float = 0.0, max_ran
     ranks = vc.ranks()
     extra = {"tails": [info.tail[k] for k in range(n - 1)], "jacobi_sweeps_max": info.c.jacobi_sweeps_max}
     return _views_of_compact(bufs, ranks, d), ranks, info.c.norm, extra
+
+
+def solve(w, b, guess, nsweeps: int = 1, ncores: int = 1, rel_tol: float = 0.0, max_rank: int = 0,
+          workspace: Optional[torch.Tensor] = None):
+    """DMRG-like solution of w x = b (qtt_solve) starting from a copy of
+    `guess`.  Returns (cores, ranks, norm)."""
+    L = load_library()
+    h = handle(b[0].device.index)
+    vw, vb = TTView(list(w), 2), TTView(list(b), 1)
+    n = len(guess)
+    d = [g.shape[1] for g in guess]
+    r_in = [guess[0].shape[0]] + [g.shape[-1] for g in guess]
+    probe = TTView([g.detach().reshape(-1) for g in guess], 1, ranks_override=r_in, phys_override=d)
+    bnd = (C.c_int64 * (n + 1))()
+    nb = C.c_size_t()
+    _check(L.qtt_solve_query(C.byref(vw.struct), C.byref(vb.struct), C.byref(probe.struct), int(ncores),
+                             int(max_rank), bnd, C.byref(nb)), "qtt_solve_query")
+    bounds = [int(bnd[k]) for k in range(n + 1)]
+    dev = b[0].device
+    bufs = []
+    for k, g in enumerate(guess):
+        buf = torch.zeros(max(bounds[k] * d[k] * bounds[k + 1], g.numel()), dtype=torch.float64, device=dev)
+        buf[: g.numel()] = g.detach().reshape(-1)
+        bufs.append(buf)
+    vx = TTView(bufs, 1, ranks_override=r_in, phys_override=d)
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = _workspace(nb.value, dev)
+    info = _Info(n)
+    _check(L.qtt_solve(h.ptr, C.byref(vw.struct), C.byref(vb.struct), C.byref(vx.struct), int(nsweeps), int(ncores),
+                       float(rel_tol), int(max_rank), C.byref(info.c), C.c_void_p(workspace.data_ptr()),
+                       workspace.numel(), _stream_ptr()), "qtt_solve")
+    ranks = vx.ranks()
+    return _views_of_compact(bufs, ranks, d), ranks, info.c.norm
 
 
 def round_tt(cores, rel_tol: float, max_rank: int = 0, prec: str = "fp64", want_sigmas: bool = False,
