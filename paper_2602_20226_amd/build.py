@@ -35,13 +35,22 @@ CFLAGS = [
 ]
 
 
+# Host-side sanitizer build (address + undefined behaviour) of the same
+# sources, for CPU tests of the host code (argument checks, planning): the
+# device code is compiled as usual, only the host pass is instrumented.
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+SAN_DIR = os.path.join(ROOT, "_build", "san")
+SAN_LIB = os.path.join(SAN_DIR, "libqtt.so")
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+def _compile(src: str, objdir: str = OBJ, extra=()) -> str:
+    obj = os.path.join(objdir, os.path.basename(src)[:-4] + ".o")
+    cmd = [HIPCC, *CFLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -70,5 +79,44 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+def build_sanitized(verbose: bool = True) -> str:
+    """The library with the host code instrumented by AddressSanitizer and
+    UndefinedBehaviorSanitizer, at _build/san/libqtt.so (not the product
+    library; load it with the sanitizer runtime preloaded, see
+    sanitizer_runtime())."""
+    objdir = os.path.join(SAN_DIR, "obj")
+    os.makedirs(objdir, exist_ok=True)
+    srcs = sources()
+    jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")), os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(lambda src: _compile(src, objdir, SAN_FLAGS), srcs))
+    tmp = SAN_LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *SAN_FLAGS, "-o", tmp, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SAN_LIB)
+    if verbose:
+        print(f"built {SAN_LIB} (host sanitizers) from {len(srcs)} sources")
+    return SAN_LIB
+
+
+def sanitizer_runtime() -> str:
+    """Path of the compiler's AddressSanitizer runtime (to preload)."""
+    r = subprocess.run([HIPCC, "--print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        base = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "llvm", "lib", "clang")
+        for ver in sorted(os.listdir(base)) if os.path.isdir(base) else []:
+            cand = os.path.join(base, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+            if os.path.exists(cand):
+                return cand
+        raise FileNotFoundError("AddressSanitizer runtime not found")
+    return path
+
+
 if __name__ == "__main__":
-    build()
+    if len(sys.argv) > 1 and sys.argv[1] == "sanitize":
+        build_sanitized()
+    else:
+        build()

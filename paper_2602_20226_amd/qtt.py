@@ -18,7 +18,9 @@ from typing import List, Optional, Sequence
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqtt.so")
+# QTT_LIBRARY names another build of the same library (the host-sanitizer
+# build of the CPU tests); by default the in-tree libqtt.so
+LIB_PATH = os.environ.get("QTT_LIBRARY") or os.path.join(HERE, "libqtt.so")
 
 QTT_OK = 0
 STATUS = {

@@ -210,3 +210,40 @@ def test_fit_workspace_size_and_shape_errors():
     assert L.qtt_fit_workspace_size(b"ij,j->i", C.byref(a), C.byref(b), C.byref(bad), C.byref(nb)) == -3
     assert L.qtt_fit_workspace_size(b"ij,jk->ik", C.byref(a), C.byref(b), C.byref(c), C.byref(nb)) == -10
     assert L.qtt_fit(None, b"ij,j->i", C.byref(a), C.byref(b), C.byref(c), 1, None, None, 0, None) == -1
+
+
+def test_fit2_and_solve_queries_bounds_and_errors():
+    """Rank capacities and workspace of the two-core fit and the linear
+    solver from the shapes alone, and their argument errors."""
+    L = Q.load_library()
+    n = 6
+    W = _fake_tt([1, 3, 5, 5, 5, 3, 1], [2] * (2 * n), legs=2)
+    b = _fake_tt([1, 2, 4, 4, 4, 2, 1], [2] * n)
+    x = _fake_tt([1, 2, 2, 2, 2, 2, 1], [2] * n)
+    bnd = (C.c_int64 * (n + 1))()
+    nb = C.c_size_t()
+    # two-core fit: bounds min(left, right, product rank, cap), at least the guess's
+    assert L.qtt_fit2_query(b"ij,j->i", C.byref(W), C.byref(b), C.byref(x), 0, bnd, C.byref(nb)) == 0
+    assert list(bnd) == [1, 2, 4, 8, 4, 2, 1] and nb.value > 0
+    assert L.qtt_fit2_query(b"ij,j->i", C.byref(W), C.byref(b), C.byref(x), 3, bnd, C.byref(nb)) == 0
+    assert list(bnd) == [1, 2, 3, 3, 3, 2, 1]
+    assert L.qtt_fit2_query(b"ijk->i", C.byref(W), C.byref(b), C.byref(x), 0, bnd, C.byref(nb)) == -2
+    short = _fake_tt([1, 2, 2, 1], [2] * 3)
+    assert L.qtt_fit2_query(b"ij,j->i", C.byref(W), C.byref(b), C.byref(short), 0, bnd, C.byref(nb)) == -3
+    # linear solver: one core keeps the guess's ranks, two cores grow to the cap
+    assert L.qtt_solve_query(C.byref(W), C.byref(b), C.byref(x), 1, 0, bnd, C.byref(nb)) == 0
+    assert list(bnd) == [1, 2, 2, 2, 2, 2, 1]
+    assert L.qtt_solve_query(C.byref(W), C.byref(b), C.byref(x), 2, 4, bnd, C.byref(nb)) == 0
+    assert list(bnd) == [1, 2, 4, 4, 4, 2, 1]
+    assert L.qtt_solve_query(C.byref(W), C.byref(b), C.byref(x), 3, 4, bnd, C.byref(nb)) == -1
+    assert L.qtt_solve_query(C.byref(W), C.byref(b), C.byref(short), 1, 0, bnd, C.byref(nb)) == -3
+    rect = _fake_tt([1, 3, 5, 5, 5, 3, 1], [2, 3] * n, legs=2)  # d_out != d_in
+    assert L.qtt_solve_query(C.byref(rect), C.byref(b), C.byref(x), 1, 0, bnd, C.byref(nb)) == -3
+    # two cores with no cap: local systems beyond the QR limit are refused
+    big = _fake_tt([1] + [2 ** min(k, 24 - k) for k in range(1, 24)] + [1], [2] * 24)
+    W24 = _fake_tt([1] + [5] * 23 + [1], [2] * 48, legs=2)
+    b24 = _fake_tt([1] + [2] * 23 + [1], [2] * 24)
+    bnd24 = (C.c_int64 * 25)()
+    assert L.qtt_solve_query(C.byref(W24), C.byref(b24), C.byref(big), 2, 0, bnd24, C.byref(nb)) == -10
+    assert L.qtt_solve(None, C.byref(W), C.byref(b), C.byref(x), 1, 1, 0.0, 0, None, None, 0, None) == -1
+    assert L.qtt_fit2(None, b"ij,j->i", C.byref(W), C.byref(b), C.byref(x), 1, 0.0, 0, None, None, 0, None) == -1
