@@ -174,7 +174,7 @@ def main():
                     help="after the measurement, run one plain device copy of this many MiB")
     ap.add_argument("--workload", default="laplacian3d_n42_r256",
                     choices=["laplacian3d_n42_r256", "laplacian3d_n42_r256_zipup", "hadamard_batch",
-                             "sum4_n42_r128_round", "laplacian2d_n32_r64_zipup_fit"],
+                             "sum4_n42_r128_round", "laplacian2d_n32_r64_zipup_fit", "heat2d_n24_solve"],
                     help="hadamard_batch: the batched form (512 uneven 1D Hadamard products, one graph launch); "
                          "laplacian3d_n42_r256_zipup: the same product by the decomposition (zip-up) algorithm")
     ap.add_argument("--ncores", type=int, default=2, choices=[1, 2],
@@ -207,6 +207,8 @@ def main():
         return bench_sum(args, I, Q, torch, dev)
     if args.workload == "laplacian2d_n32_r64_zipup_fit":
         return bench_fit(args, I, Q, torch, dev)
+    if args.workload == "heat2d_n24_solve":
+        return bench_solve(args, I, Q, torch, dev)
     zipup = args.workload.endswith("_zipup")
     w = I.laplacian3d_r256()
     A = Q.to_device(w.a, dev)
@@ -588,6 +590,109 @@ def bench_fit(args, I, Q, torch, dev):
         out["cpu_baseline"] = {"value": reps * of / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
                                "sample": f"{reps} full zip-up + variational sweep runs of the same workload "
                                          f"(NumPy FP64)", "seconds": dt}
+    print(json.dumps(out), flush=True)
+
+
+def solve_flops(ranks, d, rw, rb, nsweeps):
+    """Algorithmic FLOP of the one-core linear solver (same conventions):
+    per local solve of N = r0 d r1 unknowns the local matrix (N^2 rw0 rw1
+    products of 2 FLOP), its Householder QR (geqrf of N x N), Q^T b (ormqr
+    with one column) and the triangular solve (N^2), the right-hand side
+    (2 r0 rb0 d rb1 + 2 r0 d rb1 r1), the QR that moves the centre (geqrf of
+    the core's unfolding) and the environment steps (three-layer:
+    2 r0 rw0 r0 d r1 + 2 r0 d rw1 r1 rw0 d + 2 r1 r0 d rw1 r1; two-layer:
+    2 r0 rb0 d rb1 + 2 r1 r0 d rb1); two local solves per core per sweep."""
+    n = len(d)
+    f = 0.0
+    for k in range(n):
+        r0, r1, w0, w1, b0, b1, dk = ranks[k], ranks[k + 1], rw[k], rw[k + 1], rb[k], rb[k + 1], d[k]
+        N = r0 * dk * r1
+        local = 2.0 * N * N * w0 * w1 + geqrf_flops(N, N) + ormqr_flops(N, N, 1) + N * N
+        local += 2.0 * r0 * b0 * dk * b1 + 2.0 * r0 * dk * b1 * r1
+        move = geqrf_flops(r0 * dk, r1)
+        env = 2.0 * r0 * w0 * r0 * dk * r1 + 2.0 * r0 * dk * w1 * r1 * w0 * dk + 2.0 * r1 * r0 * dk * w1 * r1
+        env += 2.0 * r0 * b0 * dk * b1 + 2.0 * r1 * r0 * dk * b1
+        f += 2.0 * (local + move + env)
+    return f * nsweeps
+
+
+def bench_solve(args, I, Q, torch, dev):
+    """The DMRG-like linear solver (Sec. 5) on an implicit heat step of the 2D
+    2^12 x 2^12 grid (24 cores): (L + s I) x = b with L the Dirichlet
+    Laplacian MPO (rank 5), s = 1, b the rank-16 right-hand side of the 2D
+    gradient workload (seed 4) and its rank-32 x as the guess; one-core
+    sweeps (ranks 32), two sweeps per step.  A step is one qtt_solve call."""
+    import ctypes as C
+    w = I.residual_grad_2d()
+    m, D, s, nsweeps = 12, 2, 1.0, 2
+    Wc = I.laplacian_mpo(m, D, diag=2.0 + s / D)
+    A = Q.to_device(Wc, dev)
+    rhs, guess = w.extra["rhs"], w.b  # the workload's b (rank 16) and x (rank 32)
+    b = Q.to_device(rhs, dev)
+    g = Q.to_device(guess, dev)
+    n = len(g)
+    d = [c.shape[1] for c in g]
+    L = Q.load_library()
+    h = Q.handle(0)
+    vw, vb = Q.TTView(A, 2), Q.TTView(b, 1)
+    r_in = [g[0].shape[0]] + [c.shape[-1] for c in g]
+    vg = Q.TTView([c.reshape(-1) for c in g], 1, ranks_override=r_in, phys_override=d)
+    bnd = (C.c_int64 * (n + 1))()
+    nb = C.c_size_t()
+    Q._check(L.qtt_solve_query(C.byref(vw.struct), C.byref(vb.struct), C.byref(vg.struct), 1, 0, bnd, C.byref(nb)),
+             "qtt_solve_query")
+    bufs = [torch.zeros(int(bnd[k]) * d[k] * int(bnd[k + 1]), dtype=torch.float64, device=dev) for k in range(n)]
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    vx = Q.TTView(bufs, 1, ranks_override=r_in, phys_override=d)
+    info = Q._Info(n)
+
+    def step():
+        for k in range(n):  # restart from the guess
+            bufs[k][: g[k].numel()] = g[k].reshape(-1)
+        for k in range(n + 1):
+            vx._ranks[k] = r_in[k]
+        Q._check(L.qtt_solve(h.ptr, C.byref(vw.struct), C.byref(vb.struct), C.byref(vx.struct), nsweeps, 1, 0.0, 0,
+                             C.byref(info.c), C.c_void_p(ws.data_ptr()), ws.numel(), Q._stream_ptr()), "qtt_solve")
+        return vx.ranks()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ranks = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    rw = [1] + [c.shape[-1] for c in Wc]
+    rbr = [1] + [c.shape[-1] for c in rhs]
+    flops = solve_flops(ranks, d, rw, rbr, nsweeps)
+    out = {
+        "metric": "QTT DMRG-like linear solve TFLOP/s (implicit heat step, 2D 2^12 x 2^12 grid, rank 32, 2 sweeps)",
+        "value": flops / sec / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "cores": n, "operator": "Laplacian + I (MPO rank 5)", "rhs_rank": max(rbr),
+                   "x_rank": max(ranks), "sweeps": nsweeps, "local_solver": "Householder QR + triangular solve"},
+        "algorithmic_gflop_per_step": flops / 1e9,
+    }
+    if not args.no_kernel_breakdown:
+        add_roofline(out, kernel_breakdown(Q, step), sec)
+    if not args.no_cpu_baseline:
+        import oracle as O
+        threads = _blas_threads()
+        # bounded sample: one sweep of the same solve (the timed step runs two), on the host and on
+        # the GPU from the same guess, for the baseline and for the error of the GPU result
+        t0 = time.perf_counter()
+        ref = O.solve_energy(Wc, rhs, guess, nsweeps=1, ncores=1)
+        dt = time.perf_counter() - t0
+        cores, r1, _ = Q.solve(A, b, g, nsweeps=1, ncores=1)
+        out["rel_err_vs_oracle"] = O.rel_error(Q.to_host(cores), ref)
+        out["ranks_identical"] = O.ranks_of(ref) == r1
+        out["cpu_baseline"] = {"value": solve_flops(r1, d, rw, rbr, 1) / dt / 1e12, "unit": "TFLOP/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": "one sweep of the same solve from the same guess (NumPy FP64, dense local "
+                                         "solves); the GPU result of that sweep gives rel_err_vs_oracle",
+                               "seconds": dt}
     print(json.dumps(out), flush=True)
 
 

@@ -1219,7 +1219,7 @@ int zip_sweep(qtt_context* h, hipStream_t st, double* ws, const Shape& s, const 
       QTT_HIP(gather_rows_normalized(st, X, L, perm, sig, tr, V, L, rn));
       QTT_HIP(transpose(st, V, rn, m, m, (double*)out->cores[outc], rn));
       // Yn = B V_r (cols x rn); tall B = Q_B R  =>  Q_B [R V_r; 0]
-      QTT_HIP(gemm_f64(st, false, true, p, rn, L, 1.0, Xc, L, 0, V, L, 0, 0.0, Yn, rn, 0, 1));
+      QTT_HIP(gemm_prec(st, prec, false, true, p, rn, L, Xc, L, V, L, Yn, rn));
       if (tall) {
         if (cols > p) QTT_HIP(fill_f64(st, Yn + (long)p * rn, 0.0, (long)(cols - p) * rn));
         QTT_HIP(apply_q(st, Bt, cols, p, m, TB, Yn, rn, rn, false, scr));
