@@ -266,8 +266,8 @@ int qtt_fit2(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, q
  * are caller-owned with the capacity of qtt_solve_query's bounds (for
  * ncores = 2 a max_rank keeps them small); x->ranks is rewritten.  Limits:
  * local systems of at most 4096 unknowns (rank^2 d^ncores), split rows of
- * at most 1024.  info (nullable): norm = ||x||, jacobi_sweeps_max.
- * Synchronous. */
+ * at most 1024.  A zero b gives the zero train (all ranks 1) at once.
+ * info (nullable): norm = ||x||, jacobi_sweeps_max.  Synchronous. */
 int qtt_solve(qtt_handle h, const qtt_tt *w, const qtt_tt *b, qtt_tt *x, int32_t nsweeps, int32_t ncores,
               double rel_tol, int64_t max_rank, qtt_round_info *info, void *ws, size_t ws_bytes, void *stream);
 /* Rank capacity (bounds, n+1, nullable) and workspace (bytes) of qtt_solve;

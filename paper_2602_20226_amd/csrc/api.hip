@@ -2789,7 +2789,8 @@ int qtt_solve_query(const qtt_tt* w, const qtt_tt* b, const qtt_tt* x, int32_t n
   shape_from_tt(x, sx);
   Plan P;
   if ((st = make_plan(sx, 0, P, false))) return st;
-  *bytes = std::max(ws_bytes_of(P), (size_t)F.total * sizeof(double) + 256);
+  *bytes = std::max({ws_bytes_of(P), (size_t)F.total * sizeof(double) + 256,
+                     (size_t)inner_plan(b, b).total * sizeof(double) + 256});
   if (bounds)
     for (int k = 0; k <= x->n; ++k) bounds[k] = F.bnd[k];
   return QTT_OK;
@@ -2806,12 +2807,30 @@ int qtt_solve(qtt_handle h, const qtt_tt* w, const qtt_tt* b, qtt_tt* x, int32_t
   SolvePlan F;
   if ((st = make_solve_plan(w, b, x, ncores, max_rank, F))) return st;
   double nrm = 0.0;
+  const int n = x->n;
+  {
+    // b = 0: the solution is the zero train (rank 1), written directly; the
+    // sweeps would split zero super-cores into zero, not orthonormal, cores
+    double bb = 0.0;
+    if ((st = inner_impl<double>(h, b, b, &bb, ws, (hipStream_t)stream))) return st;
+    if (!std::isfinite(bb)) return QTT_ERR_NONFINITE;
+    if (bb == 0.0) {
+      Scoped sc(h->device);
+      for (int k = 0; k < n; ++k) QTT_HIP(fill_f64((hipStream_t)stream, (double*)x->cores[k], 0.0, dphys(x, k)));
+      QTT_HIP(hipStreamSynchronize((hipStream_t)stream));
+      for (int k = 0; k <= n; ++k) x->ranks[k] = 1;
+      if (info) {
+        info->norm = 0.0;
+        info->jacobi_sweeps_max = 0;
+      }
+      return QTT_OK;
+    }
+  }
   // the guess, orthogonalised from the left (centre at core n; ranks may shrink)
   if ((st = qtt_orthogonalize(h, x, &nrm, ws, ws_bytes, stream))) return st;
   Scoped sc(h->device);
   hipStream_t strm = (hipStream_t)stream;
   double* wsa = align_ws(ws);
-  const int n = x->n;
   std::vector<long> rc(n + 1);
   for (int k = 0; k <= n; ++k) rc[k] = x->ranks[k];
   int maxsw = 0;
