@@ -28,6 +28,10 @@ numpy.linalg, written from the paper's definitions:
   * the DMRG-like linear solver of Sec. 5 for symmetric positive definite
     operators: the energy <x, W x> - 2 <x, b> minimised over one core or a
     super-core of two cores at a time (local dense solves);
+  * the AMEn linear solver of Sec. 5: one-core energy minimisation, a
+    truncation of each solved core and its basis enriched by the projection
+    of the residual b - W x onto the frames of a second train z that tracks
+    the residual (Dolgov and Savostyanov's alternating minimal energy method);
   * sums of many trains (the block structure of Sec. 3.1, operators
     included) and the operator product 'ij,jk->ik';
   * general digit bases (factorised dimensions, Sec. 2): every function takes
@@ -36,7 +40,8 @@ numpy.linalg, written from the paper's definitions:
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: dense reconstruction + numpy.einsum on tiny grids, the closed forms of
 Sec. 4 (exp rank 1, cos/sin rank 2, degree-p polynomial rank p+1, the shift
-matrices of Sec. 4.2), Laplacian eigenvectors, and invariants.
+matrices of Sec. 4.2), the discrete Poisson solution j (N + 1 - j) / 2,
+Laplacian eigenvectors, dense solves, and invariants.
 """
 from .tt import *  # noqa: F401,F403
 from .tt import __all__  # noqa: F401

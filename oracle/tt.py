@@ -24,6 +24,7 @@ __all__ = [
     "fit",
     "fit_two_core",
     "solve_energy",
+    "solve_amen",
     "RoundInfo",
     "truncation_rank",
     "cut_gaps",
@@ -684,6 +685,154 @@ def solve_energy(W, b, x0, nsweeps: int = 1, ncores: int = 1, rel_tol: float = 0
     ranks = [1] + [c.shape[-1] for c in X]
     if return_info:
         return X, {"ranks": ranks, "energies": energies}
+    return X
+
+
+def solve_amen(W, b, x0, z0, nsweeps: int = 1, rel_tol: float = 0.0, max_rank: int = 0,
+               return_info: bool = False, trace: Optional[list] = None):
+    """Solution of W x = b (W symmetric positive definite) by the AMEn solver
+    named in Sec. 5: one-core energy minimisation as in solve_energy,
+    followed at every step by a truncation of the solved core and a gradient
+    (residual) enrichment of its basis, after Dolgov and Savostyanov's
+    alternating minimal energy method.
+
+    Besides x the method carries a second train z (ranks never grow) that
+    approximates the residual r = b - W x.  A step at core q of a sweep
+    moving left (moving right is the mirror image):
+      1. the local system of solve_energy gives the core x_q (frames of x
+         orthonormal around q);
+      2. x_q's unfolding (r_q) x (d r_{q+1}) is truncated by an SVD,
+         keeping the smallest rank whose discarded singular values have
+         2-norm <= rel_tol ||x_q||_F / sqrt(n-1), capped at max_rank:
+         x_q ~= (U S) V^T;
+      3. z's core becomes the projection of r (with the truncated core) onto
+         z's own left and right frames, z_q = (Z_<q x I x Z_>q)^T r, made
+         right-orthonormal by a QR of its transposed unfolding;
+      4. the enrichment core is the projection of r onto z's left frame and
+         x's right frame, e_q = (Z_<q x I x X_>q)^T r;
+      5. the rows [V^T; e_q] (rank r + r_z) are orthonormalised by a QR of
+         their transpose: x_q = Q^T, and x_{q-1} takes (U S) R^T restricted
+         to V's rows (the enrichment rows meet zeros, so the tensor x is the
+         truncated one, now in a larger basis that contains the residual
+         direction).
+    The end cores of a pass take the solved core itself, and z's end core
+    the projection without the QR.  (The factor absorbed into the neighbour
+    in step 5 keeps x a valid train between steps; the next local solve
+    replaces that core, so the result does not depend on it.)  The guess x
+    and the initial residual train z (its random numbers are an input) are
+    orthogonalised from the left first; each sweep runs from the right end
+    to the left and back.  Returns x's cores (and, with return_info, z's
+    cores, the ranks of x and the energy -x_loc . b_loc after every local
+    solve).  trace (tests): a list that receives, per truncated step, the
+    direction, q, the truncated core, e_q, z's projected core and copies of
+    the cores of x and z the projections used as frames."""
+    Wm = [np.asarray(w, dtype=np.float64) for w in W]
+    Bm = [_mat(c) for c in b]
+    x, _ = orthogonalize(x0)
+    X = [_mat(c).copy() for c in x]
+    z, _ = orthogonalize(z0)
+    Z = [_mat(c).copy() for c in z]
+    n = len(X)
+    if len(Z) != n:
+        raise ValueError("x0 and z0 must have the same number of cores")
+    energies = []
+    one3 = np.ones((1, 1, 1))
+    one2 = np.ones((1, 1))
+
+    def w_left(LW, U, q, V):  # <U|W|V> environment, one core to the right
+        return np.einsum("aAx,aic,AijB,xjy->cBy", LW, U, Wm[q], V, optimize=True)
+
+    def w_right(RW, U, q, V):
+        return np.einsum("aic,AijB,xjy,cBy->aAx", U, Wm[q], V, RW, optimize=True)
+
+    def b_left(Lb, U, q):  # <U|b> environment
+        return np.einsum("ae,aic,eif->cf", Lb, U, Bm[q], optimize=True)
+
+    def b_right(Rb, U, q):
+        return np.einsum("aic,eif,cf->ae", U, Bm[q], Rb, optimize=True)
+
+    def project(q, LW, RW, Lb, Rb, xq):
+        """(frame_left x I x frame_right)^T (b - W x) with x's core q = xq."""
+        return (np.einsum("ae,eif,cf->aic", Lb, Bm[q], Rb, optimize=True)
+                - np.einsum("aAx,AijB,xjy,cBy->aic", LW, Wm[q], xq, RW, optimize=True))
+
+    def local_solve(q, LW, RW, Lb, Rb):
+        A = np.einsum("aAx,AijB,cBy->aicxjy", LW, Wm[q], RW, optimize=True)
+        rhs = np.einsum("ae,eif,cf->aic", Lb, Bm[q], Rb, optimize=True)
+        N = rhs.size
+        sol = np.linalg.solve(A.reshape(N, N), rhs.reshape(N))
+        energies.append(-float(sol @ rhs.reshape(N)))
+        return sol.reshape(rhs.shape)
+
+    def truncate(M):
+        U, sg, Vt = np.linalg.svd(M, full_matrices=False)
+        delta = rel_tol * float(np.linalg.norm(sg)) / math.sqrt(max(n - 1, 1))
+        r = max(truncation_rank(sg, delta, max_rank)[0], 1)
+        return U[:, :r], sg[:r], Vt[:r]
+
+    LW, Lb, LzW, Lzb = [one3], [one2], [one3], [one2]
+    for q in range(n - 1):
+        LW.append(w_left(LW[q], X[q], q, X[q]))
+        Lb.append(b_left(Lb[q], X[q], q))
+        LzW.append(w_left(LzW[q], Z[q], q, X[q]))
+        Lzb.append(b_left(Lzb[q], Z[q], q))
+    RW, Rb, RzW, Rzb = ([None] * (n + 1) for _ in range(4))
+    RW[n], Rb[n], RzW[n], Rzb[n] = one3, one2, one3, one2
+    for _ in range(nsweeps):
+        for q in range(n - 1, -1, -1):  # right to left
+            sol = local_solve(q, LW[q], RW[q + 1], Lb[q], Rb[q + 1])
+            if q == 0:
+                X[0] = sol
+                Z[0] = project(0, LzW[0], RzW[1], Lzb[0], Rzb[1], sol)
+                break
+            r0, d, r1 = sol.shape
+            U, sg, Vt = truncate(sol.reshape(r0, d * r1))
+            rn = Vt.shape[0]
+            US = U * sg[None, :]
+            xt = (US @ Vt).reshape(r0, d, r1)
+            zc = project(q, LzW[q], RzW[q + 1], Lzb[q], Rzb[q + 1], xt)
+            e = project(q, LzW[q], RW[q + 1], Lzb[q], Rb[q + 1], xt)
+            if trace is not None:
+                trace.append({"dir": "left", "q": q, "xt": xt, "e": e, "zc": zc,
+                              "X": [c.copy() for c in X], "Z": [c.copy() for c in Z]})
+            Qm, Rr = np.linalg.qr(np.vstack([Vt, e.reshape(e.shape[0], d * r1)]).T)
+            X[q] = Qm.T.reshape(Qm.shape[1], d, r1)
+            X[q - 1] = np.einsum("aib,bc->aic", X[q - 1], US @ Rr[:, :rn].T)
+            Qz, _ = np.linalg.qr(zc.reshape(zc.shape[0], d * zc.shape[2]).T)
+            Z[q] = Qz.T.reshape(Qz.shape[1], d, zc.shape[2])
+            RW[q] = w_right(RW[q + 1], X[q], q, X[q])
+            Rb[q] = b_right(Rb[q + 1], X[q], q)
+            RzW[q] = w_right(RzW[q + 1], Z[q], q, X[q])
+            Rzb[q] = b_right(Rzb[q + 1], Z[q], q)
+        LW, Lb, LzW, Lzb = [one3], [one2], [one3], [one2]
+        for q in range(n):  # and back
+            sol = local_solve(q, LW[q], RW[q + 1], Lb[q], Rb[q + 1])
+            if q == n - 1:
+                X[q] = sol
+                Z[q] = project(q, LzW[q], RzW[q + 1], Lzb[q], Rzb[q + 1], sol)
+                break
+            r0, d, r1 = sol.shape
+            U, sg, Vt = truncate(sol.reshape(r0 * d, r1))
+            rn = U.shape[1]
+            SVt = sg[:, None] * Vt
+            xt = (U @ SVt).reshape(r0, d, r1)
+            zc = project(q, LzW[q], RzW[q + 1], Lzb[q], Rzb[q + 1], xt)
+            e = project(q, LW[q], RzW[q + 1], Lb[q], Rzb[q + 1], xt)
+            if trace is not None:
+                trace.append({"dir": "right", "q": q, "xt": xt, "e": e, "zc": zc,
+                              "X": [c.copy() for c in X], "Z": [c.copy() for c in Z]})
+            Qm, Rr = np.linalg.qr(np.hstack([U, e.reshape(r0 * d, e.shape[2])]))
+            X[q] = Qm.reshape(r0, d, Qm.shape[1])
+            X[q + 1] = np.einsum("ab,bic->aic", Rr[:, :rn] @ SVt, X[q + 1])
+            Qz, _ = np.linalg.qr(zc.reshape(zc.shape[0] * d, zc.shape[2]))
+            Z[q] = Qz.reshape(zc.shape[0], d, Qz.shape[1])
+            LW.append(w_left(LW[q], X[q], q, X[q]))
+            Lb.append(b_left(Lb[q], X[q], q))
+            LzW.append(w_left(LzW[q], Z[q], q, X[q]))
+            Lzb.append(b_left(Lzb[q], Z[q], q))
+    ranks = [1] + [c.shape[-1] for c in X]
+    if return_info:
+        return X, {"z": Z, "ranks": ranks, "energies": energies}
     return X
 
 
