@@ -689,7 +689,7 @@ def solve_energy(W, b, x0, nsweeps: int = 1, ncores: int = 1, rel_tol: float = 0
 
 
 def solve_amen(W, b, x0, z0, nsweeps: int = 1, rel_tol: float = 0.0, max_rank: int = 0,
-               return_info: bool = False, trace: Optional[list] = None):
+               span_tol: float = 1e-10, return_info: bool = False, trace: Optional[list] = None):
     """Solution of W x = b (W symmetric positive definite) by the AMEn solver
     named in Sec. 5: one-core energy minimisation as in solve_energy,
     followed at every step by a truncation of the solved core and a gradient
@@ -705,27 +705,40 @@ def solve_amen(W, b, x0, z0, nsweeps: int = 1, rel_tol: float = 0.0, max_rank: i
          keeping the smallest rank whose discarded singular values have
          2-norm <= rel_tol ||x_q||_F / sqrt(n-1), capped at max_rank:
          x_q ~= (U S) V^T;
-      3. z's core becomes the projection of r (with the truncated core) onto
-         z's own left and right frames, z_q = (Z_<q x I x Z_>q)^T r, made
-         right-orthonormal by a QR of its transposed unfolding;
+      3. z's core is built from the projection of r (with the truncated
+         core) onto z's own left and right frames,
+         z_q = (Z_<q x I x Z_>q)^T r, as the orthonormal rows spanning its
+         rows (below);
       4. the enrichment core is the projection of r onto z's left frame and
          x's right frame, e_q = (Z_<q x I x X_>q)^T r;
-      5. the rows [V^T; e_q] (rank r + r_z) are orthonormalised by a QR of
-         their transpose: x_q = Q^T, and x_{q-1} takes (U S) R^T restricted
-         to V's rows (the enrichment rows meet zeros, so the tensor x is the
+      5. x's core becomes the orthonormal rows spanning the rows of
+         [V^T; e_q / s] (rank up to r + r_z), and x_{q-1} takes the
+         coefficients of U S V^T in that basis (the tensor x is the
          truncated one, now in a larger basis that contains the residual
          direction).
+    "Orthonormal rows spanning the rows of M" are the right singular vectors
+    of M whose discarded singular values have 2-norm <= span_tol (at least
+    one; a zero row where the kept singular value is zero), with M scaled
+    by s = ||projection of b|| + ||projection of W x|| (the two terms of the
+    projected residual).  A QR would span the same space when M has full
+    row rank; where it has not -- the frames of x and z overlap near the
+    ends of the chain, and a converged residual is rounding noise -- its
+    extra rows are arbitrary, and the next local solve would search along
+    them.  The cut leaves out directions below span_tol relative to the
+    residual's own terms, so the result does not depend on how the basis is
+    completed.
     The end cores of a pass take the solved core itself, and z's end core
-    the projection without the QR.  (The factor absorbed into the neighbour
-    in step 5 keeps x a valid train between steps; the next local solve
-    replaces that core, so the result does not depend on it.)  The guess x
-    and the initial residual train z (its random numbers are an input) are
-    orthogonalised from the left first; each sweep runs from the right end
-    to the left and back.  Returns x's cores (and, with return_info, z's
-    cores, the ranks of x and the energy -x_loc . b_loc after every local
-    solve).  trace (tests): a list that receives, per truncated step, the
-    direction, q, the truncated core, e_q, z's projected core and copies of
-    the cores of x and z the projections used as frames."""
+    the projection.  (The factor absorbed into the neighbour in step 5 keeps
+    x a valid train between steps; the next local solve replaces that core,
+    so the result does not depend on it.)  The guess x and the initial
+    residual train z (its random numbers are an input) are orthogonalised
+    from the left first; each sweep runs from the right end to the left and
+    back.  Returns x's cores (and, with return_info, z's cores, the ranks of
+    x and the energy -x_loc . b_loc after every local solve).  trace
+    (tests): a list that receives, per truncated step, the direction, q,
+    the truncated core, e_q, z's projected core, their scales s, copies of
+    the cores of x and z the projections used as frames, the kept singular
+    vectors and the new bases of x and z (as rows)."""
     Wm = [np.asarray(w, dtype=np.float64) for w in W]
     Bm = [_mat(c) for c in b]
     x, _ = orthogonalize(x0)
@@ -752,9 +765,21 @@ def solve_amen(W, b, x0, z0, nsweeps: int = 1, rel_tol: float = 0.0, max_rank: i
         return np.einsum("aic,eif,cf->ae", U, Bm[q], Rb, optimize=True)
 
     def project(q, LW, RW, Lb, Rb, xq):
-        """(frame_left x I x frame_right)^T (b - W x) with x's core q = xq."""
-        return (np.einsum("ae,eif,cf->aic", Lb, Bm[q], Rb, optimize=True)
-                - np.einsum("aAx,AijB,xjy,cBy->aic", LW, Wm[q], xq, RW, optimize=True))
+        """(frame_left x I x frame_right)^T (b - W x) with x's core q = xq, and
+        the scale ||projection of b|| + ||projection of W x||."""
+        pb = np.einsum("ae,eif,cf->aic", Lb, Bm[q], Rb, optimize=True)
+        pw = np.einsum("aAx,AijB,xjy,cBy->aic", LW, Wm[q], xq, RW, optimize=True)
+        return pb - pw, float(np.linalg.norm(pb) + np.linalg.norm(pw))
+
+    def span_rows(M):
+        _, sg, Vt = np.linalg.svd(M, full_matrices=False)
+        k = truncation_rank(sg, span_tol, 0)[0]
+        out = Vt[:k].copy()
+        out[sg[:k] == 0.0] = 0.0
+        return out
+
+    def unit(M, s):
+        return M / s if s > 0.0 else M
 
     def local_solve(q, LW, RW, Lb, Rb):
         A = np.einsum("aAx,AijB,cBy->aicxjy", LW, Wm[q], RW, optimize=True)
@@ -783,23 +808,24 @@ def solve_amen(W, b, x0, z0, nsweeps: int = 1, rel_tol: float = 0.0, max_rank: i
             sol = local_solve(q, LW[q], RW[q + 1], Lb[q], Rb[q + 1])
             if q == 0:
                 X[0] = sol
-                Z[0] = project(0, LzW[0], RzW[1], Lzb[0], Rzb[1], sol)
+                Z[0] = project(0, LzW[0], RzW[1], Lzb[0], Rzb[1], sol)[0]
                 break
             r0, d, r1 = sol.shape
             U, sg, Vt = truncate(sol.reshape(r0, d * r1))
-            rn = Vt.shape[0]
             US = U * sg[None, :]
             xt = (US @ Vt).reshape(r0, d, r1)
-            zc = project(q, LzW[q], RzW[q + 1], Lzb[q], Rzb[q + 1], xt)
-            e = project(q, LzW[q], RW[q + 1], Lzb[q], Rb[q + 1], xt)
+            zc, sz = project(q, LzW[q], RzW[q + 1], Lzb[q], Rzb[q + 1], xt)
+            e, se = project(q, LzW[q], RW[q + 1], Lzb[q], Rb[q + 1], xt)
             if trace is not None:
-                trace.append({"dir": "left", "q": q, "xt": xt, "e": e, "zc": zc,
+                trace.append({"dir": "left", "q": q, "xt": xt, "e": e, "zc": zc, "se": se, "sz": sz,
                               "X": [c.copy() for c in X], "Z": [c.copy() for c in Z]})
-            Qm, Rr = np.linalg.qr(np.vstack([Vt, e.reshape(e.shape[0], d * r1)]).T)
-            X[q] = Qm.T.reshape(Qm.shape[1], d, r1)
-            X[q - 1] = np.einsum("aib,bc->aic", X[q - 1], US @ Rr[:, :rn].T)
-            Qz, _ = np.linalg.qr(zc.reshape(zc.shape[0], d * zc.shape[2]).T)
-            Z[q] = Qz.T.reshape(Qz.shape[1], d, zc.shape[2])
+            B = span_rows(np.vstack([Vt, unit(e.reshape(e.shape[0], d * r1), se)]))
+            X[q] = B.reshape(B.shape[0], d, r1)
+            X[q - 1] = np.einsum("aib,bc->aic", X[q - 1], US @ (Vt @ B.T))
+            Bz = span_rows(unit(zc.reshape(zc.shape[0], d * zc.shape[2]), sz))
+            Z[q] = Bz.reshape(Bz.shape[0], d, zc.shape[2])
+            if trace is not None:
+                trace[-1].update({"Vt": Vt, "B": B, "Bz": Bz})
             RW[q] = w_right(RW[q + 1], X[q], q, X[q])
             Rb[q] = b_right(Rb[q + 1], X[q], q)
             RzW[q] = w_right(RzW[q + 1], Z[q], q, X[q])
@@ -809,23 +835,24 @@ def solve_amen(W, b, x0, z0, nsweeps: int = 1, rel_tol: float = 0.0, max_rank: i
             sol = local_solve(q, LW[q], RW[q + 1], Lb[q], Rb[q + 1])
             if q == n - 1:
                 X[q] = sol
-                Z[q] = project(q, LzW[q], RzW[q + 1], Lzb[q], Rzb[q + 1], sol)
+                Z[q] = project(q, LzW[q], RzW[q + 1], Lzb[q], Rzb[q + 1], sol)[0]
                 break
             r0, d, r1 = sol.shape
             U, sg, Vt = truncate(sol.reshape(r0 * d, r1))
-            rn = U.shape[1]
             SVt = sg[:, None] * Vt
             xt = (U @ SVt).reshape(r0, d, r1)
-            zc = project(q, LzW[q], RzW[q + 1], Lzb[q], Rzb[q + 1], xt)
-            e = project(q, LW[q], RzW[q + 1], Lb[q], Rzb[q + 1], xt)
+            zc, sz = project(q, LzW[q], RzW[q + 1], Lzb[q], Rzb[q + 1], xt)
+            e, se = project(q, LW[q], RzW[q + 1], Lb[q], Rzb[q + 1], xt)
             if trace is not None:
-                trace.append({"dir": "right", "q": q, "xt": xt, "e": e, "zc": zc,
+                trace.append({"dir": "right", "q": q, "xt": xt, "e": e, "zc": zc, "se": se, "sz": sz,
                               "X": [c.copy() for c in X], "Z": [c.copy() for c in Z]})
-            Qm, Rr = np.linalg.qr(np.hstack([U, e.reshape(r0 * d, e.shape[2])]))
-            X[q] = Qm.reshape(r0, d, Qm.shape[1])
-            X[q + 1] = np.einsum("ab,bic->aic", Rr[:, :rn] @ SVt, X[q + 1])
-            Qz, _ = np.linalg.qr(zc.reshape(zc.shape[0] * d, zc.shape[2]))
-            Z[q] = Qz.reshape(zc.shape[0], d, Qz.shape[1])
+            B = span_rows(np.vstack([U.T, unit(e.reshape(r0 * d, e.shape[2]), se).T]))
+            X[q] = B.T.reshape(r0, d, B.shape[0])
+            X[q + 1] = np.einsum("ab,bic->aic", (B @ U) @ SVt, X[q + 1])
+            Bz = span_rows(unit(zc.reshape(zc.shape[0] * d, zc.shape[2]), sz).T)
+            Z[q] = Bz.T.reshape(zc.shape[0], d, Bz.shape[0])
+            if trace is not None:
+                trace[-1].update({"Vt": U.T, "B": B, "Bz": Bz})
             LW.append(w_left(LW[q], X[q], q, X[q]))
             Lb.append(b_left(Lb[q], X[q], q))
             LzW.append(w_left(LzW[q], Z[q], q, X[q]))

@@ -14,7 +14,12 @@ The checks do not go through the oracle's other solvers:
   r = b - W x onto its frame: <z, r> = ||z||^2 <= ||r||^2, and z vanishes
   when x has converged;
 - ranks stay within the cap plus the enrichment rank (and grow past the
-  cap: the enrichment is kept).
+  cap: the enrichment is kept);
+- x and z are linear in b (the basis cut is relative to the residual's own
+  terms);
+- the enriched bases are orthonormal, span every significant direction of
+  [V^T; e/s] and hold none of the exactly null directions that the overlap
+  of the x and z frames near the chain ends produces.
 """
 import numpy as np
 
@@ -166,3 +171,51 @@ def test_enrichment_and_residual_cores_follow_their_definitions():
                            compute_uv=False)
         truncated += int(np.sum(sv > 1e-12 * sv[0]) <= 2)
     assert truncated == len(trace)
+
+
+def test_solution_is_linear_in_the_right_hand_side():
+    """x(c b) = c x(b) and z(c b) = c z(b) with the same ranks: the
+    enrichment cut is measured against the residual's own terms, not an
+    absolute level."""
+    W, b, x0, z0, A, bd, xs = _case_2d(seed=19)
+    X1, i1 = O.solve_amen(W, b, x0, z0, nsweeps=2, rel_tol=1e-10, max_rank=4, return_info=True)
+    for c in (1e-12, 1e12):
+        bc = O.tt_scale(b, c)
+        Xc, ic = O.solve_amen(W, bc, x0, z0, nsweeps=2, rel_tol=1e-10, max_rank=4, return_info=True)
+        assert ic["ranks"] == i1["ranks"]
+        assert O.rel_error(O.tt_scale(Xc, 1.0 / c), X1) < 1e-12
+        assert O.diff_norm(O.tt_scale(ic["z"], 1.0 / c), i1["z"]) < 1e-12 * O.norm(b)
+
+
+def test_enriched_bases_hold_no_null_directions():
+    """Near the ends of the chain the frames of x and z overlap, so the
+    residual's projection has exactly null directions there, and where the
+    residual vanishes in the frames it is rounding noise.  The new bases
+    are orthonormal, every row carries a direction of [V^T; e/s] (and of
+    z's projection), and no significant direction is left out."""
+    m = 7
+    W = Q.laplacian_mpo(m, 1, diag=2.25)
+    rng = np.random.default_rng(620)
+    b = Q.random_mps(m, 2, rng)
+    x0 = Q.random_mps(m, 2, rng)
+    z0 = Q.random_mps(m, 3, rng)
+    trace = []
+    O.solve_amen(W, b, x0, z0, nsweeps=2, rel_tol=1e-10, max_rank=12, trace=trace)
+    shrunk = 0
+    for t in trace:
+        B, Bz, Vt = t["B"], t["Bz"], t["Vt"]
+        r0, d, r1 = t["xt"].shape
+        if t["dir"] == "left":
+            E = np.vstack([Vt, t["e"].reshape(t["e"].shape[0], d * r1) / t["se"]])
+            Ez = t["zc"].reshape(t["zc"].shape[0], -1) / t["sz"]
+        else:
+            E = np.vstack([Vt, (t["e"].reshape(r0 * d, -1) / t["se"]).T])
+            Ez = (t["zc"].reshape(-1, t["zc"].shape[2]) / t["sz"]).T
+        for basis, M in ((B, E), (Bz, Ez)):
+            k = basis.shape[0]
+            assert np.abs(basis @ basis.T - np.eye(k)).max() < 1e-13
+            assert np.linalg.norm(M - (M @ basis.T) @ basis) < 1e-9
+            if basis is B or np.linalg.norm(M) > 1e-6:
+                assert np.linalg.svd(M @ basis.T, compute_uv=False).min() > 1e-8
+        shrunk += int(B.shape[0] < min(E.shape))
+    assert shrunk > 0  # the overlap occurs in this case
