@@ -275,6 +275,38 @@ int qtt_solve(qtt_handle h, const qtt_tt *w, const qtt_tt *b, qtt_tt *x, int32_t
 int qtt_solve_query(const qtt_tt *w, const qtt_tt *b, const qtt_tt *x, int32_t ncores, int64_t max_rank,
                     int64_t *bounds, size_t *bytes);
 
+/* Linear system W x = b for a symmetric positive definite W by the AMEn
+ * solver of Sec. 5 (single-core sweeps with gradient enrichment, after
+ * Dolgov and Savostyanov's alternating minimal energy method).  Same
+ * operands as qtt_solve, plus z: a train that approximates the residual
+ * b - W x (caller-owned FP64 MPS of x's length and sizes; its initial cores
+ * are an input, e.g. seeded random numbers; its ranks never grow).  Each
+ * step at core q: the one-core local system of qtt_solve gives x_q; its
+ * unfolding is truncated by the Jacobi SVD (smallest rank whose discarded
+ * singular values have 2-norm <= rel_tol ||x_q||_F / sqrt(n-1), capped at
+ * max_rank when > 0); z's core is built from the projection of the
+ * residual onto z's frames, and the projection e onto z's frame on one side
+ * and x's on the other enriches the kept singular vectors V: the new cores
+ * are the orthonormal rows spanning [V^T; e / s] and z's projection / s
+ * (Jacobi SVD; directions whose discarded singular values have 2-norm
+ * <= 1e-10 are left out, s = ||projected b|| + ||projected W x||), so a
+ * bond of x holds up to (truncated rank + z's rank) vectors and no
+ * direction in which the residual vanishes (where the frames of x and z
+ * overlap near the chain ends a QR would add arbitrary ones; z's end cores
+ * are the projections themselves).  x and z are orthogonalised from the
+ * left first; each of nsweeps sweeps runs right to left and back.  x's and
+ * z's cores are caller-owned with the capacity of qtt_solve_amen_query's
+ * bounds (a max_rank keeps x's small); x->ranks and z->ranks are
+ * rewritten.  Limits: local systems of at most 4096 unknowns, split rows of
+ * at most 1024.  A zero b gives zero trains (all ranks 1) at once.
+ * info (nullable): norm = ||x||, jacobi_sweeps_max.  Synchronous. */
+int qtt_solve_amen(qtt_handle h, const qtt_tt *w, const qtt_tt *b, qtt_tt *x, qtt_tt *z, int32_t nsweeps,
+                   double rel_tol, int64_t max_rank, qtt_round_info *info, void *ws, size_t ws_bytes, void *stream);
+/* Rank capacities of x and z (n+1 entries each, nullable) and workspace
+ * (bytes) of qtt_solve_amen; pure shape arithmetic. */
+int qtt_solve_amen_query(const qtt_tt *w, const qtt_tt *b, const qtt_tt *x, const qtt_tt *z, int64_t max_rank,
+                         int64_t *x_bounds, int64_t *z_bounds, size_t *bytes);
+
 /* Rank capacity per bond of qtt_fit2's result (bounds, n+1 entries, nullable:
  * the guess's rank or the largest rank a split can give, whichever is
  * larger) and its device workspace (bytes); pure shape arithmetic. */

@@ -1479,7 +1479,9 @@ int make_fit2_plan(const Shape& s, const qtt_tt* c, long max_rank, Fit2Plan& F) 
 
 // Truncated SVD of M (p0 x L, row-major; overwritten by its Householder QR
 // when tall): vt (rn x L, ld L) the kept right singular vectors as rows,
-// mv (p0 x rn, ld rn) = M V_r = U_r Sigma_r.  Reads the decision back.
+// mv (p0 x rn, ld rn) = M V_r = U_r Sigma_r.  The rank rule's threshold is
+// rel_tol * ||M||_F / sqrt(nb), or rel_tol * (*norm_override) / sqrt(nb)
+// with a device scalar given.  Reads the decision back.
 // Device buffers of a truncated split (see split_rows).
 struct SplitBufs {
   double *TB, *X, *Xc, *Yt, *sig, *nrm, *scr;
@@ -1506,7 +1508,8 @@ SplitBufs fit2_bufs(double* ws, const Fit2Plan& F) {
 }
 
 int split_rows(qtt_context* h, hipStream_t st, const SplitBufs& bf, double* M, int p0, int L, double rel_tol, int nb,
-               long max_rank, double* vt, double* mv, int& rn, double& tail, int& swp) {
+               long max_rank, double* vt, double* mv, int& rn, double& tail, int& swp,
+               const double* norm_override = nullptr) {
   double* TB = bf.TB;
   double* X = bf.X;
   double* Xc = bf.Xc;
@@ -1530,8 +1533,9 @@ int split_rows(qtt_context* h, hipStream_t st, const SplitBufs& bf, double* M, i
   QTT_HIP(permute_rows(st, Xc, p, L, perm, X));
   QTT_HIP(jacobi_rows(st, X, p, L, ctr, h->max_sweeps, sweeps, sig));  // sig[0]: largest row norm
   QTT_HIP(row_norms_sorted(st, X, p, L, sig, perm));
-  QTT_HIP(frob_norm(st, sig, p, nrm));  // ||S||_F of the super-core being split
-  QTT_HIP(truncate_decide(st, sig, p, nrm, rel_tol, nb, max_rank, tr));
+  // the threshold's scale: ||S||_F of the matrix being split, or a given one
+  if (!norm_override) QTT_HIP(frob_norm(st, sig, p, nrm));
+  QTT_HIP(truncate_decide(st, sig, p, norm_override ? norm_override : nrm, rel_tol, nb, max_rank, tr));
   QTT_HIP(hipMemcpyAsync(h->pin_int, sweeps, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   int e = readback(h, st, tr, sizeof(TruncOut), h->pin_trunc);
   if (e) return e;
@@ -1963,6 +1967,383 @@ int solve_sweeps(qtt_context* h, hipStream_t st, double* ws, const SolvePlan& F,
     }
   }
   QTT_HIP(frob_norm(st, core(n - 1), rc[n - 1] * d[n - 1], ws + F.offNrm));
+  return QTT_OK;
+}
+
+// ---------------------------------------------------------------- AMEn solver
+// AMEn (Sec. 5, single-core sweeps with gradient enrichment): the one-core
+// energy minimisation of the DMRG-like solver, then per step a truncated SVD
+// of the solved core, the projection of the residual r = b - W x onto the
+// frames of a second train z (z's new core) and onto z's frame on the side
+// the sweep moves from and x's frame on the other (the enrichment core e).
+// x's new core is the orthonormal basis of the rows of [V^T; e / s] and z's
+// that of its projection (Jacobi SVD, directions whose discarded singular
+// values have 2-norm <= kAmenSpanTol dropped, s = ||projected b|| +
+// ||projected W x||): the projected residual has exactly null directions
+// where the frames of x and z overlap, and a QR would complete them
+// arbitrarily.  The factor the method absorbs into the next core is not
+// formed: the next local solve replaces that core before anything reads it.
+constexpr double kAmenSpanTol = 1e-10;
+
+struct AmenPlan {
+  SolvePlan S;               // x's environments, the local solve and the splits
+  std::vector<long> bz;      // z's rank bounds
+  std::vector<long> offLzW, offRzW, offLzb, offRzb;
+  long offXt = 0, offZc = 0, offEn = 0, offWx = 0, offU1 = 0, offU2 = 0, offRE = 0, offRz = 0, offScale = 0,
+       offOne = 0;
+  long total = 0;
+};
+
+int amen_check(const qtt_tt* w, const qtt_tt* b, const qtt_tt* x, const qtt_tt* z) {
+  int st = solve_check(w, b, x);
+  if (st) return st;
+  if ((st = check_tt(z, 1))) return st;
+  if (z->dtype != QTT_F64) return QTT_ERR_DTYPE;
+  if (z->n != x->n) return QTT_ERR_SHAPE;
+  for (int k = 0; k < x->n; ++k)
+    if (dphys(z, k) != dphys(x, k)) return QTT_ERR_SHAPE;
+  return QTT_OK;
+}
+
+// Rank bounds: z's ranks never grow past those of its left-orthogonalised
+// guess; a bond of x holds at most the truncated rank (<= max_rank) plus
+// z's rank, never more than the larger of its unfolding sizes (a pass
+// moving right bounds it by the left one, a pass moving left by the right
+// one), and at least what the orthogonalised guess had.
+int make_amen_plan(const qtt_tt* w, const qtt_tt* b, const qtt_tt* x, const qtt_tt* z, long max_rank, AmenPlan& F) {
+  const int n = x->n;
+  SolvePlan& S = F.S;
+  S.nc = 1;
+  S.bnd.assign(n + 1, 1);
+  S.rw.assign(n + 1, 1);
+  S.rb.assign(n + 1, 1);
+  F.bz.assign(n + 1, 1);
+  std::vector<long> left(n + 1, 1), right(n + 1, 1);
+  std::vector<int> d(n);
+  for (int k = 0; k < n; ++k) d[k] = dphys(x, k);
+  for (int k = 1; k <= n; ++k) left[k] = std::min<long>(left[k - 1] * d[k - 1], 1L << 40);
+  for (int k = n - 1; k >= 0; --k) right[k] = std::min<long>(right[k + 1] * d[k], 1L << 40);
+  const long cap = max_rank > 0 ? max_rank : (1L << 40);
+  for (int k = 0; k <= n; ++k) {
+    S.rw[k] = w->ranks[k];
+    S.rb[k] = b->ranks[k];
+    F.bz[k] = std::max(1L, std::min<long>(left[k], z->ranks[k]));
+    const long g = std::min<long>(left[k], x->ranks[k]);
+    long v = (k == 0 || k == n) ? 1 : std::min(std::max(left[k], right[k]), std::max(g, cap + F.bz[k]));
+    S.bnd[k] = std::max(v, 1L);
+  }
+  const std::vector<long>& B = S.bnd;
+  const std::vector<long>& Z = F.bz;
+  long off = 0;
+  auto take = [&](long cnt) {
+    long o = off;
+    off += round_up(std::max(cnt, 1L), 32);
+    return o;
+  };
+  S.offLW.assign(n + 1, 0);
+  S.offRW.assign(n + 1, 0);
+  S.offLb.assign(n + 1, 0);
+  S.offRb.assign(n + 1, 0);
+  F.offLzW.assign(n + 1, 0);
+  F.offRzW.assign(n + 1, 0);
+  F.offLzb.assign(n + 1, 0);
+  F.offRzb.assign(n + 1, 0);
+  for (int k = 0; k <= n; ++k) {
+    S.offLW[k] = take(B[k] * S.rw[k] * B[k]);
+    S.offRW[k] = take(B[k] * S.rw[k] * B[k]);
+    S.offLb[k] = take(B[k] * S.rb[k]);
+    S.offRb[k] = take(B[k] * S.rb[k]);
+    F.offLzW[k] = take(Z[k] * S.rw[k] * B[k]);
+    F.offRzW[k] = take(Z[k] * S.rw[k] * B[k]);
+    F.offLzb[k] = take(Z[k] * S.rb[k]);
+    F.offRzb[k] = take(Z[k] * S.rb[k]);
+  }
+  long maxN = 1, maxT = 1, maxE = 1, maxU = 1, maxSplit = 1, maxTB = 1, maxX = 1, maxP = 1, maxc = 1;
+  long maxXt = 1, maxZc = 1, maxRE = 1;
+  // one Jacobi split of a p0 x L row matrix (its buffers)
+  auto split_need = [&](long p0, long L) -> int {
+    if (L > 1024 || p0 > kMaxRows) return QTT_ERR_UNSUPPORTED;
+    const long p = std::min(p0, L);
+    maxSplit = std::max(maxSplit, p0 * L);
+    maxTB = std::max(maxTB, qr_t_doubles((int)p0, (int)p));
+    maxX = std::max(maxX, p * L);
+    maxP = std::max(maxP, p);
+    maxc = std::max({maxc, L, p0});
+    return QTT_OK;
+  };
+  for (int k = 0; k < n; ++k) {
+    const long r0 = B[k], r1 = B[k + 1], z0 = Z[k], z1 = Z[k + 1], w0 = S.rw[k], w1 = S.rw[k + 1], dk = d[k];
+    const long N = r0 * dk * r1;
+    maxN = std::max(maxN, N);
+    maxXt = std::max(maxXt, N);
+    maxT = std::max(maxT, std::max(r0, z0) * dk * std::max({S.rb[k + 1], r1, z1}));
+    // three-layer steps (bra x or z, ket x) and the residual projections
+    maxE = std::max({maxE, std::max(r0, z0) * w0 * dk * r1, std::max(r0, z0) * dk * w1 * r1});
+    maxU = std::max({maxU, r0 * dk * std::max(r1, z1) * w1, dk * std::max(r1, z1) * w0 * r0});
+    maxZc = std::max({maxZc, z0 * dk * z1, z0 * dk * r1, r0 * dk * z1});
+    int e;
+    const long mL = dk * r1, mR = r0 * dk;
+    if (k > 0) {  // moving left: truncation (r0) x (d r1), bases [V; e] (<= r0 + z0 rows) and z (z0 rows)
+      const long cL = std::min(r0, mL) + z0;
+      if ((e = split_need(r0, mL)) || (e = split_need(cL, mL)) || (e = split_need(z0, dk * z1))) return e;
+      maxRE = std::max(maxRE, cL * mL);
+    }
+    if (k < n - 1) {  // moving right: the transposed forms, (r1) x (r0 d), [U, e]^T, z^T
+      const long cR = std::min(r1, mR) + z1;
+      if ((e = split_need(r1, mR)) || (e = split_need(cR, mR)) || (e = split_need(z1, z0 * dk))) return e;
+      maxRE = std::max(maxRE, cR * mR);
+    }
+  }
+  if (maxN > kMaxRows) return QTT_ERR_UNSUPPORTED;  // the local QR solve
+  maxE = std::max(maxE, maxU);  // right steps with z as bra use the same buffers
+  S.offA = take(maxN * maxN);
+  S.offRhs = take(maxN);
+  S.offT = take(maxT);
+  S.offE1 = take(maxE);
+  S.offE2 = take(maxE);
+  S.offLTB = take(qr_t_doubles((int)maxN, (int)maxN));
+  S.offLScr = take(qr_scratch_doubles(maxN));
+  S.offS = take(maxSplit);
+  S.offSt = take(maxSplit);
+  S.offV = take(maxX);
+  S.offMV = take(maxSplit);
+  S.offTB = take(maxTB);
+  S.offX = take(maxX);
+  S.offXc = take(maxX);
+  S.offYt = take(maxX);
+  S.offSig = take(maxP);
+  S.offPerm = take(maxP / 2 + 1);
+  S.offTrunc = take(8);
+  S.offCtr = take(96);
+  S.offSweeps = take(1);
+  S.offNrm = take(1);
+  S.offScr = take(qr_scratch_doubles(maxc));
+  F.offXt = take(maxXt);
+  F.offZc = take(maxZc);
+  F.offEn = take(maxZc);
+  F.offWx = take(maxZc);
+  F.offU1 = take(maxU);
+  F.offU2 = take(maxU);
+  F.offRE = take(maxRE);
+  F.offRz = take(maxZc);
+  F.offScale = take(4);
+  F.offOne = take(1);
+  F.total = S.total = off;
+  return QTT_OK;
+}
+
+// Three-layer environment steps with bra u (ranks ru0, ru1) and ket v
+// (rv0, rv1): LW' = sum u^T LW W v (left, LW: ru0 x w0 x rv0) and
+// RW = sum u W v RW' (right, RW': ru1 x w1 x rv1).
+hipError_t env3_left_bk(hipStream_t st, const double* LW, const double* u, const double* v, const double* W, long ru0,
+                        long ru1, long rv0, long rv1, long d, long w0, long w1, double* T1, double* T2, double* out) {
+  hipError_t e = gemm_f64(st, false, false, (int)(ru0 * w0), (int)(d * rv1), (int)rv0, 1.0, LW, rv0, 0, v, d * rv1,
+                          0, 0.0, T1, d * rv1, 0, 1);
+  if (e != hipSuccess) return e;
+  if ((e = env3_left_mid(st, T1, W, (int)ru0, (int)w0, (int)d, (int)w1, (int)rv1, T2)) != hipSuccess) return e;
+  return gemm_f64(st, true, false, (int)ru1, (int)(w1 * rv1), (int)(ru0 * d), 1.0, u, ru1, 0, T2, w1 * rv1, 0, 0.0,
+                  out, w1 * rv1, 0, 1);
+}
+
+hipError_t env3_right_bk(hipStream_t st, const double* RW, const double* u, const double* v, const double* W, long ru0,
+                         long ru1, long rv0, long rv1, long d, long w0, long w1, double* U1, double* U2, double* out) {
+  hipError_t e = gemm_f64(st, false, true, (int)(rv0 * d), (int)(ru1 * w1), (int)rv1, 1.0, v, rv1, 0, RW, rv1, 0,
+                          0.0, U1, ru1 * w1, 0, 1);
+  if (e != hipSuccess) return e;
+  if ((e = env3_right_mid(st, U1, W, (int)rv0, (int)w0, (int)d, (int)w1, (int)ru1, U2)) != hipSuccess) return e;
+  return gemm_f64(st, false, false, (int)ru0, (int)(w0 * rv0), (int)(d * ru1), 1.0, u, d * ru1, 0, U2, w0 * rv0, 0,
+                  0.0, out, w0 * rv0, 0, 1);
+}
+
+// out[a][i][c] = (Lb b_q Rb^T)[a][i][c] - sum LW[a][al][x] W[al][i][j][be] v[x][j][y] RW[c][be][y]:
+// the projection of b - W x onto a left frame (ra0 columns, environments
+// LW, Lb) and a right frame (rc1 rows, environments RW, Rb), x's core q = v
+// (rv0 x d x rv1); norms[0], norms[1] (device) receive the Frobenius norms
+// of the two terms.  wx: scratch of ra0 d rc1.
+hipError_t residual_project(hipStream_t st, const double* LW, const double* RW, const double* Lb, const double* Rb,
+                            const double* W, const double* bq, const double* v, long ra0, long rc1, long rv0,
+                            long rv1, long rb0, long rb1, long d, long w0, long w1, double* T, double* U1,
+                            double* U2, double* wx, double* out, double* norms) {
+  hipError_t e = fit_project(st, Lb, bq, Rb, ra0, rc1, rb0, rb1, d, T, out);
+  if (e != hipSuccess) return e;
+  if ((e = gemm_f64(st, false, true, (int)(rv0 * d), (int)(rc1 * w1), (int)rv1, 1.0, v, rv1, 0, RW, rv1, 0, 0.0, U1,
+                    rc1 * w1, 0, 1)) != hipSuccess)
+    return e;
+  if ((e = env3_right_mid(st, U1, W, (int)rv0, (int)w0, (int)d, (int)w1, (int)rc1, U2)) != hipSuccess) return e;
+  if ((e = gemm_f64(st, false, true, (int)ra0, (int)(d * rc1), (int)(w0 * rv0), 1.0, LW, w0 * rv0, 0, U2, w0 * rv0,
+                    0, 0.0, wx, d * rc1, 0, 1)) != hipSuccess)
+    return e;
+  const long cnt = ra0 * d * rc1;
+  if ((e = frob_norm(st, out, cnt, norms)) != hipSuccess) return e;
+  if ((e = frob_norm(st, wx, cnt, norms + 1)) != hipSuccess) return e;
+  return axpy_f64(st, cnt, -1.0, wx, out);
+}
+
+int amen_sweeps(qtt_context* h, hipStream_t st, double* ws, const AmenPlan& F, const qtt_tt* w, const qtt_tt* b,
+                qtt_tt* x, qtt_tt* z, std::vector<long>& rc, std::vector<long>& rz, int nsweeps, double rel_tol,
+                long max_rank, int& maxsw) {
+  const SolvePlan& S = F.S;
+  const int n = x->n;
+  std::vector<int> d(n);
+  for (int k = 0; k < n; ++k) d[k] = dphys(x, k);
+  auto X = [&](int k) { return (double*)x->cores[k]; };
+  auto Zc = [&](int k) { return (double*)z->cores[k]; };
+  auto W = [&](int k) { return (const double*)w->cores[k]; };
+  auto B = [&](int k) { return (const double*)b->cores[k]; };
+  double* E1 = ws + S.offE1;
+  double* E2 = ws + S.offE2;
+  double* T = ws + S.offT;
+  double* sol = ws + S.offRhs;
+  double* xt = ws + F.offXt;
+  double* zc = ws + F.offZc;
+  double* en = ws + F.offEn;
+  double* RE = ws + F.offRE;
+  double* Rz = ws + F.offRz;
+  double* U1 = ws + F.offU1;
+  double* U2 = ws + F.offU2;
+  double* sc = ws + F.offScale;  // [0..1] scale terms of e, [2..3] of z's projection
+  const double* one = ws + F.offOne;
+  double* Sm = ws + S.offS;
+  double* St = ws + S.offSt;
+  double* V = ws + S.offV;
+  double* MV = ws + S.offMV;
+  const SplitBufs bf = solve_bufs(ws, S);
+  const long* rw = S.rw.data();
+  const long* rb = S.rb.data();
+  // environments of x (bra = ket = x) and of z against x and b, one core on
+  auto left_step = [&](int k) -> int {
+    QTT_HIP(env3_left_bk(st, ws + S.offLW[k], X(k), X(k), W(k), rc[k], rc[k + 1], rc[k], rc[k + 1], d[k], rw[k],
+                         rw[k + 1], E1, E2, ws + S.offLW[k + 1]));
+    QTT_HIP(env_step_left<double>(st, ws + S.offLb[k], X(k), B(k), rc[k], rc[k + 1], rb[k], rb[k + 1], d[k], T,
+                                  ws + S.offLb[k + 1]));
+    QTT_HIP(env3_left_bk(st, ws + F.offLzW[k], Zc(k), X(k), W(k), rz[k], rz[k + 1], rc[k], rc[k + 1], d[k], rw[k],
+                         rw[k + 1], E1, E2, ws + F.offLzW[k + 1]));
+    QTT_HIP(env_step_left<double>(st, ws + F.offLzb[k], Zc(k), B(k), rz[k], rz[k + 1], rb[k], rb[k + 1], d[k], T,
+                                  ws + F.offLzb[k + 1]));
+    return QTT_OK;
+  };
+  auto right_step = [&](int k) -> int {
+    QTT_HIP(env3_right_bk(st, ws + S.offRW[k + 1], X(k), X(k), W(k), rc[k], rc[k + 1], rc[k], rc[k + 1], d[k], rw[k],
+                          rw[k + 1], E1, E2, ws + S.offRW[k]));
+    QTT_HIP(env_step_right<double>(st, ws + S.offRb[k + 1], X(k), B(k), rc[k], rc[k + 1], rb[k], rb[k + 1], d[k], T,
+                                   ws + S.offRb[k]));
+    QTT_HIP(env3_right_bk(st, ws + F.offRzW[k + 1], Zc(k), X(k), W(k), rz[k], rz[k + 1], rc[k], rc[k + 1], d[k],
+                          rw[k], rw[k + 1], E1, E2, ws + F.offRzW[k]));
+    QTT_HIP(env_step_right<double>(st, ws + F.offRzb[k + 1], Zc(k), B(k), rz[k], rz[k + 1], rb[k], rb[k + 1], d[k], T,
+                                   ws + F.offRzb[k]));
+    return QTT_OK;
+  };
+  // projection of the residual with x's core q = v onto the frames given by
+  // their environments (left: z or x, right: z or x); norms: its two terms
+  auto project = [&](int q, bool zleft, bool zright, const double* v, double* out, double* norms) -> int {
+    const long ra0 = zleft ? rz[q] : rc[q], rc1 = zright ? rz[q + 1] : rc[q + 1];
+    QTT_HIP(residual_project(st, ws + (zleft ? F.offLzW[q] : S.offLW[q]),
+                             ws + (zright ? F.offRzW[q + 1] : S.offRW[q + 1]), ws + (zleft ? F.offLzb[q] : S.offLb[q]),
+                             ws + (zright ? F.offRzb[q + 1] : S.offRb[q + 1]), W(q), B(q), v, ra0, rc1, rc[q],
+                             rc[q + 1], rb[q], rb[q + 1], d[q], rw[q], rw[q + 1], T, U1, U2, ws + F.offWx, out,
+                             norms));
+    return QTT_OK;
+  };
+  // orthonormal rows spanning the rows of M (p0 x L, overwritten): Jacobi
+  // SVD, directions with discarded tail <= kAmenSpanTol dropped -> V (k x L)
+  auto span_rows = [&](double* M, int p0, int L, int& k) -> int {
+    int swp = 0;
+    double tail = 0.0;
+    int e = split_rows(h, st, bf, M, p0, L, kAmenSpanTol, 1, 0, V, MV, k, tail, swp, one);
+    maxsw = std::max(maxsw, swp);
+    return e;
+  };
+  QTT_HIP(fill_f64(st, ws + F.offOne, 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + S.offLW[0], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + S.offLb[0], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + F.offLzW[0], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + F.offLzb[0], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + S.offRW[n], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + S.offRb[n], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + F.offRzW[n], 1.0, 1));
+  QTT_HIP(fill_f64(st, ws + F.offRzb[n], 1.0, 1));
+  int e;
+  for (int k = 0; k + 1 < n; ++k)
+    if ((e = left_step(k))) return e;
+  maxsw = 0;
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    for (int q = n - 1; q >= 0; --q) {  // right to left
+      if ((e = solve_local(st, ws, S, w, b, rc, d, q))) return e;
+      const long r0 = rc[q], r1 = rc[q + 1], m = d[q] * r1;
+      if (q == 0) {
+        QTT_HIP(copy_pad_rows(st, sol, 1, (int)m, m, X(0), 1, m));
+        if ((e = project(0, true, true, sol, Zc(0), sc + 2))) return e;
+        break;
+      }
+      // truncated split of the (r0) x (d r1) unfolding: V (rn x m) rows, MV = U S (r0 x rn)
+      QTT_HIP(copy_pad_rows(st, sol, (int)r0, (int)m, m, Sm, (int)r0, m));
+      int rn = 0, swp = 0;
+      double tail = 0.0;
+      if ((e = split_rows(h, st, bf, Sm, (int)r0, (int)m, rel_tol, n - 1, max_rank, V, MV, rn, tail, swp))) return e;
+      maxsw = std::max(maxsw, swp);
+      QTT_HIP(gemm_f64(st, false, false, (int)r0, (int)m, rn, 1.0, MV, rn, 0, V, m, 0, 0.0, xt, m, 0, 1));
+      const long z0 = rz[q], z1 = rz[q + 1];
+      if ((e = project(q, true, true, xt, zc, sc + 2))) return e;  // z's projection (z0 x d x z1)
+      if ((e = project(q, true, false, xt, en, sc))) return e;     // enrichment (z0 x d x r1)
+      // x's core: orthonormal rows spanning [V; en / s] ((rn + z0) x m)
+      const int c = rn + (int)z0;
+      QTT_HIP(copy_pad_rows(st, V, rn, (int)m, m, RE, rn, m));
+      QTT_HIP(copy_scaled_inv(st, en, (int)z0, (int)m, m, sc, RE + (long)rn * m, m));
+      int qq = 0;
+      if ((e = span_rows(RE, c, (int)m, qq))) return e;
+      if (qq > S.bnd[q]) return QTT_ERR_UNSUPPORTED;
+      QTT_HIP(copy_pad_rows(st, V, qq, (int)m, m, X(q), qq, m));
+      // z's core: orthonormal rows spanning its projection / s (z0 x d z1)
+      const int mz = (int)(d[q] * z1);
+      QTT_HIP(copy_scaled_inv(st, zc, (int)z0, mz, mz, sc + 2, Rz, mz));
+      int qz = 0;
+      if ((e = span_rows(Rz, (int)z0, mz, qz))) return e;
+      QTT_HIP(copy_pad_rows(st, V, qz, mz, mz, Zc(q), qz, mz));
+      rc[q] = qq;
+      rz[q] = qz;
+      if ((e = right_step(q))) return e;
+    }
+    for (int q = 0; q < n; ++q) {  // and back
+      if ((e = solve_local(st, ws, S, w, b, rc, d, q))) return e;
+      const long r0 = rc[q], r1 = rc[q + 1], m = r0 * d[q];
+      if (q == n - 1) {
+        QTT_HIP(copy_pad_rows(st, sol, (int)m, 1, 1, X(q), (int)m, 1));
+        if ((e = project(q, true, true, sol, Zc(q), sc + 2))) return e;
+        break;
+      }
+      // truncated split of the (r0 d) x r1 unfolding through its transpose:
+      // V (rn x m) = U^T, MV (r1 x rn) = V S
+      QTT_HIP(transpose(st, sol, (int)m, (int)r1, r1, St, m));
+      int rn = 0, swp = 0;
+      double tail = 0.0;
+      if ((e = split_rows(h, st, bf, St, (int)r1, (int)m, rel_tol, n - 1, max_rank, V, MV, rn, tail, swp))) return e;
+      maxsw = std::max(maxsw, swp);
+      QTT_HIP(gemm_f64(st, true, true, (int)m, (int)r1, rn, 1.0, V, m, 0, MV, rn, 0, 0.0, xt, r1, 0, 1));
+      const long z0 = rz[q], z1 = rz[q + 1];
+      if ((e = project(q, true, true, xt, zc, sc + 2))) return e;  // z's projection (z0 x d x z1)
+      if ((e = project(q, false, true, xt, en, sc))) return e;     // enrichment (r0 x d x z1)
+      // x's core: orthonormal columns spanning [U, en / s] (m x (rn + z1)), as rows
+      const int c = rn + (int)z1;
+      QTT_HIP(copy_pad_rows(st, V, rn, (int)m, m, RE, rn, m));
+      QTT_HIP(transpose(st, en, (int)m, (int)z1, z1, RE + (long)rn * m, m));
+      QTT_HIP(copy_scaled_inv(st, RE + (long)rn * m, (int)z1, (int)m, m, sc, RE + (long)rn * m, m));
+      int qq = 0;
+      if ((e = span_rows(RE, c, (int)m, qq))) return e;
+      if (qq > S.bnd[q + 1]) return QTT_ERR_UNSUPPORTED;
+      QTT_HIP(transpose(st, V, qq, (int)m, m, X(q), qq));
+      // z's core: orthonormal columns spanning its projection / s ((z0 d) x z1)
+      const int mz = (int)(z0 * d[q]);
+      QTT_HIP(transpose(st, zc, mz, (int)z1, z1, Rz, mz));
+      QTT_HIP(copy_scaled_inv(st, Rz, (int)z1, mz, mz, sc + 2, Rz, mz));
+      int qz = 0;
+      if ((e = span_rows(Rz, (int)z1, mz, qz))) return e;
+      QTT_HIP(transpose(st, V, qz, mz, mz, Zc(q), qz));
+      rc[q + 1] = qq;
+      rz[q + 1] = qz;
+      if ((e = left_step(q))) return e;
+    }
+  }
+  QTT_HIP(frob_norm(st, X(n - 1), rc[n - 1] * d[n - 1], ws + S.offNrm));
   return QTT_OK;
 }
 
@@ -2909,6 +3290,87 @@ int qtt_fit2(qtt_handle h, const char* spec, const qtt_tt* a, const qtt_tt* b, q
     info->jacobi_sweeps_max = maxsw;
   }
   for (int k = 0; k <= n; ++k) c->ranks[k] = rc[k];
+  return QTT_OK;
+}
+
+int qtt_solve_amen_query(const qtt_tt* w, const qtt_tt* b, const qtt_tt* x, const qtt_tt* z, int64_t max_rank,
+                         int64_t* x_bounds, int64_t* z_bounds, size_t* bytes) {
+  if (!bytes) return QTT_ERR_ARG;
+  int st = amen_check(w, b, x, z);
+  if (st) return st;
+  AmenPlan F;
+  if ((st = make_amen_plan(w, b, x, z, max_rank, F))) return st;
+  Shape sx, sz;
+  shape_from_tt(x, sx);
+  shape_from_tt(z, sz);
+  Plan Px, Pz;
+  if ((st = make_plan(sx, 0, Px, false)) || (st = make_plan(sz, 0, Pz, false))) return st;
+  *bytes = std::max({ws_bytes_of(Px), ws_bytes_of(Pz), (size_t)F.total * sizeof(double) + 256,
+                     (size_t)inner_plan(b, b).total * sizeof(double) + 256});
+  for (int k = 0; k <= x->n; ++k) {
+    if (x_bounds) x_bounds[k] = F.S.bnd[k];
+    if (z_bounds) z_bounds[k] = F.bz[k];
+  }
+  return QTT_OK;
+}
+
+int qtt_solve_amen(qtt_handle h, const qtt_tt* w, const qtt_tt* b, qtt_tt* x, qtt_tt* z, int32_t nsweeps,
+                   double rel_tol, int64_t max_rank, qtt_round_info* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return QTT_ERR_ARG;
+  if (nsweeps < 0 || !(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return QTT_ERR_ARG;
+  size_t need = 0;
+  int st = qtt_solve_amen_query(w, b, x, z, max_rank, nullptr, nullptr, &need);
+  if (st) return st;
+  if (!ws || ws_bytes < need) return QTT_ERR_WORKSPACE;
+  AmenPlan F;
+  if ((st = make_amen_plan(w, b, x, z, max_rank, F))) return st;
+  const int n = x->n;
+  hipStream_t strm = (hipStream_t)stream;
+  {
+    // b = 0: x and the residual train are the zero train (rank 1); the
+    // truncated splits would normalise zero rows
+    double bb = 0.0;
+    if ((st = inner_impl<double>(h, b, b, &bb, ws, strm))) return st;
+    if (!std::isfinite(bb)) return QTT_ERR_NONFINITE;
+    if (bb == 0.0) {
+      Scoped sc(h->device);
+      for (int k = 0; k < n; ++k) {
+        QTT_HIP(fill_f64(strm, (double*)x->cores[k], 0.0, dphys(x, k)));
+        QTT_HIP(fill_f64(strm, (double*)z->cores[k], 0.0, dphys(z, k)));
+      }
+      QTT_HIP(hipStreamSynchronize(strm));
+      for (int k = 0; k <= n; ++k) x->ranks[k] = z->ranks[k] = 1;
+      if (info) {
+        info->norm = 0.0;
+        info->jacobi_sweeps_max = 0;
+      }
+      return QTT_OK;
+    }
+  }
+  // the guess and the residual train, orthogonalised from the left (ranks may shrink)
+  double nrm = 0.0;
+  if ((st = qtt_orthogonalize(h, x, &nrm, ws, ws_bytes, stream))) return st;
+  if ((st = qtt_orthogonalize(h, z, &nrm, ws, ws_bytes, stream))) return st;
+  Scoped sc(h->device);
+  double* wsa = align_ws(ws);
+  std::vector<long> rc(n + 1), rz(n + 1);
+  for (int k = 0; k <= n; ++k) {
+    rc[k] = x->ranks[k];
+    rz[k] = z->ranks[k];
+  }
+  int maxsw = 0;
+  if ((st = amen_sweeps(h, strm, wsa, F, w, b, x, z, rc, rz, nsweeps, rel_tol, max_rank, maxsw))) return st;
+  int e = readback(h, strm, wsa + F.S.offNrm, sizeof(double), h->pin_dbl);
+  if (e) return e;
+  if (!std::isfinite(h->pin_dbl[0])) return QTT_ERR_NONFINITE;
+  if (info) {
+    info->norm = h->pin_dbl[0];
+    info->jacobi_sweeps_max = maxsw;
+  }
+  for (int k = 0; k <= n; ++k) {
+    x->ranks[k] = rc[k];
+    z->ranks[k] = rz[k];
+  }
   return QTT_OK;
 }
 

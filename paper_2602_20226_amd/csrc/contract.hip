@@ -181,6 +181,23 @@ __global__ void k_transpose(const double* __restrict__ A, int rows, int cols, lo
 }
 
 // Frobenius norm of a vector; one workgroup, deterministic order.
+// y += alpha x
+__global__ void k_axpy(long n, double alpha, const double* __restrict__ x, double* __restrict__ y) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    y[e] += alpha * x[e];
+}
+// dst = src / (s2[0] + s2[1]) (a copy when the sum is zero); dst may be src.
+__global__ void k_copy_scaled_inv(const double* src, int rows, int cols, long lds, const double* __restrict__ s2,
+                                  double* dst, long ldd) {
+  const double s = s2[0] + s2[1];
+  const double f = s > 0.0 ? 1.0 / s : 1.0;
+  const long n = (long)rows * cols;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const long r = e / cols;
+    const int c = (int)(e % cols);
+    dst[r * ldd + c] = src[r * lds + c] * f;
+  }
+}
 __global__ __launch_bounds__(1024) void k_frob(const double* __restrict__ x, long n, double* out) {
   __shared__ double red[16];
   double s = 0.0;
@@ -371,6 +388,18 @@ hipError_t transpose(hipStream_t s, const double* A, int rows, int cols, long ld
 }
 hipError_t frob_norm(hipStream_t s, const double* x, long n, double* out) {
   hipLaunchKernelGGL(k_frob, dim3(1), dim3(1024), 0, s, x, n, out);
+  return hipGetLastError();
+}
+hipError_t axpy_f64(hipStream_t s, long n, double alpha, const double* x, double* y) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, n, alpha, x, y);
+  return hipGetLastError();
+}
+hipError_t copy_scaled_inv(hipStream_t s, const double* src, int rows, int cols, long lds, const double* s2,
+                           double* dst, long ldd) {
+  const long n = (long)rows * cols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_scaled_inv, dim3(grid_for(n)), dim3(256), 0, s, src, rows, cols, lds, s2, dst, ldd);
   return hipGetLastError();
 }
 

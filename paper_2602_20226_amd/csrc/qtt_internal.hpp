@@ -110,6 +110,12 @@ hipError_t set_eye_rect(hipStream_t s, double* Z, int m, int q);
 hipError_t copy_pad_rows(hipStream_t s, const double* src, int rows, int cols, long lds,
                          double* dst, int rows_out, long ldd);
 hipError_t frob_norm(hipStream_t s, const double* x, long n, double* out);
+// y += alpha x (n entries).
+hipError_t axpy_f64(hipStream_t s, long n, double alpha, const double* x, double* y);
+// dst = src / (s2[0] + s2[1]) with s2 on the device (a plain copy when the sum
+// is zero); rows x cols, leading dimensions lds / ldd; dst may equal src.
+hipError_t copy_scaled_inv(hipStream_t s, const double* src, int rows, int cols, long lds, const double* s2,
+                           double* dst, long ldd);
 hipError_t transpose(hipStream_t s, const double* A, int rows, int cols, long lda, double* B, long ldb);
 
 struct TruncOut {

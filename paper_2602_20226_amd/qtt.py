@@ -40,7 +40,7 @@ EXPORTS = [
     "qtt_batch_plan_destroy", "qtt_contract_zipup", "qtt_zipup_query", "qtt_add",
     "qtt_fit", "qtt_fit_workspace_size", "qtt_set_jacobi_max_sweeps", "qtt_contract_round_noalloc",
     "qtt_inner_prec", "qtt_batch_plan_tiles", "qtt_contract_round_async", "qtt_fit2", "qtt_fit2_query",
-    "qtt_solve", "qtt_solve_query",
+    "qtt_solve", "qtt_solve_query", "qtt_solve_amen", "qtt_solve_amen_query",
 ]
 # size of the fixed device array behind qtt_contract_round_noalloc
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -130,6 +130,10 @@ def load_library():
     L.qtt_solve.argtypes = [vp, P(TT), P(TT), P(TT), C.c_int32, C.c_int32, C.c_double, C.c_int64, P(RoundInfoC),
                             vp, C.c_size_t, vp]
     L.qtt_solve_query.argtypes = [P(TT), P(TT), P(TT), C.c_int32, C.c_int64, P(C.c_int64), P(C.c_size_t)]
+    L.qtt_solve_amen.argtypes = [vp, P(TT), P(TT), P(TT), P(TT), C.c_int32, C.c_double, C.c_int64,
+                                 P(RoundInfoC), vp, C.c_size_t, vp]
+    L.qtt_solve_amen_query.argtypes = [P(TT), P(TT), P(TT), P(TT), C.c_int64, P(C.c_int64), P(C.c_int64),
+                                       P(C.c_size_t)]
     L.qtt_fit2_query.argtypes = [C.c_char_p, P(TT), P(TT), P(TT), C.c_int64, P(C.c_int64), P(C.c_size_t)]
     L.qtt_add.argtypes = [vp, C.c_int32, P(TT), P(C.c_double), P(TT), vp]
     L.qtt_zipup_query.argtypes = [C.c_char_p, P(TT), P(TT), C.c_int64, C.c_int32, P(C.c_int64), P(C.c_size_t)]
@@ -689,6 +693,48 @@ def solve(w, b, guess, nsweeps: int = 1, ncores: int = 1, rel_tol: float = 0.0, 
                        workspace.numel(), _stream_ptr()), "qtt_solve")
     ranks = vx.ranks()
     return _views_of_compact(bufs, ranks, d), ranks, info.c.norm
+
+
+def solve_amen(w, b, guess, residual_guess, nsweeps: int = 1, rel_tol: float = 0.0, max_rank: int = 0,
+               workspace: Optional[torch.Tensor] = None):
+    """AMEn solution of w x = b (qtt_solve_amen) starting from copies of
+    `guess` and of `residual_guess` (the initial residual train z).
+    Returns (x cores, x ranks, z cores, z ranks, norm)."""
+    L = load_library()
+    h = handle(b[0].device.index)
+    vw, vb = TTView(list(w), 2), TTView(list(b), 1)
+    n = len(guess)
+    d = [g.shape[1] for g in guess]
+    rx_in = [guess[0].shape[0]] + [g.shape[-1] for g in guess]
+    rz_in = [residual_guess[0].shape[0]] + [g.shape[-1] for g in residual_guess]
+    px = TTView([g.detach().reshape(-1) for g in guess], 1, ranks_override=rx_in, phys_override=d)
+    pz = TTView([g.detach().reshape(-1) for g in residual_guess], 1, ranks_override=rz_in, phys_override=d)
+    bx, bz = (C.c_int64 * (n + 1))(), (C.c_int64 * (n + 1))()
+    nb = C.c_size_t()
+    _check(L.qtt_solve_amen_query(C.byref(vw.struct), C.byref(vb.struct), C.byref(px.struct), C.byref(pz.struct),
+                                  int(max_rank), bx, bz, C.byref(nb)), "qtt_solve_amen_query")
+    dev = b[0].device
+
+    def buffers(cores, bounds):
+        out = []
+        for k, g in enumerate(cores):
+            buf = torch.zeros(max(bounds[k] * d[k] * bounds[k + 1], g.numel()), dtype=torch.float64, device=dev)
+            buf[: g.numel()] = g.detach().reshape(-1)
+            out.append(buf)
+        return out
+
+    xb = buffers(guess, [int(bx[k]) for k in range(n + 1)])
+    zb = buffers(residual_guess, [int(bz[k]) for k in range(n + 1)])
+    vx = TTView(xb, 1, ranks_override=rx_in, phys_override=d)
+    vz = TTView(zb, 1, ranks_override=rz_in, phys_override=d)
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = _workspace(nb.value, dev)
+    info = _Info(n)
+    _check(L.qtt_solve_amen(h.ptr, C.byref(vw.struct), C.byref(vb.struct), C.byref(vx.struct), C.byref(vz.struct),
+                            int(nsweeps), float(rel_tol), int(max_rank), C.byref(info.c),
+                            C.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr()), "qtt_solve_amen")
+    rx, rz = vx.ranks(), vz.ranks()
+    return _views_of_compact(xb, rx, d), rx, _views_of_compact(zb, rz, d), rz, info.c.norm
 
 
 def round_tt(cores, rel_tol: float, max_rank: int = 0, prec: str = "fp64", want_sigmas: bool = False,

@@ -246,4 +246,25 @@ def test_fit2_and_solve_queries_bounds_and_errors():
     bnd24 = (C.c_int64 * 25)()
     assert L.qtt_solve_query(C.byref(W24), C.byref(b24), C.byref(big), 2, 0, bnd24, C.byref(nb)) == -10
     assert L.qtt_solve(None, C.byref(W), C.byref(b), C.byref(x), 1, 1, 0.0, 0, None, None, 0, None) == -1
+    # AMEn: z's bounds are its left-orthogonalised ranks; x's hold the cap
+    # plus z's rank, within the larger unfolding size
+    z = _fake_tt([1, 3, 3, 3, 3, 3, 1], [2] * n)
+    bz = (C.c_int64 * (n + 1))()
+    assert L.qtt_solve_amen_query(C.byref(W), C.byref(b), C.byref(x), C.byref(z), 4, bnd, bz, C.byref(nb)) == 0
+    assert list(bz) == [1, 2, 3, 3, 3, 3, 1]
+    assert list(bnd) == [1, 6, 7, 7, 7, 7, 1] and nb.value > 0
+    assert L.qtt_solve_amen_query(C.byref(W), C.byref(b), C.byref(x), C.byref(z), 0, bnd, None, C.byref(nb)) == 0
+    assert list(bnd) == [1, 32, 16, 8, 16, 32, 1]
+    assert L.qtt_solve_amen_query(C.byref(W), C.byref(b), C.byref(x), C.byref(z), 4, None, None, None) == -1
+    assert L.qtt_solve_amen_query(C.byref(W), C.byref(b), C.byref(x), C.byref(short), 4, bnd, bz,
+                                  C.byref(nb)) == -3
+    z24 = _fake_tt([1] + [4] * 23 + [1], [2] * 24)
+    x24 = _fake_tt([1] + [2] * 23 + [1], [2] * 24)
+    assert L.qtt_solve_amen_query(C.byref(W24), C.byref(b24), C.byref(x24), C.byref(z24), 0, bnd24, None,
+                                  C.byref(nb)) == -10
+    assert L.qtt_solve_amen_query(C.byref(W24), C.byref(b24), C.byref(x24), C.byref(z24), 32, bnd24, None,
+                                  C.byref(nb)) == 0
+    assert max(bnd24) == 36
+    assert L.qtt_solve_amen(None, C.byref(W), C.byref(b), C.byref(x), C.byref(z), 1, 0.0, 0, None, None, 0,
+                            None) == -1
     assert L.qtt_fit2(None, b"ij,j->i", C.byref(W), C.byref(b), C.byref(x), 1, 0.0, 0, None, None, 0, None) == -1
