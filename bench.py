@@ -17,7 +17,9 @@ super-core), whose FLOP are counted under the same conventions for the work
 that algorithm does; `--workload sum4_n42_r128_round` the exact sum of four
 rank-128 trains followed by rounding, and `--workload
 laplacian2d_n32_r64_zipup_fit` a zip-up guess followed by one variational
-sweep (Sec. 3.3).
+sweep (Sec. 3.3); `--workload heat2d_n24_solve` and `heat2d_n24_amen` the
+DMRG-like and AMEn linear solvers (Sec. 5) on an implicit heat step of a 2D
+2^12 x 2^12 grid.
 """
 from __future__ import annotations
 
@@ -174,7 +176,8 @@ def main():
                     help="after the measurement, run one plain device copy of this many MiB")
     ap.add_argument("--workload", default="laplacian3d_n42_r256",
                     choices=["laplacian3d_n42_r256", "laplacian3d_n42_r256_zipup", "hadamard_batch",
-                             "sum4_n42_r128_round", "laplacian2d_n32_r64_zipup_fit", "heat2d_n24_solve"],
+                             "sum4_n42_r128_round", "laplacian2d_n32_r64_zipup_fit", "heat2d_n24_solve",
+                             "heat2d_n24_amen"],
                     help="hadamard_batch: the batched form (512 uneven 1D Hadamard products, one graph launch); "
                          "laplacian3d_n42_r256_zipup: the same product by the decomposition (zip-up) algorithm")
     ap.add_argument("--ncores", type=int, default=2, choices=[1, 2],
@@ -209,6 +212,8 @@ def main():
         return bench_fit(args, I, Q, torch, dev)
     if args.workload == "heat2d_n24_solve":
         return bench_solve(args, I, Q, torch, dev)
+    if args.workload == "heat2d_n24_amen":
+        return bench_amen(args, I, Q, torch, dev)
     zipup = args.workload.endswith("_zipup")
     w = I.laplacian3d_r256()
     A = Q.to_device(w.a, dev)
@@ -692,6 +697,135 @@ def bench_solve(args, I, Q, torch, dev):
                                "cores": threads, "kind": "oracle",
                                "sample": "one sweep of the same solve from the same guess (NumPy FP64, dense local "
                                          "solves); the GPU result of that sweep gives rel_err_vs_oracle",
+                               "seconds": dt}
+    print(json.dumps(out), flush=True)
+
+
+def amen_flops(ranks, zranks, d, rw, rb):
+    """Algorithmic FLOP of one AMEn sweep (two passes) at fixed ranks of x
+    and z: per core and pass the local solve of solve_flops, the nominal
+    SVD of the solved core's unfolding and the product U S V^T, two residual
+    projections (right-hand side part 2 a rb0 d rb1 + 2 a d rb1 c; operator
+    part 2 r0 d c rw1 r1 + 2 d c rw0 r0 d rw1 + 2 a d c rw0 r0, with a x c
+    the frame ranks: z x z and z x x), the nominal SVDs of the enriched
+    basis ((r + rz) x d r) and of z's projection, and the environment steps
+    of x and of z against x and b."""
+    n = len(d)
+    f = 0.0
+    for k in range(n):
+        r0, r1, z0, z1, w0, w1, b0, b1, dk = (ranks[k], ranks[k + 1], zranks[k], zranks[k + 1], rw[k], rw[k + 1],
+                                              rb[k], rb[k + 1], d[k])
+        N = r0 * dk * r1
+        local = 2.0 * N * N * w0 * w1 + geqrf_flops(N, N) + ormqr_flops(N, N, 1) + N * N
+        local += 2.0 * r0 * b0 * dk * b1 + 2.0 * r0 * dk * b1 * r1
+        trunc = svd_nominal_flops(r0, dk * r1) + 2.0 * N * min(r0, dk * r1)
+
+        def proj(a, c):
+            return (2.0 * a * b0 * dk * b1 + 2.0 * a * dk * b1 * c + 2.0 * r0 * dk * c * w1 * r1
+                    + 2.0 * dk * c * w0 * r0 * dk * w1 + 2.0 * a * dk * c * w0 * r0)
+
+        projs = proj(z0, z1) + proj(z0, r1)
+        bases = svd_nominal_flops(min(r0, dk * r1) + z0, dk * r1) + svd_nominal_flops(z0, dk * z1)
+
+        def env3(a):
+            return 2.0 * a * w0 * r0 * dk * r1 + 2.0 * a * dk * w1 * r1 * w0 * dk + 2.0 * r1 * a * dk * w1 * r1
+
+        env = env3(r0) + env3(z0) + 2.0 * (r0 + z0) * b0 * dk * b1 + 2.0 * (r1 + z1) * (r0 + z0) * dk * b1
+        f += 2.0 * (local + trunc + projs + bases + env)
+    return f
+
+
+def bench_amen(args, I, Q, torch, dev):
+    """The AMEn linear solver (Sec. 5) on the implicit heat step of
+    bench_solve ((L + s I) x = b on the 2D 2^12 x 2^12 grid, 24 cores, b of
+    rank 16): from a random rank-4 guess and a rank-4 residual train (seed
+    31), ranks capped at 24 (plus the enrichment), rel_tol 1e-8, two sweeps
+    per step.  A step is one qtt_solve_amen call."""
+    import ctypes as C
+    import numpy as np
+    w = I.residual_grad_2d()
+    m, D, s, nsweeps, cap, tol = 12, 2, 1.0, 2, 24, 1e-8
+    Wc = I.laplacian_mpo(m, D, diag=2.0 + s / D)
+    A = Q.to_device(Wc, dev)
+    rhs = w.extra["rhs"]
+    b = Q.to_device(rhs, dev)
+    rng = np.random.default_rng(31)
+    guess = I.random_mps(m * D, 4, rng)
+    zguess = I.random_mps(m * D, 4, rng)
+    g, zg = Q.to_device(guess, dev), Q.to_device(zguess, dev)
+    n = len(g)
+    d = [c.shape[1] for c in g]
+    L = Q.load_library()
+    h = Q.handle(0)
+    vw, vb = Q.TTView(A, 2), Q.TTView(b, 1)
+    rx_in = [1] + [c.shape[-1] for c in g]
+    rz_in = [1] + [c.shape[-1] for c in zg]
+    px = Q.TTView([c.reshape(-1) for c in g], 1, ranks_override=rx_in, phys_override=d)
+    pz = Q.TTView([c.reshape(-1) for c in zg], 1, ranks_override=rz_in, phys_override=d)
+    bx, bz = (C.c_int64 * (n + 1))(), (C.c_int64 * (n + 1))()
+    nb = C.c_size_t()
+    Q._check(L.qtt_solve_amen_query(C.byref(vw.struct), C.byref(vb.struct), C.byref(px.struct), C.byref(pz.struct),
+                                    cap, bx, bz, C.byref(nb)), "qtt_solve_amen_query")
+    xb = [torch.zeros(int(bx[k]) * d[k] * int(bx[k + 1]), dtype=torch.float64, device=dev) for k in range(n)]
+    zb = [torch.zeros(int(bz[k]) * d[k] * int(bz[k + 1]), dtype=torch.float64, device=dev) for k in range(n)]
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    vx = Q.TTView(xb, 1, ranks_override=rx_in, phys_override=d)
+    vz = Q.TTView(zb, 1, ranks_override=rz_in, phys_override=d)
+    info = Q._Info(n)
+
+    def step(sweeps=nsweeps):
+        for k in range(n):  # restart from the guesses
+            xb[k][: g[k].numel()] = g[k].reshape(-1)
+            zb[k][: zg[k].numel()] = zg[k].reshape(-1)
+        for k in range(n + 1):
+            vx._ranks[k] = rx_in[k]
+            vz._ranks[k] = rz_in[k]
+        Q._check(L.qtt_solve_amen(h.ptr, C.byref(vw.struct), C.byref(vb.struct), C.byref(vx.struct),
+                                  C.byref(vz.struct), sweeps, tol, cap, C.byref(info.c), C.c_void_p(ws.data_ptr()),
+                                  ws.numel(), Q._stream_ptr()), "qtt_solve_amen")
+        return vx.ranks(), vz.ranks()
+
+    # ranks at the start of each sweep (untimed): the orthogonalised guesses, then after one sweep
+    start = [step(0), step(1)]
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ranks, zranks = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    rw = [1] + [c.shape[-1] for c in Wc]
+    rbr = [1] + [c.shape[-1] for c in rhs]
+    flops = sum(amen_flops(rx, rz, d, rw, rbr) for rx, rz in start)
+    out = {
+        "metric": "QTT AMEn linear solve TFLOP/s (implicit heat step, 2D 2^12 x 2^12 grid, rank cap 24 + 4, 2 sweeps)",
+        "value": flops / sec / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "cores": n, "operator": "Laplacian + I (MPO rank 5)", "rhs_rank": max(rbr),
+                   "guess_rank": 4, "residual_rank": 4, "max_rank": cap, "rel_tol": tol, "x_rank": max(ranks),
+                   "sweeps": nsweeps},
+        "algorithmic_gflop_per_step": flops / 1e9,
+        "flop_ranks": "each sweep counted at the ranks it starts from (the guess's, then those after one sweep)",
+    }
+    if not args.no_kernel_breakdown:
+        add_roofline(out, kernel_breakdown(Q, step), sec)
+    if not args.no_cpu_baseline:
+        import oracle as O
+        threads = _blas_threads()
+        # the whole solve (two sweeps, about 10 s on the host) from the same guesses; the timed
+        # step's own result gives the error against it
+        gpu_x = Q.to_host(Q._views_of_compact(xb, ranks, d))
+        t0 = time.perf_counter()
+        ref, rinfo = O.solve_amen(Wc, rhs, guess, zguess, nsweeps=nsweeps, rel_tol=tol, max_rank=cap,
+                                  return_info=True)
+        dt = time.perf_counter() - t0
+        out["rel_err_vs_oracle"] = O.rel_error(gpu_x, ref)
+        out["ranks_identical"] = rinfo["ranks"] == ranks
+        out["cpu_baseline"] = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+                               "sample": "the same solve (both sweeps) from the same guesses (NumPy FP64, dense "
+                                         "local solves); the timed step's result gives rel_err_vs_oracle",
                                "seconds": dt}
     print(json.dumps(out), flush=True)
 
