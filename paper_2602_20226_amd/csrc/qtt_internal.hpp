@@ -165,8 +165,9 @@ hipError_t env3_right_mid(hipStream_t s, const double* U1, const double* W, int 
 // G[al][(i1,i2)][(j1,j2)][ga] = sum_be W1[al][i1][j1][be] W2[be][i2][j2][ga]
 hipError_t mpo_pair(hipStream_t s, const double* W1, const double* W2, int w0, int d1, int w1, int d2, int w2,
                     double* G);
-// x <- R^{-1} x, R the upper triangle of A (N x N, leading dimension lda).
-hipError_t trsv_upper(hipStream_t s, const double* A, int N, long lda, double* x);
+// x <- R^{-1} x, R the upper triangle of A (N x N, leading dimension lda);
+// A's strictly lower triangle is overwritten (R^T is mirrored into it).
+hipError_t trsv_upper(hipStream_t s, double* A, int N, long lda, double* x);
 
 // ---------------------------------------------------------------- kernel setup
 // Raise the dynamic-LDS limit of the kernels that stage more than 64 KiB

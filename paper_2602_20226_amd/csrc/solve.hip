@@ -102,21 +102,75 @@ __global__ void k_mpo_pair(const double* __restrict__ W1, const double* __restri
   }
 }
 
-// x <- R^{-1} x for the upper triangle R of A (N x N, leading dimension lda),
-// by columns from the last: x_k = x_k / R_kk, then x_{0..k-1} -= R_{0..k-1,k}
-// x_k.  One workgroup; the update of each column is spread over its threads.
-__global__ __launch_bounds__(1024) void k_trsv_upper(const double* __restrict__ A, int N, long lda,
-                                                     double* __restrict__ x) {
-  __shared__ double xk;
-  for (int k = N - 1; k >= 0; --k) {
-    if (threadIdx.x == 0) {
-      const double v = x[k] / A[(long)k * lda + k];
-      x[k] = v;
-      xk = v;
+// A[j][i] = A[i][j] for i < j: the upper triangle mirrored into the lower
+// one (whose previous contents are dropped), by 32 x 32 tiles staged in LDS
+// so that both the reads and the writes are row-contiguous.  Tiles above
+// the diagonal go to disjoint tiles below it; a diagonal tile moves only its
+// strictly upper entries, so no entry is both read and written.
+__global__ __launch_bounds__(256) void k_reflect_upper(double* __restrict__ A, int N, long lda) {
+  __shared__ double tile[32][33];
+  const int nt = (N + 31) / 32;
+  // blockIdx.x enumerates the tile pairs (bi <= bj) row by row
+  int t = blockIdx.x, bi = 0;
+  while (t >= nt - bi) {
+    t -= nt - bi;
+    ++bi;
+  }
+  const int bj = bi + t;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of 32 per pass
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi * 32 + r, j = bj * 32 + tx;
+    tile[r][tx] = (i < N && j < N) ? A[(long)i * lda + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j = bj * 32 + r, i = bi * 32 + tx;  // destination row j, column i
+    if (j < N && i < N && i < j) A[(long)j * lda + i] = tile[tx][r];
+  }
+}
+
+// x <- R^{-1} x for an upper-triangular R given by its transpose in the
+// lower triangle of L (N x N, leading dimension ldl): blocked from the
+// bottom in blocks B of 64 unknowns.  The diagonal block R_BB is staged in
+// LDS and x_B solved by one wave (lane i holds x_i; x_k = x_k / R_kk,
+// broadcast, lanes i < k subtract R_ik x_k); then every unknown above the
+// block takes x_i -= sum_b L[b][i] x_b over the block's rows b of L, read
+// contiguously along i (each thread keeps its 64 loads independent).  One
+// workgroup; the operation order is fixed, so the result is deterministic.
+constexpr int kTrsvB = 64;
+
+__global__ __launch_bounds__(1024) void k_trsv_rt(const double* __restrict__ L, int N, long ldl,
+                                                  double* __restrict__ x) {
+  __shared__ double R[kTrsvB][kTrsvB + 1];
+  __shared__ double xb[kTrsvB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k1 = N; k1 > 0; k1 -= kTrsvB) {
+    const int k0 = k1 > kTrsvB ? k1 - kTrsvB : 0;
+    const int nb = k1 - k0;
+    for (int e = tid; e < nb * nb; e += blockDim.x) {
+      const int c = e / nb, r = e % nb;  // R_BB[r][c] = L[k0 + c][k0 + r]
+      R[r][c] = (c >= r) ? L[(long)(k0 + c) * ldl + k0 + r] : 0.0;
     }
     __syncthreads();
-    const double v = xk;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] -= A[(long)i * lda + k] * v;
+    if (wave == 0) {
+      double xi = lane < nb ? x[k0 + lane] : 0.0;
+      for (int k = nb - 1; k >= 0; --k) {
+        if (lane == k) xi = xi / R[k][k];
+        const double xk = __shfl(xi, k);
+        if (lane < k) xi -= R[lane][k] * xk;
+      }
+      if (lane < nb) {
+        x[k0 + lane] = xi;
+        xb[lane] = xi;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < k0; i += blockDim.x) {
+      const double* col = L + (long)k0 * ldl + i;
+      double acc = 0.0;
+      for (int b = 0; b < nb; ++b) acc += col[(long)b * ldl] * xb[b];
+      x[i] -= acc;
+    }
     __syncthreads();
   }
 }
@@ -155,9 +209,13 @@ hipError_t mpo_pair(hipStream_t s, const double* W1, const double* W2, int w0, i
   return hipGetLastError();
 }
 
-hipError_t trsv_upper(hipStream_t s, const double* A, int N, long lda, double* x) {
+hipError_t trsv_upper(hipStream_t s, double* A, int N, long lda, double* x) {
   if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trsv_upper, dim3(1), dim3(1024), 0, s, A, N, lda, x);
+  const int nt = (N + 31) / 32;
+  hipLaunchKernelGGL(k_reflect_upper, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, A, N, lda);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_trsv_rt, dim3(1), dim3(1024), 0, s, A, N, lda, x);
   return hipGetLastError();
 }
 
