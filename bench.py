@@ -401,14 +401,19 @@ KERNEL_CLASSES = {
     "apply_panel": ("hbm", 8000.0, "GB/s", "k_apply1", "qr.hip"),
     "block_vty": ("mfma", 78600.0, "GFLOP/s", "k_vty", "qr.hip"),
     "block_upd": ("mfma", 78600.0, "GFLOP/s", "k_vupd", "qr.hip"),
+    "chol_block": ("alu", 78600.0, "GFLOP/s", "k_potrf_inv", "solve.hip"),
+    "chol_update": ("mfma", 78600.0, "GFLOP/s", "k_gemm", "solve.hip"),
+    "chol_solve": ("hbm", 8000.0, "GB/s", "k_chol_fwd/k_chol_bwd", "solve.hip"),
 }
+ROUNDING_CLASSES = ("jacobi", "qr_panel", "apply_panel", "block_vty", "block_upd")
 
 
-def kernel_breakdown(Q, step):
+def kernel_breakdown(Q, step, classes=ROUNDING_CLASSES):
     """One extra step per kernel class, every launch of the class bracketed by
     HIP events on its launch stream inside libqtt."""
     kernels = {}
-    for cls, (bound, peak, unit, kname, src) in KERNEL_CLASSES.items():
+    for cls in classes:
+        bound, peak, unit, kname, src = KERNEL_CLASSES[cls]
         Q.profile_start(cls, 20000)
         step()
         launches, kms, kbytes, kflops = Q.profile_stop()
@@ -601,8 +606,8 @@ def bench_fit(args, I, Q, torch, dev):
 def solve_flops(ranks, d, rw, rb, nsweeps):
     """Algorithmic FLOP of the one-core linear solver (same conventions):
     per local solve of N = r0 d r1 unknowns the local matrix (N^2 rw0 rw1
-    products of 2 FLOP), its Householder QR (geqrf of N x N), Q^T b (ormqr
-    with one column) and the triangular solve (N^2), the right-hand side
+    products of 2 FLOP), its Cholesky factorisation (N^3 / 3) and the two
+    triangular solves (2 N^2), the right-hand side
     (2 r0 rb0 d rb1 + 2 r0 d rb1 r1), the QR that moves the centre (geqrf of
     the core's unfolding) and the environment steps (three-layer:
     2 r0 rw0 r0 d r1 + 2 r0 d rw1 r1 rw0 d + 2 r1 r0 d rw1 r1; two-layer:
@@ -612,7 +617,7 @@ def solve_flops(ranks, d, rw, rb, nsweeps):
     for k in range(n):
         r0, r1, w0, w1, b0, b1, dk = ranks[k], ranks[k + 1], rw[k], rw[k + 1], rb[k], rb[k + 1], d[k]
         N = r0 * dk * r1
-        local = 2.0 * N * N * w0 * w1 + geqrf_flops(N, N) + ormqr_flops(N, N, 1) + N * N
+        local = 2.0 * N * N * w0 * w1 + N ** 3 / 3.0 + 2.0 * N * N
         local += 2.0 * r0 * b0 * dk * b1 + 2.0 * r0 * dk * b1 * r1
         move = geqrf_flops(r0 * dk, r1)
         env = 2.0 * r0 * w0 * r0 * dk * r1 + 2.0 * r0 * dk * w1 * r1 * w0 * dk + 2.0 * r1 * r0 * dk * w1 * r1
@@ -677,11 +682,11 @@ def bench_solve(args, I, Q, torch, dev):
         "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "cores": n, "operator": "Laplacian + I (MPO rank 5)", "rhs_rank": max(rbr),
-                   "x_rank": max(ranks), "sweeps": nsweeps, "local_solver": "Householder QR + triangular solve"},
+                   "x_rank": max(ranks), "sweeps": nsweeps, "local_solver": "blocked Cholesky + two triangular solves"},
         "algorithmic_gflop_per_step": flops / 1e9,
     }
     if not args.no_kernel_breakdown:
-        add_roofline(out, kernel_breakdown(Q, step), sec)
+        add_roofline(out, kernel_breakdown(Q, step, tuple(KERNEL_CLASSES)), sec)
     if not args.no_cpu_baseline:
         import oracle as O
         threads = _blas_threads()
@@ -703,7 +708,7 @@ def bench_solve(args, I, Q, torch, dev):
 
 def amen_flops(ranks, zranks, d, rw, rb):
     """Algorithmic FLOP of one AMEn sweep (two passes) at fixed ranks of x
-    and z: per core and pass the local solve of solve_flops, the nominal
+    and z: per core and pass the local solve of solve_flops (Cholesky), the nominal
     SVD of the solved core's unfolding and the product U S V^T, two residual
     projections (right-hand side part 2 a rb0 d rb1 + 2 a d rb1 c; operator
     part 2 r0 d c rw1 r1 + 2 d c rw0 r0 d rw1 + 2 a d c rw0 r0, with a x c
@@ -716,7 +721,7 @@ def amen_flops(ranks, zranks, d, rw, rb):
         r0, r1, z0, z1, w0, w1, b0, b1, dk = (ranks[k], ranks[k + 1], zranks[k], zranks[k + 1], rw[k], rw[k + 1],
                                               rb[k], rb[k + 1], d[k])
         N = r0 * dk * r1
-        local = 2.0 * N * N * w0 * w1 + geqrf_flops(N, N) + ormqr_flops(N, N, 1) + N * N
+        local = 2.0 * N * N * w0 * w1 + N ** 3 / 3.0 + 2.0 * N * N
         local += 2.0 * r0 * b0 * dk * b1 + 2.0 * r0 * dk * b1 * r1
         trunc = svd_nominal_flops(r0, dk * r1) + 2.0 * N * min(r0, dk * r1)
 
@@ -810,7 +815,7 @@ def bench_amen(args, I, Q, torch, dev):
         "flop_ranks": "each sweep counted at the ranks it starts from (the guess's, then those after one sweep)",
     }
     if not args.no_kernel_breakdown:
-        add_roofline(out, kernel_breakdown(Q, step), sec)
+        add_roofline(out, kernel_breakdown(Q, step, tuple(KERNEL_CLASSES)), sec)
     if not args.no_cpu_baseline:
         import oracle as O
         threads = _blas_threads()

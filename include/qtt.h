@@ -260,8 +260,11 @@ int qtt_fit2(qtt_handle h, const char *spec, const qtt_tt *a, const qtt_tt *b, q
  * max_rank, so the ranks adapt).  With the cores outside the block
  * orthonormal the block's minimiser solves the local system
  * A_loc x = b_loc (A_loc from the three-layer environments of <x|W|x>,
- * b_loc from those of <x|b>), solved by Householder QR and a triangular
- * solve (FP64).  The guess is orthogonalised from the left first; each of
+ * b_loc from those of <x|b>; symmetric positive definite for such W),
+ * solved by a blocked Cholesky factorisation of its lower triangle and two
+ * triangular solves (FP64; a pivot that is not positive, i.e. W not SPD,
+ * ends in QTT_ERR_NONFINITE).  The guess is orthogonalised from the left
+ * first; each of
  * nsweeps sweeps runs from the right end to the left and back.  x's cores
  * are caller-owned with the capacity of qtt_solve_query's bounds (for
  * ncores = 2 a max_rank keeps them small); x->ranks is rewritten.  Limits:
@@ -407,7 +410,9 @@ int qtt_batch_plan_destroy(qtt_batch_plan plan);
  * class (0 = 16-column block-reflector application inside a 64-column
  * block of the Householder QR, 1 = Jacobi SVD, 2 = Householder panel,
  * 3 = V^T Y product of a 64-column block reflector, 4 = its Y += V W
- * update): every following launch of that class, up to
+ * update, 5 = Cholesky factor and inverse of a 64 x 64 diagonal block of a
+ * solver's local system, 6 = its trailing update, 7 = the two blocked
+ * triangular solves): every following launch of that class, up to
  * max_launches, is bracketed by HIP events on the stream it is launched on,
  * and its algorithmic bytes and FLOP (from the launch shape) are summed.
  * qtt_profile_stop waits for the last event and returns the launch count,

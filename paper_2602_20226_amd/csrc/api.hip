@@ -1656,14 +1656,16 @@ int fit2_setup(const char* spec, const qtt_tt* a, const qtt_tt* b, const qtt_tt*
 // split of the fitting).  With the cores outside the block orthonormal the
 // block's minimiser solves A_loc x = b_loc, A_loc the block's local matrix
 // (three-layer environments of <x|W|x> and the block's operator cores),
-// b_loc = Lb b_block Rb^T; the local system is solved by Householder QR
-// (backward stable) and an upper-triangular solve.
+// b_loc = Lb b_block Rb^T.  A_loc is symmetric positive definite (an SPD
+// operator between orthonormal frames), so the local system is solved by a
+// blocked Cholesky factorisation (backward stable for SPD matrices) and two
+// triangular solves.
 struct SolvePlan {
   int nc = 1;
   std::vector<long> bnd, rw, rb;
   std::vector<long> offLW, offRW, offLb, offRb;
   long offA = 0, offRhs = 0, offT = 0, offE1 = 0, offE2 = 0, offG = 0, offBp = 0, offGt = 0, offTq = 0, offQe = 0;
-  long offS = 0, offSt = 0, offV = 0, offMV = 0, offLTB = 0, offLScr = 0;
+  long offS = 0, offSt = 0, offV = 0, offMV = 0, offChol = 0;
   long offTB = 0, offX = 0, offXc = 0, offYt = 0, offSig = 0, offPerm = 0, offTrunc = 0, offCtr = 0, offSweeps = 0,
        offNrm = 0, offScr = 0;
   long total = 0;
@@ -1786,8 +1788,7 @@ int make_solve_plan(const qtt_tt* w, const qtt_tt* b, const qtt_tt* x, int ncore
   F.offSt = take(maxSplit);
   F.offV = take(maxX);
   F.offMV = take(maxSplit);
-  F.offLTB = take(qr_t_doubles((int)maxN, (int)maxN));
-  F.offLScr = take(qr_scratch_doubles(maxN));
+  F.offChol = take(chol_work_doubles(maxN));
   F.offTB = take(maxTB);
   F.offX = take(maxX);
   F.offXc = take(maxX);
@@ -1851,9 +1852,7 @@ int solve_local(hipStream_t st, double* ws, const SolvePlan& F, const qtt_tt* w,
   }
   QTT_HIP(local_matrix(st, ws + F.offLW[q], Wl, ws + F.offRW[q + nc], (int)r0, (int)P, (int)r1, (int)w0, (int)w1, A));
   QTT_HIP(fit_project(st, ws + F.offLb[q], bl, ws + F.offRb[q + nc], r0, r1, rbl0, rbl1, P, ws + F.offT, rhs));
-  QTT_HIP(householder_qr(st, A, (int)N, (int)N, N, ws + F.offLTB, ws + F.offLScr));
-  QTT_HIP(apply_q(st, A, (int)N, (int)N, N, ws + F.offLTB, rhs, 1, 1, true, ws + F.offLScr));
-  QTT_HIP(trsv_upper(st, A, (int)N, N, rhs));
+  QTT_HIP(chol_solve(st, A, (int)N, N, rhs, ws + F.offChol));
   return QTT_OK;
 }
 
@@ -2101,8 +2100,7 @@ int make_amen_plan(const qtt_tt* w, const qtt_tt* b, const qtt_tt* x, const qtt_
   S.offT = take(maxT);
   S.offE1 = take(maxE);
   S.offE2 = take(maxE);
-  S.offLTB = take(qr_t_doubles((int)maxN, (int)maxN));
-  S.offLScr = take(qr_scratch_doubles(maxN));
+  S.offChol = take(chol_work_doubles(maxN));
   S.offS = take(maxSplit);
   S.offSt = take(maxSplit);
   S.offV = take(maxX);
@@ -2762,7 +2760,8 @@ int qtt_contract_backward(qtt_handle h, const char* spec, const qtt_tt* a, const
 }
 
 int qtt_profile_start(qtt_handle h, int kernel_class, int max_launches) {
-  if (!h || kernel_class < 0 || kernel_class > 4 || max_launches < 1 || max_launches > (1 << 22)) return QTT_ERR_ARG;
+  if (!h || kernel_class < 0 || kernel_class >= prof::kNumClasses || max_launches < 1 || max_launches > (1 << 22))
+    return QTT_ERR_ARG;
   Scoped sc(h->device);
   return prof::start(kernel_class, max_launches) == hipSuccess ? QTT_OK : QTT_ERR_HIP;
 }

@@ -165,9 +165,15 @@ hipError_t env3_right_mid(hipStream_t s, const double* U1, const double* W, int 
 // G[al][(i1,i2)][(j1,j2)][ga] = sum_be W1[al][i1][j1][be] W2[be][i2][j2][ga]
 hipError_t mpo_pair(hipStream_t s, const double* W1, const double* W2, int w0, int d1, int w1, int d2, int w2,
                     double* G);
-// x <- R^{-1} x, R the upper triangle of A (N x N, leading dimension lda);
-// A's strictly lower triangle is overwritten (R^T is mirrored into it).
-hipError_t trsv_upper(hipStream_t s, double* A, int N, long lda, double* x);
+// x <- A^{-1} x for a symmetric positive definite A (N x N, leading
+// dimension lda; its lower triangle is read): blocked Cholesky A = L L^T in
+// place (64-column blocks: each diagonal block factored and inverted by one
+// workgroup, FP64 GEMMs for the panels and trailing updates), then L y = x
+// and L^T x = y by blocks with the diagonal blocks' inverses.  N <= 4096.
+// A is overwritten; a pivot that is not positive gives NaN in x.  work:
+// chol_work_doubles(N).
+hipError_t chol_solve(hipStream_t s, double* A, int N, long lda, double* x, double* work);
+inline long chol_work_doubles(long N) { return ((N + 63) / 64) * 4096L + (N > 64 ? N - 64 : 1) * 64L; }
 
 // ---------------------------------------------------------------- kernel setup
 // Raise the dynamic-LDS limit of the kernels that stage more than 64 KiB
@@ -184,7 +190,17 @@ inline hipError_t configure_kernels() {
 
 // ---------------------------------------------------------------- launch profiling
 namespace prof {
-enum Class { APPLY_PANEL = 0, JACOBI = 1, QR_PANEL = 2, BLOCK_VTY = 3, BLOCK_UPD = 4 };
+enum Class {
+  APPLY_PANEL = 0,
+  JACOBI = 1,
+  QR_PANEL = 2,
+  BLOCK_VTY = 3,
+  BLOCK_UPD = 4,
+  CHOL_BLOCK = 5,
+  CHOL_UPDATE = 6,
+  CHOL_SOLVE = 7
+};
+constexpr int kNumClasses = 8;
 bool active(int cls);
 void begin(hipStream_t st, int cls, double bytes, double flops);
 void end(hipStream_t st);

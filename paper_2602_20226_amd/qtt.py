@@ -866,7 +866,8 @@ class BatchPlan:
             pass
 
 
-PROFILE_CLASSES = {"apply_panel": 0, "jacobi": 1, "qr_panel": 2, "block_vty": 3, "block_upd": 4}
+PROFILE_CLASSES = {"apply_panel": 0, "jacobi": 1, "qr_panel": 2, "block_vty": 3, "block_upd": 4, "chol_block": 5,
+                   "chol_update": 6, "chol_solve": 7}
 
 
 def profile_start(kernel_class: str, max_launches: int = 100000, device: Optional[int] = None):
