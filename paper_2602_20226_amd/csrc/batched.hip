@@ -210,6 +210,55 @@ __device__ __forceinline__ int wg_rotate(double* __restrict__ xa, double* __rest
   return 1;
 }
 
+// wg_rotate with row a held in registers by the calling wave (ua, its
+// squared norm na in a register of every lane) and row c in LDS: the same
+// arithmetic, so the same results.
+__device__ __forceinline__ int wg_rotate_reg(double (&ua)[JEMAX], double& na, double* __restrict__ xc,
+                                             double* __restrict__ nc, int L, double tol, double negl) {
+  const int lane = threadIdx.x & 63;
+  const double al = na, be = *nc;
+  if (al < negl || be < negl) {
+    int changed = 0;
+    if (al < negl && al > 0.0) {
+#pragma unroll
+      for (int q = 0; q < JEMAX; ++q) ua[q] = 0.0;
+      changed = 1;
+    }
+    if (be < negl && be > 0.0) {
+      for (int c = lane; c < L; c += 64) xc[c] = 0.0;
+      changed = 1;
+    }
+    if (changed) {
+      if (al < negl) na = 0.0;
+      if (lane == 0 && be < negl) *nc = 0.0;
+    }
+    return changed;
+  }
+  double w[JEMAX];
+  double ga = 0.0;
+#pragma unroll
+  for (int q = 0; q < JEMAX; ++q) {
+    const int c = lane + 64 * q;
+    w[q] = c < L ? xc[c] : 0.0;
+    ga += ua[q] * w[q];
+  }
+  ga = wave_sum_bc(ga);
+  double cs, sn, t;
+  if (!jacobi_rotation(al, be, ga, tol, cs, sn, t)) return 0;
+#pragma unroll
+  for (int q = 0; q < JEMAX; ++q) {
+    const int c = lane + 64 * q;
+    const double u = ua[q];
+    if (c < L) {
+      ua[q] = cs * u - sn * w[q];
+      xc[c] = sn * u + cs * w[q];
+    }
+  }
+  na = al - t * ga;
+  if (lane == 0) *nc = be + t * ga;
+  return 1;
+}
+
 template <int JB>
 __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restrict__ sh, int max_sweeps, double tol,
                          Smem& sm) {
@@ -231,6 +280,23 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
     wg_sync();
   }
   const double negl = 0x1p-208 * fmax(fmax(sm.scal[12], sm.scal[13]), fmax(sm.scal[14], sm.scal[15]));
+  // a block pair's rows, this wave's share (rows t = wave + NW h of the pair),
+  // loaded into registers with every load issued before any is used
+  constexpr int RW = (2 * JB + NW - 1) / NW;
+  double v[RW][JEMAX];
+  auto fetch = [&](int f0, int f1) {
+#pragma unroll
+    for (int h = 0; h < RW; ++h) {
+      const int t = wave + NW * h;
+      const int gr = (t < JB ? f0 : f1) * JB + (t % JB);
+      const bool ok = t < JR && gr < p;
+#pragma unroll
+      for (int e = 0; e < JEMAX; ++e) {
+        const int c = lane + 64 * e;
+        v[h][e] = (ok && c < L) ? X[(long)gr * L + c] : 0.0;
+      }
+    }
+  };
   int sweep = 0;
   bool converged = false;
   for (; sweep < max_sweeps; ++sweep) {
@@ -240,17 +306,27 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
       for (int pair = 0; pair < npairs; ++pair) {
         const int b0 = rr_item(pair, round, nb2);
         const int b1 = (nb2 > 1) ? rr_item(nb2 - 1 - pair, round, nb2) : 1;
-        for (int e = tid; e < JR * L; e += BNT) {
-          const int t = e / L, c = e % L;
-          const int gr = (t < JB ? b0 : b1) * JB + (t % JB);
-          sh[t * L + c] = (gr < p) ? X[(long)gr * L + c] : 0.0;
-        }
-        wg_sync();
-        for (int t = wave; t < JR; t += NW) {  // squared row norms, carried through the visit
-          double s2 = 0.0;
-          for (int c = lane; c < L; c += 64) s2 += sh[t * L + c] * sh[t * L + c];
-          s2 = wave_sum_bc(s2);
-          if (lane == 0) sm.jn[t] = s2;
+        // the pair's rows into LDS, squared row norms formed on the way and
+        // carried through the visit
+        {
+          fetch(b0, b1);
+#pragma unroll
+          for (int h = 0; h < RW; ++h) {
+            const int t = wave + NW * h;
+            double s2 = 0.0;
+            if (t < JR) {
+#pragma unroll
+              for (int e = 0; e < JEMAX; ++e) {
+                const int c = lane + 64 * e;
+                if (c < L) {
+                  sh[t * L + c] = v[h][e];
+                  s2 += v[h][e] * v[h][e];
+                }
+              }
+            }
+            s2 = wave_sum_bc(s2);
+            if (lane == 0 && t < JR) sm.jn[t] = s2;
+          }
         }
         wg_sync();
         int rot = 0;
@@ -265,19 +341,52 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
             wg_sync();
           }
         }
-        // cross pairs: at step s top row q meets bottom row (q + s) % JB
+        // cross pairs: at step s top row q meets bottom row (q + s) % JB.
+        // Wave w keeps its top rows q = w + NW h in registers for the whole
+        // visit; only the bottom rows pass through LDS.
+        static_assert(JB % NW == 0 || JB < NW, "top rows per wave");
+        constexpr int TH = JB >= NW ? JB / NW : 1;
+        double ur[TH][JEMAX], nr[TH];
+#pragma unroll
+        for (int h = 0; h < TH; ++h) {
+          const int q = wave + NW * h;
+          const bool own = q < JB;
+#pragma unroll
+          for (int e = 0; e < JEMAX; ++e) {
+            const int c = lane + 64 * e;
+            ur[h][e] = (own && c < L) ? sh[q * L + c] : 0.0;
+          }
+          nr[h] = own ? sm.jn[q] : 0.0;
+        }
         for (int s = 0; s < JB; ++s) {
-          for (int q = wave; q < JB; q += NW) {
-            const int tc = JB + (q + s) % JB;
-            rot += wg_rotate(sh + q * L, sh + tc * L, &sm.jn[q], &sm.jn[tc], L, tol, negl);
+#pragma unroll
+          for (int h = 0; h < TH; ++h) {
+            const int q = wave + NW * h;
+            if (q < JB) {
+              const int tc = JB + (q + s) % JB;
+              rot += wg_rotate_reg(ur[h], nr[h], sh + tc * L, &sm.jn[tc], L, tol, negl);
+            }
           }
           wg_sync();
         }
+#pragma unroll
+        for (int h = 0; h < TH; ++h) {
+          const int q = wave + NW * h;
+          if (q < JB) {
+#pragma unroll
+            for (int e = 0; e < JEMAX; ++e) {
+              const int c = lane + 64 * e;
+              if (c < L) sh[q * L + c] = ur[h][e];
+            }
+            if (lane == 0) sm.jn[q] = nr[h];
+          }
+        }
+        wg_sync();
         if (lane == 0 && rot) atomicAdd(&sm.iscal[0], rot);
-        for (int e = tid; e < JR * L; e += BNT) {
-          const int t = e / L, c = e % L;
+        for (int t = wave; t < JR; t += NW) {
           const int gr = (t < JB ? b0 : b1) * JB + (t % JB);
-          if (gr < p) X[(long)gr * L + c] = sh[t * L + c];
+          if (gr < p)
+            for (int c = lane; c < L; c += 64) X[(long)gr * L + c] = sh[t * L + c];
         }
         wg_sync();
       }
