@@ -1,7 +1,8 @@
 """Degenerate and smallest cases of the later entry points: one- and
 two-core trains, rank-1 products, a zero right-hand side, and the
 stream-ordered rounding on the smallest trains, each against the oracle or
-the synchronous call."""
+the synchronous call; and the solvers' error on an operator that is not
+positive definite."""
 import numpy as np
 import pytest
 
@@ -95,3 +96,24 @@ def test_async_rounding_smallest_trains(n):
     want, info = O.round_tt(O.contract("ij,j->i", A, B), 1e-10, 0, return_info=True)
     assert ranks == info.ranks
     assert O.rel_error(host(cores), want) <= 1e-13
+
+
+@pytest.mark.parametrize("solver", ["dmrg1", "dmrg2", "amen"])
+def test_solvers_reject_an_indefinite_operator(solver):
+    """The linear solvers take W symmetric positive definite: the local
+    matrices of a negative definite W have no Cholesky factor (the first
+    pivot's square root is NaN), and the call ends with QTT_ERR_NONFINITE
+    instead of returning a train."""
+    print(f"indefinite operator, {solver}", flush=True)
+    m, D = 3, 2
+    W = [c.copy() for c in I.laplacian_mpo(m, D, diag=2.5)]
+    W[0] = -W[0]  # -W: negative definite
+    rng = np.random.default_rng(21)
+    b = I.random_mps(m * D, 2, rng)
+    x0 = I.random_mps(m * D, 2, rng)
+    z0 = I.random_mps(m * D, 2, rng)
+    with pytest.raises(Q.QttError, match="NONFINITE"):
+        if solver == "amen":
+            Q.solve_amen(dev(W), dev(b), dev(x0), dev(z0), nsweeps=1, max_rank=4)
+        else:
+            Q.solve(dev(W), dev(b), dev(x0), nsweeps=1, ncores=1 if solver == "dmrg1" else 2, max_rank=4)
