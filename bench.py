@@ -403,7 +403,7 @@ KERNEL_CLASSES = {
     "block_upd": ("mfma", 78600.0, "GFLOP/s", "k_vupd", "qr.hip"),
     "chol_block": ("alu", 78600.0, "GFLOP/s", "k_potrf_inv", "solve.hip"),
     "chol_update": ("mfma", 78600.0, "GFLOP/s", "k_gemm", "solve.hip"),
-    "chol_solve": ("hbm", 8000.0, "GB/s", "k_chol_fwd/k_chol_bwd", "solve.hip"),
+    "chol_solve": ("hbm", 8000.0, "GB/s", "k_chol_bwd", "solve.hip"),
 }
 ROUNDING_CLASSES = ("jacobi", "qr_panel", "apply_panel", "block_vty", "block_upd")
 

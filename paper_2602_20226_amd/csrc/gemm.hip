@@ -45,10 +45,13 @@ constexpr int BM = 64, BN = 64, BK = 16, PADM = 1;
 // 16x16x4 MFMA operands: lane holds A[lane % 16][lane / 16] and
 // B[lane / 16][lane % 16]; result value v of a lane sits in column lane % 16
 // and row Mfma<T>::row(lane, v).
-template <typename T, bool TA, bool TB>
+// LOWER: only the output tiles on or below the tile diagonal (for symmetric
+// updates whose upper triangle is never read); the others exit at once.
+template <typename T, bool TA, bool TB, bool LOWER = false>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, T alpha, const T* __restrict__ A,
                                               long lda, long sA, const T* __restrict__ B, long ldb,
                                               long sB, T beta, T* __restrict__ C, long ldc, long sC) {
+  if (LOWER && blockIdx.x > blockIdx.y) return;
   __shared__ T As[BK][BM + PADM];
   __shared__ T Bs[BK][BN + PADM];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -320,6 +323,16 @@ hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double
                     const double* A, long lda, long sA, const double* B, long ldb, long sB,
                     double beta, double* C, long ldc, long sC, int batch) {
   return launch_gemm<double>(s, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
+}
+
+hipError_t gemm_f64_lower_nt(hipStream_t s, int N, int K, double alpha, const double* A, long lda, double beta,
+                             double* C, long ldc) {
+  if (N <= 0) return hipSuccess;
+  const int nt = (N + BN - 1) / BN;
+  if (nt > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gemm<double, false, true, true>), dim3(nt, nt, 1), dim3(256), 0, s, N, N, K, alpha, A, lda,
+                     0L, A, lda, 0L, beta, C, ldc, 0L);
+  return hipGetLastError();
 }
 
 hipError_t gemm_f32(hipStream_t s, bool ta, bool tb, int M, int N, int K, float alpha,

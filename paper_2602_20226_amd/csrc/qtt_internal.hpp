@@ -14,6 +14,11 @@ namespace qtt {
 hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
                     const double* A, long lda, long sA, const double* B, long ldb, long sB,
                     double beta, double* C, long ldc, long sC, int batch);
+// C = alpha A A^T + beta C on the tiles of C (N x N) on or below the 64 x 64
+// tile diagonal only (A: N x K, row-major); the tiles above it are not
+// touched.  For symmetric updates whose upper triangle is never read.
+hipError_t gemm_f64_lower_nt(hipStream_t s, int N, int K, double alpha, const double* A, long lda, double beta,
+                             double* C, long ldc);
 hipError_t gemm_f32(hipStream_t s, bool ta, bool tb, int M, int N, int K, float alpha,
                     const float* A, long lda, long sA, const float* B, long ldb, long sB,
                     float beta, float* C, long ldc, long sC, int batch);
@@ -168,12 +173,15 @@ hipError_t mpo_pair(hipStream_t s, const double* W1, const double* W2, int w0, i
 // x <- A^{-1} x for a symmetric positive definite A (N x N, leading
 // dimension lda; its lower triangle is read): blocked Cholesky A = L L^T in
 // place (64-column blocks: each diagonal block factored and inverted by one
-// workgroup, FP64 GEMMs for the panels and trailing updates), then L y = x
-// and L^T x = y by blocks with the diagonal blocks' inverses.  N <= 4096.
+// workgroup, the panel formed in place with that inverse, the trailing
+// update as an FP64 GEMM on the tiles on or below the diagonal); L y = x is
+// solved along the way (each block's step with the factorisation of its
+// diagonal block and its panel), then L^T x = y by blocks with the diagonal
+// blocks' inverses.  N <= 4096.
 // A is overwritten; a pivot that is not positive gives NaN in x.  work:
 // chol_work_doubles(N).
 hipError_t chol_solve(hipStream_t s, double* A, int N, long lda, double* x, double* work);
-inline long chol_work_doubles(long N) { return ((N + 63) / 64) * 4096L + (N > 64 ? N - 64 : 1) * 64L; }
+inline long chol_work_doubles(long N) { return ((N + 63) / 64) * 4096L; }
 
 // ---------------------------------------------------------------- kernel setup
 // Raise the dynamic-LDS limit of the kernels that stage more than 64 KiB

@@ -104,80 +104,93 @@ __global__ void k_mpo_pair(const double* __restrict__ W1, const double* __restri
   }
 }
 
-// 1/x over the whole normal range: double-precision hardware estimate and
-// one third-order correction (within an ulp or two; no IEEE division).
-__device__ __forceinline__ double rcp_full(double x) {
-  const double r = __builtin_amdgcn_rcp(x);
-  const double e = fma(-x, r, 1.0);
-  return fma(r, fma(e, e, e), r);
+// sqrt(x) and 1/sqrt(x) of a pivot from one hardware estimate of 1/sqrt(x)
+// (relative error e ~2^-24), one third-order correction of it,
+// r (1 + e/2 + 3 e^2 / 8) with e = 1 - x r^2, and one Newton step of the
+// square root l = x r: fewer dependent steps than an IEEE square root
+// followed by a reciprocal, within an ulp or two of both.  A pivot that is
+// zero, negative or NaN gives NaN or an infinity, as the IEEE pair would.
+__device__ __forceinline__ void sqrt_rsqrt(double x, double& l, double& r) {
+  const double r0 = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * r0, r0, 1.0);
+  r = fma(r0 * e, fma(0.375, e, 0.5), r0);
+  const double l0 = x * r;
+  l = fma(fma(-l0, l0, x), 0.5 * r, l0);
 }
 
 // Cholesky of the nb x nb diagonal block at A[j0][j0] (nb <= 64, lower
 // triangle used and overwritten by L) and the inverse of L into Linv
 // (64 x 64, row-major, zero outside the nb x nb lower triangle).  The block
-// is padded with the identity to 64 x 64 and held in registers, a 4 x 4
-// tile per thread (256 threads, 16 x 16 tiles), together with Y, which
-// starts as I and ends as L^{-1}.  Four columns K = k..k+3 per step: the
-// threads holding them publish the 64 x 4 column panel and those holding
-// rows K of Y publish them (double-buffered LDS, one barrier per step);
-// every thread then factors the 4 x 4 diagonal block Ld (and inverts it,
-// Li) in registers, forms the multipliers l_i = Li p_i of its rows and
-// columns from the published panel rows p_i (zero for rows and columns up
-// to k+3), the rows of the inverse X_K = Li Y_K, and applies the rank-4
-// updates a -= l l^T (only the trailing lower triangle is touched where it
-// matters; the upper triangle, never read, takes what it gets) and
-// Y -= l X_K; rows K of Y become X_K and columns K of L go to LDS.  A pivot
-// that is not positive gives NaN, which propagates to the solution.
+// is padded with the identity to 64 x 64; each of the 256 threads owns one
+// 4 x 4 tile (tile row tr, tile column tc) in registers.  A tile holds A
+// while its columns are still to be factored and, from the step that
+// factors them on, the same tile of Y, which is built up to L^{-1}: its
+// columns K of L are final at that step, and the tile of Y starts there
+// (I on the diagonal, 0 below it).  Four columns K = k..k+3 per step: the
+// threads of tile column K publish the 64 x 4 column panel, those of tile
+// row K their rows of Y (double-buffered LDS, one barrier per step); every
+// thread factors the 4 x 4 diagonal block Ld and inverts it (Li) in
+// registers, forms the multipliers l_i = Li p_i of its rows (zero up to
+// row k+3) and, for its columns, either the multipliers l_j = Li p_j (tile
+// still holding A: a -= l_i l_j^T) or the rows X_K = Li Y_K of the inverse
+// (tile holding Y: y -= l_i X_K), one rank-4 update either way; tile row K
+// then takes X_K.  Tiles whose rows are finished (tile row below K) do no
+// work, so waves drop out as the factorisation proceeds.  A pivot that is
+// not positive gives NaN, which propagates to the solution.
 __global__ __launch_bounds__(256) void k_potrf_inv(double* __restrict__ A, long lda, int j0, int nb,
-                                                   double* __restrict__ Linv) {
+                                                   double* __restrict__ Linv, double* __restrict__ x) {
+  __shared__ double xs[64];
   __shared__ double P[2][64][5];
   __shared__ double Yr[2][4][65];
   __shared__ double Ls[64][65];
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   const int i0 = 4 * tr, c0 = 4 * tc;
-  double a[4][4], y[4][4];
+  double z[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = i0 + u, j = c0 + v;
-      a[u][v] = (i < nb && j <= i) ? A[(long)(j0 + i) * lda + j0 + j] : (i == j ? 1.0 : 0.0);
-      y[u][v] = (i == j) ? 1.0 : 0.0;
+      z[u][v] = (i < nb && j <= i) ? A[(long)(j0 + i) * lda + j0 + j] : (i == j ? 1.0 : 0.0);
     }
-  for (int k = 0; k < 64; k += 4) {
-    const int buf = (k >> 2) & 1;
-    if (tc == (k >> 2)) {  // this tile's columns are K: publish them for its rows
+  for (int K = 0; K < 16; ++K) {
+    const int k = 4 * K, buf = K & 1;
+    const bool active = tr >= K;  // rows not yet final (wave-uniform once a whole wave is done)
+    if (active && tc == K) {  // the column panel (rows above the block are never read)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) P[buf][i0 + u][v] = a[u][v];
+        for (int v = 0; v < 4; ++v) P[buf][i0 + u][v] = z[u][v];
     }
-    if (tr == (k >> 2)) {  // this tile's rows are K: publish them for its columns
+    if (tr == K) {  // rows K of Y: the Y tiles left of the block, I on it, 0 right of it
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Yr[buf][u][c0 + v] = y[u][v];
+        for (int v = 0; v < 4; ++v) Yr[buf][u][c0 + v] = (tc < K) ? z[u][v] : ((tc == K && u == v) ? 1.0 : 0.0);
     }
     __syncthreads();
-    // all LDS reads of the step first
-    double d[4][4], pi[4][4], pj[4][4], yk[4][4];
+    if (!active) continue;
+    const bool amode = tc > K;  // this tile still holds A
+    double d[4][4], pi[4][4], sel[4][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         d[t][q] = P[buf][k + t][q];
         pi[t][q] = P[buf][i0 + t][q];
-        pj[t][q] = P[buf][c0 + t][q];
-        yk[t][q] = Yr[buf][t][c0 + q];
+        const double pj = P[buf][c0 + t][q];  // read by A tiles only (rows below the block)
+        const double yk = Yr[buf][q][c0 + t];
+        sel[t][q] = amode ? pj : yk;
       }
     // Ld = chol(D), Li = Ld^{-1} (lower, 4 x 4), written out
-    const double l00 = sqrt(d[0][0]), r0 = rcp_full(l00);
+    double l00, r0, l11, r1, l22, r2, l33, r3;
+    sqrt_rsqrt(d[0][0], l00, r0);
     const double l10 = d[1][0] * r0, l20 = d[2][0] * r0, l30 = d[3][0] * r0;
-    const double l11 = sqrt(d[1][1] - l10 * l10), r1 = rcp_full(l11);
+    sqrt_rsqrt(d[1][1] - l10 * l10, l11, r1);
     const double l21 = (d[2][1] - l20 * l10) * r1, l31 = (d[3][1] - l30 * l10) * r1;
-    const double l22 = sqrt(d[2][2] - l20 * l20 - l21 * l21), r2 = rcp_full(l22);
+    sqrt_rsqrt(d[2][2] - l20 * l20 - l21 * l21, l22, r2);
     const double l32 = (d[3][2] - l30 * l20 - l31 * l21) * r2;
-    const double l33 = sqrt(d[3][3] - l30 * l30 - l31 * l31 - l32 * l32), r3 = rcp_full(l33);
+    sqrt_rsqrt(d[3][3] - l30 * l30 - l31 * l31 - l32 * l32, l33, r3);
     const double m10 = -l10 * r0 * r1;
     const double m21 = -l21 * r1 * r2;
     const double m20 = -(l20 * r0 + l21 * m10) * r2;
@@ -186,50 +199,48 @@ __global__ __launch_bounds__(256) void k_potrf_inv(double* __restrict__ A, long 
     const double m30 = -(l30 * r0 + l31 * m10 + l32 * m20) * r3;
     const double Li[4][4] = {{r0, 0.0, 0.0, 0.0}, {m10, r1, 0.0, 0.0}, {m20, m21, r2, 0.0}, {m30, m31, m32, r3}};
     const double L[4][4] = {{l00, 0.0, 0.0, 0.0}, {l10, l11, 0.0, 0.0}, {l20, l21, l22, 0.0}, {l30, l31, l32, l33}};
-    // multipliers of this tile's rows and columns (zero up to k+3) and X_K
-    double li[4][4], lj[4][4], xk[4][4];
+    if (tc == K) {  // the tile switches from A to Y: I on the diagonal, 0 below
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) z[u][v] = (tr == K && u == v) ? 1.0 : 0.0;
+    }
+    // l_i of this tile's rows (zero up to k+3) and m = l_j (A tiles) or X_K (Y tiles)
+    double li[4][4], m[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        double su = 0.0, sv = 0.0, sx = 0.0;
+        double su = 0.0, sm = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (q <= t) {
             su += Li[t][q] * pi[u][q];
-            sv += Li[t][q] * pj[u][q];
-            sx += Li[t][q] * yk[q][u];
+            sm += Li[t][q] * sel[u][q];
           }
-        li[u][t] = (i0 + u > k + 3) ? su : 0.0;
-        lj[u][t] = (c0 + u > k + 3) ? sv : 0.0;
-        xk[t][u] = sx;  // X_K[t][c0 + u]
+        li[u][t] = (tr > K) ? su : 0.0;
+        m[u][t] = sm;  // l_j[c0 + u][t] or X_K[t][c0 + u]
       }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          a[u][v] = fma(-li[u][t], lj[v][t], a[u][v]);
-          y[u][v] = fma(-li[u][t], xk[t][v], y[u][v]);
-        }
-    if (tr == (k >> 2)) {  // rows K of the inverse
+        for (int t = 0; t < 4; ++t) z[u][v] = fma(-li[u][t], m[v][t], z[u][v]);
+    if (tr == K) {  // rows K of the inverse (zero right of the block)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) y[u][v] = xk[u][v];
+        for (int v = 0; v < 4; ++v) z[u][v] = amode ? 0.0 : m[v][u];
     }
-    if (tc == 0 && tr != (k >> 2)) {  // columns K of L outside the diagonal block
+    if (tc == 0 && tr > K) {  // columns K of L below the diagonal block
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int i = i0 + u;
-          Ls[i][k + t] = (i > k + 3) ? li[u][t] : 0.0;
-        }
+        for (int t = 0; t < 4; ++t) Ls[i0 + u][k + t] = li[u][t];
     }
-    if (tid < 16) {  // the diagonal block of L (selects: no run-time index into registers)
-      const int t = tid >> 2, q = tid & 3;
+    if (tr == K) {  // the diagonal block of L (selects: no run-time index into registers)
+      const int t = tc >> 2, q = tc & 3;
       double v = 0.0;
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt)
@@ -245,8 +256,63 @@ __global__ __launch_bounds__(256) void k_potrf_inv(double* __restrict__ A, long 
     for (int v = 0; v < 4; ++v) {
       const int i = i0 + u, j = c0 + v;
       if (i < nb && j <= i) A[(long)(j0 + i) * lda + j0 + j] = Ls[i][j];
-      Linv[i * 64 + j] = (i < nb && j < nb) ? y[u][v] : 0.0;
+      Linv[i * 64 + j] = (i < nb && j < nb) ? z[u][v] : 0.0;
     }
+  // this block's step of the forward substitution: x_B <- L_BB^{-1} x_B
+  // (x_B already holds b_B minus the earlier blocks' panels times their
+  // solutions); each tile row is summed over its 16 lanes in fixed order
+  if (tid < 64) xs[tid] = (tid < nb) ? x[j0 + tid] : 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    double p = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) p = fma(z[u][v], xs[c0 + v], p);
+    p = row_sum(p);
+    if (tc == 0 && i0 + u < nb) x[j0 + i0 + u] = p;
+  }
+}
+
+// Panel of the blocked Cholesky in place, and the matching step of the
+// forward substitution: rows [r0, r0 + 64) of P (mr x nb, leading dimension
+// ldp) <- P Li^T with Li (64 x 64, lower triangular, row-major) the inverse
+// of the diagonal block's factor, then xr[row] -= P[row] . yb for the same
+// rows (yb: the block's solved entries).  One workgroup per 64 rows; lane r
+// of wave g forms row r0 + r, columns [16 g, 16 g + 16) (the Li reads are
+// wave-uniform LDS broadcasts); a barrier separates every read of the rows
+// from the writes, and the four partial dot products are added in fixed
+// order.
+__global__ __launch_bounds__(256) void k_panel_rmul(double* __restrict__ P, int mr, int nb, long ldp,
+                                                    const double* __restrict__ Li, const double* __restrict__ yb,
+                                                    double* __restrict__ xr) {
+  __shared__ double Ls[64][65];
+  __shared__ double ys[64];
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x, g = tid >> 6, lane = tid & 63, row = blockIdx.x * 64 + lane;
+  for (int e = tid; e < 4096; e += 256) Ls[e >> 6][e & 63] = Li[e];
+  if (tid < 64) ys[tid] = (tid < nb) ? yb[tid] : 0.0;
+  const bool ok = row < mr;
+  const double* prow = P + (long)(ok ? row : 0) * ldp;
+  __syncthreads();
+  double o[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) o[c] = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < nb; ++k) {
+    const double ak = ok ? prow[k] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) o[c] = fma(ak, Ls[16 * g + c][k], o[c]);  // Li[col][k] = 0 for k > col
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) part = fma(o[c], ys[16 * g + c], part);
+  red[g][lane] = part;
+  __syncthreads();
+  if (!ok) return;
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+    if (16 * g + c < nb) P[(long)row * ldp + 16 * g + c] = o[c];
+  if (g == 0) xr[row] -= (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // Wave sum, every lane ends with the total.
@@ -258,51 +324,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int kCholMaxN = 4096;
 
-// y <- L^{-1} y with L (N x N, lower triangle of L, leading dimension ldl)
-// given with the inverses of its 64 x 64 diagonal blocks (Linv, one 64 x 64
-// block after the other): left-looking by blocks, r_B = y_B - L[B, 0:k0]
-// y[0:k0] (rows of L read contiguously, one wave per row, lanes along it),
-// y_B = Linv_B r_B.  One workgroup, y held in LDS, fixed operation order.
-__global__ __launch_bounds__(1024) void k_chol_fwd(const double* __restrict__ L, int N, long ldl,
-                                                   const double* __restrict__ Linv, double* __restrict__ y) {
-  __shared__ double ys[kCholMaxN];
-  __shared__ double rb[64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  for (int i = tid; i < N; i += blockDim.x) ys[i] = y[i];
-  __syncthreads();
-  for (int k0 = 0, b = 0; k0 < N; k0 += 64, ++b) {
-    const int nb = min(64, N - k0);
-    // rows r = wave + nw q of the block, four at a time (independent loads)
-    for (int r0 = wave; r0 < nb; r0 += 4 * nw) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      const double* row[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) row[q] = L + (long)(k0 + min(r0 + q * nw, nb - 1)) * ldl;
-      for (int c = lane; c < k0; c += 64) {
-        const double yc = ys[c];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += row[q][c] * yc;
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double t = wave_sum(acc[q]);
-        const int r = r0 + q * nw;
-        if (lane == 0 && r < nb) rb[r] = ys[k0 + r] - t;
-      }
-    }
-    __syncthreads();
-    const double* Li = Linv + (long)b * 4096;
-    for (int r = wave; r < nb; r += nw) {
-      double acc = (lane < nb) ? Li[r * 64 + lane] * rb[lane] : 0.0;
-      acc = wave_sum(acc);
-      if (lane == 0) ys[k0 + r] = acc;
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < N; i += blockDim.x) y[i] = ys[i];
-}
-
-// x <- L^{-T} x with L and Linv as in k_chol_fwd: by blocks from the last,
+// x <- L^{-T} x with L (N x N, lower triangle, leading dimension ldl) given
+// with the inverses of its 64 x 64 diagonal blocks (Linv, one 64 x 64 block
+// after the other): by blocks from the last,
 // r_B = x_B - L[k1:N, B]^T x[k1:N] (rows of L read contiguously, lanes
 // along the block's 64 columns, waves over rows, partial sums added in
 // fixed order), x_B = Linv_B^T r_B.  One workgroup, x held in LDS.
@@ -384,37 +408,35 @@ hipError_t chol_solve(hipStream_t s, double* A, int N, long lda, double* x, doub
   if (N <= 0) return hipSuccess;
   if (N > kCholMaxN) return hipErrorInvalidValue;
   const int nblk = (N + 63) / 64;
-  double* Linv = work;                   // nblk blocks of 64 x 64
-  double* P = work + (long)nblk * 4096;  // (N - 64) x 64 panel
+  double* Linv = work;  // nblk blocks of 64 x 64
   hipError_t e;
   for (int b = 0; b < nblk; ++b) {
     const int j0 = 64 * b, nb = std::min(64, N - j0);
     double* Li = Linv + (long)b * 4096;
     if (prof::active(prof::CHOL_BLOCK))
       prof::begin(s, prof::CHOL_BLOCK, 8.0 * ((double)nb * nb + 4096.0), 2.0 * nb * nb * nb / 3.0);
-    hipLaunchKernelGGL(k_potrf_inv, dim3(1), dim3(256), 0, s, A, lda, j0, nb, Li);
+    hipLaunchKernelGGL(k_potrf_inv, dim3(1), dim3(256), 0, s, A, lda, j0, nb, Li, x);
     prof::end(s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int mr = N - j0 - nb;
     if (mr <= 0) break;
     double* A21 = A + (long)(j0 + nb) * lda + j0;
-    // L21 = A21 L11^{-T}, then A22 -= L21 L21^T (the whole square; only its lower triangle is read later)
-    if ((e = gemm_f64(s, false, true, mr, nb, nb, 1.0, A21, lda, 0, Li, 64, 0, 0.0, P, nb, 0, 1)) != hipSuccess)
-      return e;
-    if ((e = copy_pad_rows(s, P, mr, nb, nb, A21, mr, lda)) != hipSuccess) return e;
-    // algorithmic work: the lower triangle of the update, mr^2 nb FLOP
+    // L21 = A21 L11^{-T}, in place, and x[j0 + nb:] -= L21 x_B
+    hipLaunchKernelGGL(k_panel_rmul, dim3((mr + 63) / 64), dim3(256), 0, s, A21, mr, nb, lda, (const double*)Li,
+                       (const double*)(x + j0), x + j0 + nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // A22 -= L21 L21^T on the tiles on or below the diagonal (only the lower
+    // triangle is read later); algorithmic work: the lower triangle, mr^2 nb FLOP
     if (prof::active(prof::CHOL_UPDATE))
       prof::begin(s, prof::CHOL_UPDATE, 8.0 * ((double)mr * nb + (double)mr * mr), (double)mr * mr * nb);
-    e = gemm_f64(s, false, true, mr, mr, nb, -1.0, P, nb, 0, P, nb, 0, 1.0, A21 + nb, lda, 0, 1);
+    e = gemm_f64_lower_nt(s, mr, nb, -1.0, A21, lda, 1.0, A21 + nb, lda);
     prof::end(s);
     if (e != hipSuccess) return e;
   }
-  // each solve reads the lower triangle of L and the block inverses once: N^2 FLOP
+  // x now holds y with L y = b (forward substitution carried along the
+  // factorisation); L^T x = y reads the lower triangle of L and the block
+  // inverses once: N^2 FLOP
   const double sbytes = 8.0 * ((double)N * (N + 1) / 2.0 + (double)nblk * 4096.0 + 2.0 * N);
-  if (prof::active(prof::CHOL_SOLVE)) prof::begin(s, prof::CHOL_SOLVE, sbytes, (double)N * N);
-  hipLaunchKernelGGL(k_chol_fwd, dim3(1), dim3(1024), 0, s, A, N, lda, Linv, x);  // L y = b
-  prof::end(s);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   if (prof::active(prof::CHOL_SOLVE)) prof::begin(s, prof::CHOL_SOLVE, sbytes, (double)N * N);
   hipLaunchKernelGGL(k_chol_bwd, dim3(1), dim3(1024), 0, s, A, N, lda, Linv, x);  // L^T x = y
   prof::end(s);
