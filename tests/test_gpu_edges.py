@@ -1,8 +1,8 @@
 """Degenerate and smallest cases of the later entry points: one- and
 two-core trains, rank-1 products, a zero right-hand side, and the
 stream-ordered rounding on the smallest trains, each against the oracle or
-the synchronous call; and the solvers' error on an operator that is not
-positive definite."""
+the synchronous call; the solvers on the shortest chains, and their error
+on an operator that is not positive definite."""
 import numpy as np
 import pytest
 
@@ -117,3 +117,33 @@ def test_solvers_reject_an_indefinite_operator(solver):
             Q.solve_amen(dev(W), dev(b), dev(x0), dev(z0), nsweeps=1, max_rank=4)
         else:
             Q.solve(dev(W), dev(b), dev(x0), nsweeps=1, ncores=1 if solver == "dmrg1" else 2, max_rank=4)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("solver", ["dmrg1", "dmrg2", "amen"])
+def test_solvers_on_the_shortest_chains(solver, n):
+    """Two- and three-core chains (a shifted 1D Laplacian on 2^n points),
+    where every core is an end core or next to one: both sweeps turn at
+    once.  Two sweeps from a rank-2 guess (and a rank-2 residual train for
+    AMEn) against the oracle's solver: ranks identical, the solution within
+    1e-10 (relative), and the dense solve reached to 1e-12."""
+    print(f"short chain n={n}, {solver}", flush=True)
+    W = I.laplacian_mpo(n, 1, diag=2.5)
+    rng = np.random.default_rng(730 + n)
+    b = I.random_mps(n, 2, rng)
+    x0 = I.random_mps(n, 2, rng)
+    if solver == "amen":
+        z0 = I.random_mps(n, 2, rng)
+        ref, info = O.solve_amen(W, b, x0, z0, nsweeps=2, rel_tol=1e-12, return_info=True)
+        xc, ranks, _, _, _ = Q.solve_amen(dev(W), dev(b), dev(x0), dev(z0), nsweeps=2, rel_tol=1e-12)
+    else:
+        nc = 1 if solver == "dmrg1" else 2
+        ref, info = O.solve_energy(W, b, x0, nsweeps=2, ncores=nc, rel_tol=1e-12, return_info=True)
+        xc, ranks, _ = Q.solve(dev(W), dev(b), dev(x0), nsweeps=2, ncores=nc, rel_tol=1e-12)
+    assert ranks == info["ranks"], (ranks, info["ranks"])
+    got = host(xc)
+    assert O.rel_error(got, ref) <= 1e-10
+    # rank 2 is the full rank of every bond here, so the sweeps reach the exact solution
+    A = O.mpo_to_dense(W)
+    xs = np.linalg.solve(A, O.to_dense(b).ravel())
+    assert np.linalg.norm(O.to_dense(got).ravel() - xs) <= 1e-12 * np.linalg.norm(xs)
