@@ -411,8 +411,9 @@ int qtt_batch_plan_destroy(qtt_batch_plan plan);
  * block of the Householder QR, 1 = Jacobi SVD, 2 = Householder panel,
  * 3 = V^T Y product of a 64-column block reflector, 4 = its Y += V W
  * update, 5 = Cholesky factor and inverse of a 64 x 64 diagonal block of a
- * solver's local system, 6 = its trailing update, 7 = the two blocked
- * triangular solves): every following launch of that class, up to
+ * solver's local system (with that block's step of the forward
+ * substitution), 6 = its trailing update, 7 = the blocked backward
+ * triangular solve): every following launch of that class, up to
  * max_launches, is bracketed by HIP events on the stream it is launched on,
  * and its algorithmic bytes and FLOP (from the launch shape) are summed.
  * qtt_profile_stop waits for the last event and returns the launch count,
