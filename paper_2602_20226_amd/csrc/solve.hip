@@ -169,18 +169,29 @@ __global__ __launch_bounds__(256) void k_potrf_inv(double* __restrict__ A, long 
         for (int v = 0; v < 4; ++v) Yr[buf][u][c0 + v] = (tc < K) ? z[u][v] : ((tc == K && u == v) ? 1.0 : 0.0);
     }
     __syncthreads();
+    // the 4 x 4 pivot block is the same for every thread: lanes 0-15 of each
+    // wave read it and it is made wave-uniform (16 LDS values per wave
+    // instead of per thread)
+    const double dl = P[buf][k + ((tid >> 2) & 3)][tid & 3];
+    double d[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) d[t][q] = readlane_f64(dl, 4 * t + q);
     if (!active) continue;
     const bool amode = tc > K;  // this tile still holds A
-    double d[4][4], pi[4][4], sel[4][4];
+    // the multipliers' source: the panel rows of this tile's columns (A
+    // tiles, P[c0 + t][q]) or the rows K of Y over them (Y tiles,
+    // Yr[q][c0 + t]); one read per entry from the address chosen per thread
+    const double* src = amode ? &P[buf][c0][0] : &Yr[buf][0][c0];
+    const int st = amode ? 5 : 1, sq = amode ? 1 : 65;
+    double pi[4][4], sel[4][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        d[t][q] = P[buf][k + t][q];
         pi[t][q] = P[buf][i0 + t][q];
-        const double pj = P[buf][c0 + t][q];  // read by A tiles only (rows below the block)
-        const double yk = Yr[buf][q][c0 + t];
-        sel[t][q] = amode ? pj : yk;
+        sel[t][q] = src[t * st + q * sq];
       }
     // Ld = chol(D), Li = Ld^{-1} (lower, 4 x 4), written out
     double l00, r0, l11, r1, l22, r2, l33, r3;
