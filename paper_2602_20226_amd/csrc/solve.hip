@@ -326,13 +326,6 @@ __global__ __launch_bounds__(256) void k_panel_rmul(double* __restrict__ P, int 
   if (g == 0) xr[row] -= (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
-// Wave sum, every lane ends with the total.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
 constexpr int kCholMaxN = 4096;
 
 // x <- L^{-T} x with L (N x N, lower triangle, leading dimension ldl) given
