@@ -149,11 +149,6 @@ __global__ void k_eye_rect(double* Z, int m, int q) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
     Z[e] = (e / q == e % q) ? 1.0 : 0.0;
 }
-__global__ void k_identity(double* Z, int p) {
-  const long n = (long)p * p;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
-    Z[e] = (e / p == e % p) ? 1.0 : 0.0;
-}
 // dst[r][c] = src[r][c] for r < rows, 0 for rows <= r < rows_out (c < cols)
 __global__ void k_copy_pad(const double* __restrict__ src, int rows, int cols, long lds, double* __restrict__ dst,
                            int rows_out, long ldd) {
@@ -366,11 +361,6 @@ hipError_t fill_f32(hipStream_t s, float* p, float v, long n) {
 hipError_t set_eye_rect(hipStream_t s, double* Z, int m, int q) {
   if (m <= 0 || q <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_eye_rect, dim3(grid_for((long)m * q)), dim3(256), 0, s, Z, m, q);
-  return hipGetLastError();
-}
-hipError_t set_identity(hipStream_t s, double* Z, int p) {
-  if (p <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_identity, dim3(grid_for((long)p * p)), dim3(256), 0, s, Z, p);
   return hipGetLastError();
 }
 hipError_t copy_pad_rows(hipStream_t s, const double* src, int rows, int cols, long lds, double* dst, int rows_out,

@@ -110,7 +110,6 @@ hipError_t row_norms_sorted(hipStream_t s, const double* X, int p, int L, double
 hipError_t fill_f64(hipStream_t s, double* p, double v, long n);
 hipError_t fill_u32(hipStream_t s, unsigned* p, unsigned v, long n);
 hipError_t fill_f32(hipStream_t s, float* p, float v, long n);
-hipError_t set_identity(hipStream_t s, double* Z, int p);
 hipError_t set_eye_rect(hipStream_t s, double* Z, int m, int q);
 hipError_t copy_pad_rows(hipStream_t s, const double* src, int rows, int cols, long lds,
                          double* dst, int rows_out, long ldd);
