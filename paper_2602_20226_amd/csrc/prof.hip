@@ -17,7 +17,6 @@ struct State {
   int cap = 0;
   int used = 0;
   bool open = false;
-  bool last_ok = false;  // the most recent begin() of the class was recorded
   std::vector<hipEvent_t> ev;
   double bytes = 0.0, flops = 0.0;
 };
@@ -34,10 +33,8 @@ bool active(int cls) {
 
 void begin(hipStream_t st, int cls, double bytes, double flops) {
   State& s = state();
-  if (s.cls == cls) s.last_ok = false;
   if (s.cls != cls || s.used >= s.cap || s.open) return;
   if (hipEventRecord(s.ev[2 * s.used], st) != hipSuccess) return;
-  s.last_ok = true;
   s.open = true;
   s.bytes += bytes;
   s.flops += flops;
@@ -51,13 +48,6 @@ void end(hipStream_t st) {
   ++s.used;
 }
 
-void amend(int cls, double bytes, double flops) {
-  State& s = state();
-  if (s.cls != cls || !s.last_ok) return;
-  s.bytes += bytes;
-  s.flops += flops;
-}
-
 hipError_t start(int cls, int max_launches) {
   State& s = state();
   for (hipEvent_t e : s.ev) (void)hipEventDestroy(e);
@@ -65,7 +55,6 @@ hipError_t start(int cls, int max_launches) {
   s.cls = -1;
   s.used = 0;
   s.open = false;
-  s.last_ok = false;
   s.bytes = s.flops = 0.0;
   s.ev.resize(2 * (size_t)max_launches);
   for (auto& e : s.ev) {

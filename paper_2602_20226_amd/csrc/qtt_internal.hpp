@@ -211,9 +211,6 @@ constexpr int kNumClasses = 8;
 bool active(int cls);
 void begin(hipStream_t st, int cls, double bytes, double flops);
 void end(hipStream_t st);
-// Adds work to the last launch recorded for class cls (work known only after
-// the launch, e.g. an iteration count read back later).
-void amend(int cls, double bytes, double flops);
 hipError_t start(int cls, int max_launches);
 hipError_t stop(long* launches, double* total_ms, double* bytes, double* flops);
 }  // namespace prof
