@@ -236,6 +236,23 @@ def test_round_small(case):
         assert O.rel_error(host(got.cores), X) <= 1e-13
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("maxr", [0, 400])
+def test_round_longest_jacobi_rows(maxr):
+    """Ranks up to 512 (n = 20): the SVD sweep's matrices reach 512 rows of
+    2 x 512 = 1024 entries, the longest rows the Jacobi takes (its widest LDS
+    staging); untruncated and with the cap binding at 400."""
+    n = 20
+    ranks = [min(2 ** k, 512, 2 ** (n - k)) for k in range(n + 1)]
+    log(f"round longest Jacobi rows, max rank {max(ranks)}, cap {maxr}")
+    rng = np.random.default_rng(111)
+    X = [rng.standard_normal((ranks[k], 2, ranks[k + 1])) / np.sqrt(2 * ranks[k + 1]) for k in range(n)]
+    ref, info = O.round_tt(X, 0.0, maxr, return_info=True)
+    got = Q.round_tt(dev(X), 0.0, maxr, want_sigmas=True)
+    assert max(got.ranks) == (512 if maxr == 0 else maxr)
+    check_round(got, ref, info)
+
+
 def test_round_zero_tensor_is_rank1_zero():
     X = [np.zeros((1, 2, 3)), np.zeros((3, 2, 3)), np.zeros((3, 2, 1))]
     got = Q.round_tt(dev(X), 1e-8, 0)
