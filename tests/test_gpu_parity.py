@@ -237,19 +237,22 @@ def test_round_small(case):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("maxr", [0, 400])
-def test_round_longest_jacobi_rows(maxr):
+@pytest.mark.parametrize("peak,maxr", [(512, 0), (512, 400), (1024, 512)])
+def test_round_longest_jacobi_rows(peak, maxr):
     """Ranks up to 512 (n = 20): the SVD sweep's matrices reach 512 rows of
     2 x 512 = 1024 entries, the longest rows the Jacobi takes (its widest LDS
-    staging); untruncated and with the cap binding at 400."""
+    staging); untruncated and with the cap binding at 400.  With the middle
+    rank 1024 and a cap of 512 (the cap keeps every row length within 1024)
+    one matrix has 1024 rows of 2 x 512 entries: the most rows and the
+    largest grid of the Jacobi."""
     n = 20
-    ranks = [min(2 ** k, 512, 2 ** (n - k)) for k in range(n + 1)]
+    ranks = [min(2 ** k, peak, 2 ** (n - k)) for k in range(n + 1)]
     log(f"round longest Jacobi rows, max rank {max(ranks)}, cap {maxr}")
     rng = np.random.default_rng(111)
     X = [rng.standard_normal((ranks[k], 2, ranks[k + 1])) / np.sqrt(2 * ranks[k + 1]) for k in range(n)]
     ref, info = O.round_tt(X, 0.0, maxr, return_info=True)
     got = Q.round_tt(dev(X), 0.0, maxr, want_sigmas=True)
-    assert max(got.ranks) == (512 if maxr == 0 else maxr)
+    assert max(got.ranks) == (peak if maxr == 0 else maxr)
     check_round(got, ref, info)
 
 
