@@ -256,6 +256,18 @@ def test_round_longest_jacobi_rows(peak, maxr):
     check_round(got, ref, info)
 
 
+def test_round_rejects_rows_longer_than_1024():
+    """Without a cap, the core left of a rank-1024 bond splits into rows of
+    2 x 1024 entries, past the Jacobi's limit: the size check refuses the
+    call (QTT_ERR_UNSUPPORTED) before anything is launched."""
+    n = 20
+    ranks = [min(2 ** k, 1024, 2 ** (n - k)) for k in range(n + 1)]
+    rng = np.random.default_rng(112)
+    X = [rng.standard_normal((ranks[k], 2, ranks[k + 1])) for k in range(n)]
+    with pytest.raises(Q.QttError, match="UNSUPPORTED"):
+        Q.round_tt(dev(X), 0.0, 0)
+
+
 def test_round_zero_tensor_is_rank1_zero():
     X = [np.zeros((1, 2, 3)), np.zeros((3, 2, 3)), np.zeros((3, 2, 1))]
     got = Q.round_tt(dev(X), 1e-8, 0)
