@@ -268,7 +268,9 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
   const int nb2 = nblk + (nblk & 1);
   const int npairs = nb2 / 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // deflation level: 2^-208 times the largest squared input row norm
+  // deflation level: (8 u sqrt(p))^2 times the largest squared input row
+  // norm (rows at the rounding noise of the input are set to zero, as in the
+  // single-chain Jacobi)
   {
     double mx = 0.0;
     for (int i = wave; i < p; i += NW) {
@@ -279,7 +281,8 @@ __device__ int wg_jacobi(double* __restrict__ X, int p, int L, double* __restric
     if (lane == 0) sm.scal[12 + wave] = mx;
     wg_sync();
   }
-  const double negl = 0x1p-208 * fmax(fmax(sm.scal[12], sm.scal[13]), fmax(sm.scal[14], sm.scal[15]));
+  const double negl =
+      64.0 * 0x1p-106 * (double)p * fmax(fmax(sm.scal[12], sm.scal[13]), fmax(sm.scal[14], sm.scal[15]));
   // a block pair's rows, this wave's share (rows t = wave + NW h of the pair),
   // loaded into registers with every load issued before any is used
   constexpr int RW = (2 * JB + NW - 1) / NW;

@@ -97,7 +97,8 @@ hipError_t extract_r(hipStream_t s, const double* A, int kr, int n, long lda, do
 // sweeps_dev[0] receives the sweeps executed, sweeps_dev[1] 1 if a sweep
 // without rotations was reached within max_sweeps (converged), else 0.
 // ref_norm (device, nullable): the largest input row norm; rows whose norm
-// falls below eps^2 times it are deflated to zero.
+// falls below 8 u sqrt(p) times it (the rounding noise of the input) are
+// deflated to zero.
 hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter, int max_sweeps,
                        int* sweeps_dev, const double* ref_norm = nullptr);
 // dst[j] = src[perm[j]] (row gather).

@@ -121,17 +121,20 @@ __device__ __forceinline__ void lds_get(const double* slot, double (&r)[E]) {
 // ctr[0..1]: grid barrier; ctr[2..4]: rotation counts of three consecutive
 // sweeps; ctr[JCTR + b]: rounds completed by block b.
 // Rows are deflated to exact zeros once their squared norm falls below
-// negl = 2^-208 max_i ||x_i||^2 of the input (norm below eps^2 times the
-// largest): a row that has become an exact tiny multiple of another cannot
-// be rotated away (each rotation shrinks it by about eps while it stays
-// parallel, so the relative test would fire on every sweep), and at that
-// size it is zero to working precision.  ref (nullable) points at the
-// largest input row norm.
+// negl = defl max_i ||x_i||^2 of the input, defl = (8 u sqrt(p))^2: a row
+// at that level is rounding noise of the input (its singular value is
+// within the error any backward-stable SVD makes), and left in, such rows
+// cannot be rotated away -- a row that has become an exact tiny multiple of
+// another shrinks by about eps per rotation while it stays parallel, so the
+// relative test would fire on every sweep, and rows that collapse to the
+// rounding level of an exactly rank-deficient input become orthogonal only
+// after all the others.  ref (nullable) points at the largest input row
+// norm.
 template <int E>
 __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, int L, unsigned* __restrict__ ctr,
                                                 int max_sweeps, int* sweeps_out, double tol,
-                                                const double* __restrict__ ref) {
-  const double negl = ref ? 0x1p-208 * (ref[0] * ref[0]) : 0.0;
+                                                const double* __restrict__ ref, double defl) {
+  const double negl = ref ? defl * (ref[0] * ref[0]) : 0.0;
   extern __shared__ double sh[];  // 16 row slots of 64 E doubles
   __shared__ double bes[2][JB];   // squared norms travelling with the bottom rows
   __shared__ unsigned s_tot;
@@ -460,7 +463,9 @@ hipError_t jacobi_rows(hipStream_t s, double* X, int p, int L, unsigned* counter
   const int grid = nb2 / 2;
   // tolerance on |a.c| / (||a|| ||c||)
   const double tol = 2.220446049250313e-16 * sqrt((double)L);
-  void* args[] = {&X, &p, &L, &counter, &max_sweeps, &sweeps_dev, (void*)&tol, (void*)&ref_norm};
+  // deflation level relative to the largest squared row norm: (8 u sqrt(p))^2
+  double defl = 64.0 * 0x1p-106 * (double)p;
+  void* args[] = {&X, &p, &L, &counter, &max_sweeps, &sweeps_dev, (void*)&tol, (void*)&ref_norm, (void*)&defl};
   const void* fn;
   int E;
   if (L <= 64) {

@@ -23,8 +23,8 @@ def ranks_agree(got_ranks, ref_info):
     (both SVDs agree to about u sqrt(p) s_1 in every value).  Below that --
     in practice the untruncated tol = 0 roundings -- the oracle keeps values
     that are rounding noise of an exactly rank-deficient input, and the
-    Jacobi SVD, which sets rows below eps^2 of its largest input row to exact
-    zeros, may drop them: there the GPU rank may fall short of the oracle's
+    Jacobi SVD, which sets rows below 8 u sqrt(p) of its largest input row
+    to exact zeros, may drop them: there the GPU rank may fall short of the oracle's
     by at most the number of noise-level values."""
     import numpy as np
     u = 2.0 ** -53
