@@ -152,10 +152,9 @@ __global__ __launch_bounds__(JNT) void k_jacobi(double* __restrict__ X, int p, i
       const int b0 = rr_item(pair, round, nb2);
       const int b1 = rr_item(nb2 - 1 - pair, round, nb2);
       const unsigned expect = (unsigned)(sweep * nrounds + round);
-      if (tid == 0) {
-        while (__hip_atomic_load(&ver[b0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != expect)
-          __builtin_amdgcn_s_sleep(1);
-        while (__hip_atomic_load(&ver[b1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != expect)
+      if (tid < 2) {  // lanes 0 and 1 poll the two blocks' versions together
+        const int bb = tid == 0 ? b0 : b1;
+        while (__hip_atomic_load(&ver[bb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != expect)
           __builtin_amdgcn_s_sleep(1);
       }
       __syncthreads();
