@@ -285,45 +285,74 @@ __global__ __launch_bounds__(256) void k_potrf_inv(double* __restrict__ A, long 
 }
 
 // Panel of the blocked Cholesky in place, and the matching step of the
-// forward substitution: rows [r0, r0 + 64) of P (mr x nb, leading dimension
-// ldp) <- P Li^T with Li (64 x 64, lower triangular, row-major) the inverse
-// of the diagonal block's factor, then xr[row] -= P[row] . yb for the same
-// rows (yb: the block's solved entries).  One workgroup per 64 rows; lane r
-// of wave g forms row r0 + r, columns [16 g, 16 g + 16) (the Li reads are
-// wave-uniform LDS broadcasts); a barrier separates every read of the rows
-// from the writes, and the four partial dot products are added in fixed
-// order.
+// forward substitution: rows [r0, r0 + 32) of P (mr x nb, leading dimension
+// ldp) <- P Li^T with Li (64 x 64, lower triangular, row-major, zero outside
+// the nb x nb block) the inverse of the diagonal block's factor, then
+// xr[row] -= P[row] . yb for the same rows (yb: the block's solved entries).
+// One workgroup per 32 rows: the rows and Li^T are staged in LDS with
+// coalesced loads (every read of the rows precedes the barrier, every write
+// follows it), the 32 x 64 product runs on the FP64 matrix cores (wave w
+// owns the 16-row half w / 2 and the two 16-column tiles 2 (w % 2) + {0, 1};
+// operand lane layout A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+// result C[i][j] with i = lane / 16 + 4 v, j = lane % 16), and each row's
+// dot product with yb is summed over its 16 lanes and the two waves of its
+// half in fixed order.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+constexpr int kPanelRows = 32;
 __global__ __launch_bounds__(256) void k_panel_rmul(double* __restrict__ P, int mr, int nb, long ldp,
                                                     const double* __restrict__ Li, const double* __restrict__ yb,
                                                     double* __restrict__ xr) {
-  __shared__ double Ls[64][65];
+  constexpr int PR = kPanelRows;
+  __shared__ double As[64][PR + 1];  // As[k][i] = P[r0 + i][k]
+  __shared__ double Bs[64][65];      // Bs[k][j] = Li[j][k]
   __shared__ double ys[64];
-  __shared__ double red[4][64];
-  const int tid = threadIdx.x, g = tid >> 6, lane = tid & 63, row = blockIdx.x * 64 + lane;
-  for (int e = tid; e < 4096; e += 256) Ls[e >> 6][e & 63] = Li[e];
-  if (tid < 64) ys[tid] = (tid < nb) ? yb[tid] : 0.0;
-  const bool ok = row < mr;
-  const double* prow = P + (long)(ok ? row : 0) * ldp;
-  __syncthreads();
-  double o[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) o[c] = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < nb; ++k) {
-    const double ak = ok ? prow[k] : 0.0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) o[c] = fma(ak, Ls[16 * g + c][k], o[c]);  // Li[col][k] = 0 for k > col
+  __shared__ double red[2][PR];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r0 = blockIdx.x * PR;
+  for (int e = tid; e < PR * 64; e += 256) {
+    const int i = e >> 6, k = e & 63;
+    As[k][i] = (r0 + i < mr && k < nb) ? P[(long)(r0 + i) * ldp + k] : 0.0;
   }
-  double part = 0.0;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) part = fma(o[c], ys[16 * g + c], part);
-  red[g][lane] = part;
+  for (int e = tid; e < 4096; e += 256) Bs[e & 63][e >> 6] = Li[e];
+  if (tid < 64) ys[tid] = (tid < nb) ? yb[tid] : 0.0;
   __syncthreads();
-  if (!ok) return;
+  const int ti = w >> 1, tj0 = 2 * (w & 1);
+  const int il = lane & 15, kq = lane >> 4;
+  f64x4_t acc[2];
 #pragma unroll
-  for (int c = 0; c < 16; ++c)
-    if (16 * g + c < nb) P[(long)row * ldp + 16 * g + c] = o[c];
-  if (g == 0) xr[row] -= (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  for (int t = 0; t < 2; ++t) acc[t] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    const int k = 4 * ks + kq;
+    const double a = As[k][16 * ti + il];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[k][16 * (tj0 + t) + il], acc[t], 0, 0, 0);
+  }
+  // this wave's part of each row's dot product with yb: over its 32 columns
+  double part[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double pv = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) pv = fma(acc[t][v], ys[16 * (tj0 + t) + il], pv);
+    part[v] = row_sum(pv);  // the 16 lanes of a row of lanes hold the 16 columns of one output row
+  }
+  if (il == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w & 1][16 * ti + kq + 4 * v] = part[v];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int col = 16 * (tj0 + t) + il;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + 16 * ti + kq + 4 * v;
+      if (row < mr && col < nb) P[(long)row * ldp + col] = acc[t][v];
+    }
+  }
+  if (tid < PR && r0 + tid < mr) xr[r0 + tid] -= red[0][tid] + red[1][tid];
 }
 
 constexpr int kCholMaxN = 4096;
@@ -426,7 +455,8 @@ hipError_t chol_solve(hipStream_t s, double* A, int N, long lda, double* x, doub
     if (mr <= 0) break;
     double* A21 = A + (long)(j0 + nb) * lda + j0;
     // L21 = A21 L11^{-T}, in place, and x[j0 + nb:] -= L21 x_B
-    hipLaunchKernelGGL(k_panel_rmul, dim3((mr + 63) / 64), dim3(256), 0, s, A21, mr, nb, lda, (const double*)Li,
+    hipLaunchKernelGGL(k_panel_rmul, dim3((mr + kPanelRows - 1) / kPanelRows), dim3(256), 0, s, A21, mr, nb, lda,
+                       (const double*)Li,
                        (const double*)(x + j0), x + j0 + nb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // A22 -= L21 L21^T on the tiles on or below the diagonal (only the lower
