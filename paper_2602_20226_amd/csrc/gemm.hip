@@ -317,6 +317,56 @@ __global__ __launch_bounds__(256) void k_gemm_viaf32(int M, int N, int K, const 
       }
 }
 
+// C = alpha A A^T + beta C for K <= 64 on the tiles on or below the
+// diagonal: one workgroup per 32-row x 64-column tile, the tile's rows of A
+// (as the left operand) and the 64 rows of its columns (as the right one)
+// staged in LDS at once with coalesced loads, the product on FP64 MFMA
+// 16x16x4 (wave w owns rows 16 (w / 2) and columns 32 (w % 2) of the tile:
+// two 16 x 16 results; lane layout as in k_gemm).  Tiles wholly above the
+// diagonal exit at once.
+__global__ __launch_bounds__(256) void k_syrk_k64(int N, int K, double alpha, const double* __restrict__ A, long lda,
+                                                  double beta, double* __restrict__ C, long ldc) {
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 64;
+  if (j0 > i0 + 31) return;
+  __shared__ double As[64][33];  // As[k][i] = A[i0 + i][k]
+  __shared__ double Bs[64][65];  // Bs[k][j] = A[j0 + j][k]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < 32 * 64; e += 256) {
+    const int i = e >> 6, k = e & 63;
+    As[k][i] = (i0 + i < N && k < K) ? A[(long)(i0 + i) * lda + k] : 0.0;
+  }
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int j = e >> 6, k = e & 63;
+    Bs[k][j] = (j0 + j < N && k < K) ? A[(long)(j0 + j) * lda + k] : 0.0;
+  }
+  __syncthreads();
+  const int ti = w >> 1, tj0 = 2 * (w & 1), il = lane & 15, kq = lane >> 4;
+  double4_t acc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) acc[t] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    const int k = 4 * ks + kq;
+    const double a = As[k][16 * ti + il];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[k][16 * (tj0 + t) + il], acc[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int col = j0 + 16 * (tj0 + t) + il;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = i0 + 16 * ti + kq + 4 * v;
+      if (row < N && col < N) {
+        double r = alpha * acc[t][v];
+        if (beta != 0.0) r += beta * C[(long)row * ldc + col];
+        C[(long)row * ldc + col] = r;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
@@ -328,6 +378,12 @@ hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double
 hipError_t gemm_f64_lower_nt(hipStream_t s, int N, int K, double alpha, const double* A, long lda, double beta,
                              double* C, long ldc) {
   if (N <= 0) return hipSuccess;
+  if (K <= 64) {
+    const int nr = (N + 31) / 32, nc = (N + 63) / 64;
+    if (nr > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_syrk_k64, dim3(nc, nr, 1), dim3(256), 0, s, N, K, alpha, A, lda, beta, C, ldc);
+    return hipGetLastError();
+  }
   const int nt = (N + BN - 1) / BN;
   if (nt > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_gemm<double, false, true, true>), dim3(nt, nt, 1), dim3(256), 0, s, N, N, K, alpha, A, lda,

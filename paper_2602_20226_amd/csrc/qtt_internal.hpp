@@ -14,9 +14,10 @@ namespace qtt {
 hipError_t gemm_f64(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
                     const double* A, long lda, long sA, const double* B, long ldb, long sB,
                     double beta, double* C, long ldc, long sC, int batch);
-// C = alpha A A^T + beta C on the tiles of C (N x N) on or below the 64 x 64
-// tile diagonal only (A: N x K, row-major); the tiles above it are not
-// touched.  For symmetric updates whose upper triangle is never read.
+// C = alpha A A^T + beta C on the tiles of C (N x N) that hold part of its
+// lower triangle (32 x 64 tiles for K <= 64, else 64 x 64; A: N x K,
+// row-major); the tiles wholly above the diagonal are not touched.  For
+// symmetric updates whose upper triangle is never read.
 hipError_t gemm_f64_lower_nt(hipStream_t s, int N, int K, double alpha, const double* A, long lda, double beta,
                              double* C, long ldc);
 hipError_t gemm_f32(hipStream_t s, bool ta, bool tb, int M, int N, int K, float alpha,
