@@ -402,7 +402,7 @@ KERNEL_CLASSES = {
     "block_vty": ("mfma", 78600.0, "GFLOP/s", "k_vty", "qr.hip"),
     "block_upd": ("mfma", 78600.0, "GFLOP/s", "k_vupd", "qr.hip"),
     "chol_block": ("alu", 78600.0, "GFLOP/s", "k_potrf_inv", "solve.hip"),
-    "chol_update": ("mfma", 78600.0, "GFLOP/s", "k_gemm", "solve.hip"),
+    "chol_update": ("mfma", 78600.0, "GFLOP/s", "k_syrk_k64", "gemm.hip"),
     "chol_solve": ("hbm", 8000.0, "GB/s", "k_chol_bwd", "solve.hip"),
 }
 ROUNDING_CLASSES = ("jacobi", "qr_panel", "apply_panel", "block_vty", "block_upd")
